@@ -1,0 +1,190 @@
+"""Benchmark: stereo frames/s of the bricked multiresolution ray caster.
+
+Workload (the bricked stereo configuration): a 2048^3 uint16 volume of 400
+branching Gaussian tubes over Poisson(200) background, bricked 64^3 with a
+one-voxel apron, 6 LOD levels, all 37,449 bricks resident in HBM; a stereo
+pair of 1440x1600 per eye (64 mm inter-pupillary distance with the volume's
+longest edge = 1 m, head 1.25 m from the centre), step 0.5 voxel of the
+selected level, screen-space LOD at 1 pixel, early termination at 0.99,
+empty-brick skipping. Inputs are synthetic and seeded.
+
+One step = one sg_render_views call covering both eyes (LOD cut map and ray
+casting for every pixel), with the volume already resident in HBM. The
+pyramid build, apron fill and transfer-function refresh are one-time per
+volume / per transfer function and are timed separately (``setup_ms``).
+
+Prints one JSON line. ``roofline`` covers the ray-casting kernel, timed
+with HIP events around its launches; ``cpu_baseline`` is the FP64 oracle on
+a random pixel subset of the same frame, on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s and stereo frames/s, plain vs learned-upsampler path at PSNR≥40 dB"
+HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
+FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector (packed FMA)
+FLOP_PER_SAMPLE = 56         # algorithmic FP32 operations of one single-channel sample
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_views():
+    import gen
+    c = np.array([1024.0, 1024.0, 1024.0])
+    head = c + 2560.0 * gen.unit((1.0, 0.7, 0.4))
+    ipd = 131.072
+    t = math.tan(math.radians(50.0))
+    return gen.stereo(head, c, ipd, 1440, 1600, t, 0.9 * t)
+
+
+PARAMS = {"step": 0.5, "ert": 0.99, "tau": 1.0, "lod": 1, "skip_empty": 1, "bias": 0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (multi-GPU sort-last compositing is "
+              "a design, not an implementation); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    from gen.large import TubeVolume, upload_generated
+    from paper_1804_08197_amd import sg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
+    want_cpu = args.cpu_seconds > 0
+
+    t0 = time.time()
+    tv = TubeVolume().to_device()
+    log("geometry: %d segments in %.1fs" % (tv.n_segments, time.time() - t0))
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    host = np.empty(dims[::-1], dtype=np.uint16) if want_cpu else None
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    upload_generated(h, tv, B, host_out=host, slab_bricks=2, build_lod=False)
+    ev[1].record()
+    sg.sg_build_lod(h, 0, 0)
+    ev[2].record()
+    tf = gen.tf_hot()
+    sg.sg_set_transfer_function(h, 0, tf, *gen.TUBE_DOMAIN)
+    sg.sg_volume_commit(h)
+    ev[3].record()
+    torch.cuda.synchronize()
+    setup = {"generate_upload_ms": ev[0].elapsed_time(ev[1]),
+             "build_lod_ms": ev[1].elapsed_time(ev[2]),
+             "commit_apron_range_empty_ms": ev[2].elapsed_time(ev[3])}
+    log("setup: %s" % json.dumps({k: round(v, 1) for k, v in setup.items()}))
+
+    views = workload_views()
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    npix = sum(v["width"] * v["height"] for v in views)
+
+    # counting pass (untimed): samples and distinct 4^3 micro-blocks read
+    stats = sg.sg_render_views_stats(h, views, PARAMS, outs)
+    samples = stats["total_samples"]
+    mb = stats["microblocks"]
+    log("samples/frame %d, microblocks %d" % (samples, mb))
+
+    for _ in range(args.warmup):
+        sg.sg_render_views(h, views, PARAMS, outs)
+    torch.cuda.synchronize()
+    sg.sg_set_kernel_timing(h, True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        sg.sg_render_views(h, views, PARAMS, outs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+    sg.sg_set_kernel_timing(h, False)
+    assert n_k == args.steps
+    ms_step = wall * 1e3 / args.steps
+    fps = args.steps / wall
+    ray_avg_s = ray_ms / n_k * 1e-3
+    log("%.3f ms/step (wall), raycast kernel %.3f ms, cutmap %.4f ms" % (
+        ms_step, ray_ms / n_k, cut_ms / n_k))
+
+    bytes_alg = mb * 64 * 2 + npix * 16
+    flops_alg = samples * FLOP_PER_SAMPLE
+    hbm = {"bound": "hbm", "achieved": bytes_alg / ray_avg_s / 1e9, "peak": HBM_PEAK / 1e9,
+           "unit": "GB/s", "traffic": None}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    alu = {"bound": "alu", "achieved": flops_alg / ray_avg_s / 1e12, "peak": FP32_PEAK / 1e12,
+           "unit": "TFLOP/s", "traffic": None}
+    alu["frac"] = alu["achieved"] / alu["peak"]
+    roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+
+    out = {"metric": METRIC, "value": fps, "unit": "stereo frames/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600",
+                      "volume": "2048^3 uint16, 400 branching Gaussian tubes + Poisson(200)",
+                      "brick": B, "levels": levels, "views": 2, "width": 1440, "height": 1600,
+                      "step_voxels": 0.5, "ert": 0.99, "lod_tau_px": 1.0, "skip_empty": True},
+           "samples_per_frame": samples, "samples_per_s": samples * fps,
+           "raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
+           "microblocks_per_frame": mb, "roofline": roof, "roofline_other": other,
+           "setup_ms": setup}
+
+    if want_cpu:
+        out["cpu_baseline"] = cpu_baseline(host, tf, views, samples, npix, args.cpu_seconds)
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
+    """The FP64 oracle on a seeded random subset of the frame's pixels."""
+    import gen
+    import oracle
+    t0 = time.time()
+    sc = oracle.Scene([host], gen.TUBES_BRICK, gen.TUBES_LEVELS,
+                      [np.asarray(tf, np.float32).astype(np.float64)], [gen.TUBE_DOMAIN])
+    cuts = [sc.cut(v, PARAMS) for v in views]
+    emps = [sc.empty(c) for c in cuts]
+    log("oracle setup %.1fs (pyramid, cuts %s)" % (time.time() - t0, [len(c) for c in cuts]))
+    rng = np.random.default_rng(2024)
+    threads = oracle.max_threads()
+    done_pix, done_samp, spent, n = 0, 0, 0.0, 64
+    while spent < seconds:
+        for i, v in enumerate(views):
+            pix = np.stack([rng.integers(0, v["width"], n), rng.integers(0, v["height"], n)], 1)
+            t = time.perf_counter()
+            r = sc.render(v, PARAMS, pixels=pix, cut=cuts[i], empty=emps[i], threads=threads)
+            spent += time.perf_counter() - t
+            done_pix += n
+            done_samp += r["total_samples"]
+        n = min(n * 2, 8192)
+    frame_s = spent / done_pix * npix
+    return {"value": 1.0 / frame_s, "unit": "stereo frames/s", "cores": threads,
+            "kind": "oracle", "samples_per_s": done_samp / spent,
+            "sample": "%d random pixels of both eyes (%.2f%% of the frame), %.1fs of CPU wall "
+                      "time, extrapolated by pixel count" % (done_pix, 100.0 * done_pix / npix,
+                                                             spent)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * sg.h -- C ABI of the MI355X (gfx950) stereo volume ray caster.
+ *
+ * Direct volume ray casting through a bricked, multiresolution (octree LOD)
+ * volume, following syGlass (arXiv 1804.08197): Sec 5.1 (ray casting with the
+ * emission-absorption model and early ray termination), Sec 5.2 (octree
+ * blocks in a multi-resolution pyramid, top-down LOD selection, front-to-back
+ * block order), Sec 5.3 (one render per eye of a head-mounted display),
+ * Sec 4.1/4.2 (volume chunks uploaded to a GPU-resident cache), Sec 5.6
+ * (pre-multiplied alpha output) and Sec 8 (transfer functions, multichannel).
+ *
+ * Conventions shared by every call
+ *  - World space is level-0 voxel units: voxel (i, j, k) covers
+ *    [i, i+1) x [j, j+1) x [k, k+1) with its value at the centre; the volume
+ *    box is [0, dims]. Voxel arrays are x fastest.
+ *  - Every function returns an sg_status and never throws. Argument and state
+ *    errors are reported synchronously; asynchronous device errors surface on
+ *    a later call or on stream synchronisation. sg_last_error() gives a
+ *    thread-local description of the last failure.
+ *  - hip_stream is a hipStream_t (NULL = the default stream). Device work is
+ *    enqueued on it in order; device pointers passed in are read or written
+ *    in that stream order.
+ *  - Ownership: the library owns everything it allocates for a volume (brick
+ *    pool, page table, transfer functions, per-view scratch); the caller owns
+ *    its inputs and output buffers. A volume is not thread-safe; distinct
+ *    volumes are independent.
+ *  - There is no CPU fallback: without a usable gfx950 device the calls that
+ *    need one return SG_ERR_DEVICE.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_ABI_VERSION 1
+
+typedef enum {
+  SG_OK = 0,
+  SG_ERR_INVALID_ARG = -1,   /* NULL, out of range, NaN or inconsistent input */
+  SG_ERR_OUT_OF_MEMORY = -2, /* device allocation failed (e.g. pool > HBM)   */
+  SG_ERR_DEVICE = -3,        /* no device, or a HIP runtime call failed        */
+  SG_ERR_STATE = -4,         /* call not valid now (e.g. no transfer function) */
+  SG_ERR_UNSUPPORTED = -5    /* valid request this build does not implement   */
+} sg_status;
+
+typedef enum { SG_U8 = 1, SG_U16 = 2 } sg_dtype;
+
+/* sg_render_params.flags */
+enum {
+  SG_LOD = 1u << 0,        /* screen-space LOD cut (Sec 5.2); without it every
+                              node is rendered at level lod_bias             */
+  SG_SKIP_EMPTY = 1u << 1  /* skip nodes whose opacity is zero everywhere     */
+};
+
+typedef struct sg_volume sg_volume; /* opaque */
+
+/* Volume geometry. The brick pool holds, for every channel and timepoint,
+ * every node of the pyramid: level L has dims ceil(dims / 2^L) voxels,
+ * split into bricks of brick^3 core voxels stored with a one-voxel apron
+ * ((brick+2)^3 voxels per slot). */
+typedef struct {
+  int32_t dims[3];    /* level-0 voxels per axis, >= 1                        */
+  int32_t channels;   /* 1..4                                                 */
+  int32_t timepoints; /* >= 1                                                 */
+  int32_t dtype;      /* sg_dtype                                             */
+  int32_t brick;      /* core edge: power of two in [2, 256]                  */
+  int32_t levels;     /* pyramid levels, 1..16 (1 = no pyramid)               */
+  int32_t device;     /* HIP device ordinal                                   */
+} sg_volume_desc;
+
+/* One eye / camera (Sec 5.1: one ray per pixel; Sec 5.3: one view per eye).
+ * The camera looks down its own -z axis. cam_to_world is row-major 4x4 with
+ * the eye position in its last column (m[3], m[7], m[11]) and a rotation in
+ * its upper-left 3x3. The image plane at distance 1 spans
+ * [tan_left, tan_right] x [tan_bottom, tan_top] (asymmetric frusta allowed);
+ * pixel (x, y) has its centre at tangent
+ *   (tan_left + (x + 0.5) / width * (tan_right - tan_left),
+ *    tan_top  - (y + 0.5) / height * (tan_top - tan_bottom)),
+ * row 0 at the top. */
+typedef struct {
+  double cam_to_world[16];
+  double tan_left, tan_right, tan_bottom, tan_top;
+  int32_t width, height; /* >= 1 */
+} sg_view;
+
+typedef struct {
+  double step_voxels;   /* sample spacing in voxels of the sampled level (0.5),
+                           in [1/64, 64]                                      */
+  double ert_alpha;     /* stop a ray once its alpha >= this (0.99); > 1 = off */
+  double lod_tau_px;    /* LOD: largest voxel footprint in pixels (1.0)        */
+  double background[4]; /* premultiplied RGBA composited under the volume     */
+  double depth_alpha;   /* depth output: first sample with alpha >= this (0.5) */
+  int32_t lod_bias;     /* finest level used (0 = full resolution)            */
+  int32_t timepoint;    /* 0 .. timepoints-1                                  */
+  uint32_t flags;       /* SG_LOD | SG_SKIP_EMPTY                             */
+  int32_t reserved;     /* must be 0                                          */
+} sg_render_params;
+
+/* Optional instrumentation of one render (sg_render_views_stats). */
+typedef struct {
+  int32_t *const *samples; /* in: per view a device int32 [height*width]
+                              buffer for per-pixel sample counts, or NULL    */
+  uint64_t total_samples;  /* out: samples evaluated over all views          */
+  uint64_t microblocks;    /* out: distinct 4^3 voxel blocks (per channel and
+                              level) read by the trilinear stencils          */
+} sg_render_stats;
+
+/* Create a volume on desc->device: allocates the brick pool for every
+ * channel, timepoint and node, the page table (node -> pool slot) and the
+ * per-node value ranges. The pool starts zeroed.
+ * Errors: SG_ERR_INVALID_ARG (bad desc, out NULL), SG_ERR_OUT_OF_MEMORY,
+ * SG_ERR_DEVICE. On success *out owns all of it until sg_volume_destroy. */
+sg_status sg_volume_create(const sg_volume_desc *desc, sg_volume **out);
+
+/* Release every device allocation of vol (after synchronising its device). */
+sg_status sg_volume_destroy(sg_volume *vol);
+
+/* Upload n brick cores of one (channel, timepoint, level) into the pool
+ * (Sec 4.1: decompressed chunks uploaded to the GPU; Sec 4.2: GPU cache).
+ *   coords : host int32 [n][3] brick indices (bx, by, bz) at that level
+ *   src    : n consecutive cores of brick^3 voxels (x fastest) of the
+ *            volume's dtype; a host pointer (copied before the call returns)
+ *            or, if src_on_device, a device pointer read in stream order.
+ * Core voxels outside the level's extent (partial bricks at the far faces)
+ * are ignored: commit replaces them by the clamped edge values.
+ * Marks the channel/timepoint for commit (apron fill, value ranges). */
+sg_status sg_upload_bricks(sg_volume *vol, int32_t channel, int32_t timepoint,
+                           int32_t level, int32_t n, const int32_t *coords,
+                           const void *src, int32_t src_on_device,
+                           void *hip_stream);
+
+/* Build levels 1..levels-1 of one (channel, timepoint) from its level-0
+ * cores on the device (Sec 5.2 multi-resolution pyramid): each coarse voxel
+ * is (sum of its 2x2x2 children + 4) >> 3, child indices clamped to the
+ * finer level. Marks the channel/timepoint for commit. */
+sg_status sg_build_lod(sg_volume *vol, int32_t channel, int32_t timepoint,
+                       void *hip_stream);
+
+/* Finish pending uploads/builds on the device: fill every brick's apron
+ * (and out-of-extent core voxels) with clamped neighbour values, recompute
+ * per-brick min/max, and recompute empty-node flags. sg_render_views calls
+ * this itself when something is pending. */
+sg_status sg_volume_commit(sg_volume *vol, void *hip_stream);
+
+/* Set the transfer function of a channel (Sec 5.1 tau and T; Sec 8):
+ * rgba is a host float [n_entries][4] table, copied before return: r, g, b
+ * are the emitted colour, a the extinction per level-0 voxel length. Entry
+ * k sits at raw value domain_lo + k/(n_entries-1) * (domain_hi - domain_lo);
+ * lookups interpolate linearly and clamp at both ends.
+ * n_entries in [2, 1024], all entries finite, extinction >= 0,
+ * domain_hi > domain_lo. Every channel of a volume uses the same n_entries.
+ * The device copy and the empty flags are refreshed in stream order by the
+ * next commit or render. */
+sg_status sg_set_transfer_function(sg_volume *vol, int32_t channel,
+                                   const float *rgba, int32_t n_entries,
+                                   double domain_lo, double domain_hi);
+
+/* Render n_views views in one launch sequence on hip_stream (Sec 5.1-5.3):
+ * per view an LOD cut (Sec 5.2), then per pixel a ray through the cut's
+ * nodes front to back, trilinear samples every step_voxels * 2^L level-0
+ * units, transfer-function lookup, emission-absorption compositing with
+ * early termination, background composited underneath.
+ *   views    : host array [n_views]
+ *   out_rgba : host array [n_views] of device float pointers, each
+ *              [height][width][4] premultiplied RGBA, row 0 = top
+ *   out_depth: NULL, or host array [n_views] of device float pointers (or
+ *              NULL entries), each [height][width]: distance along the ray
+ *              of the first sample whose alpha >= depth_alpha, +inf if none
+ * Asynchronous: returns after enqueueing. Requires a transfer function for
+ * every channel (SG_ERR_STATE otherwise). n_views in [1, 4096]. */
+sg_status sg_render_views(sg_volume *vol, int32_t n_views, const sg_view *views,
+                          const sg_render_params *params, float *const *out_rgba,
+                          float *const *out_depth, void *hip_stream);
+
+/* Same render with instrumentation (per-pixel sample counts, total samples,
+ * distinct micro-blocks read). Synchronises hip_stream before returning so
+ * that the host counters are valid. Slower; for tests and measurement. */
+sg_status sg_render_views_stats(sg_volume *vol, int32_t n_views,
+                                const sg_view *views,
+                                const sg_render_params *params,
+                                float *const *out_rgba, float *const *out_depth,
+                                sg_render_stats *stats, void *hip_stream);
+
+/* The LOD cut of one view (Sec 5.2) as computed on the device, for checking:
+ * nodes receives the cut's node identifiers sorted ascending, each
+ *   (level << 60) | (bx << 40) | (by << 20) | bz,
+ * and empty[i] (if not NULL) the empty flag of nodes[i] at params->timepoint.
+ * *n_nodes is the capacity on input and the cut size on output; if the cut
+ * is larger nothing is written and SG_ERR_INVALID_ARG is returned with the
+ * needed size in *n_nodes. Host buffers; synchronises hip_stream. */
+sg_status sg_get_lod_cut(sg_volume *vol, const sg_view *view,
+                         const sg_render_params *params, uint64_t *nodes,
+                         int32_t *n_nodes, uint8_t *empty, void *hip_stream);
+
+/* Instrumentation: while enabled, every render of vol records HIP events
+ * on its stream around the cut-map kernel and around the ray-casting kernel.
+ * sg_get_kernel_timing synchronises those events and returns the number of
+ * renders recorded and the summed kernel milliseconds (cut map, ray cast)
+ * since the last query or enable, then clears the record. */
+sg_status sg_set_kernel_timing(sg_volume *vol, int32_t enable);
+sg_status sg_get_kernel_timing(sg_volume *vol, int32_t *renders,
+                               double *cutmap_ms, double *raycast_ms);
+
+/* Bytes of device memory the volume holds (pool, tables, scratch). */
+sg_status sg_volume_memory(const sg_volume *vol, uint64_t *bytes);
+
+const char *sg_status_string(sg_status s); /* static string, never NULL */
+const char *sg_last_error(void);           /* thread-local, never NULL  */
+int32_t sg_abi_version(void);              /* SG_ABI_VERSION            */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

@@ -1,0 +1,172 @@
+// lod.hip -- per-view LOD cut and cut map (Sec 5.2).
+//
+// The cut is the set of nodes that suit the view while every ancestor does
+// not (the top-down traversal of Sec 5.2). A node (L, b) suits when its
+// voxel edge s = 2^L, seen from the eye at the distance d of the node's
+// nearest point, subtends no more than tau pixels of angular size theta:
+//   s*s <= K * d*d,  K = (tau * theta)^2,  theta = (tan_top - tan_bottom) / H,
+// and every node at the finest allowed level (lod_bias) suits. Instead of a
+// recursive traversal, one thread per level-0 brick cell walks its ancestor
+// chain from the top level down and records the first node that suits: that
+// node is in the cut (its ancestors were all rejected) and the map
+// cell -> node covers the volume exactly once. The comparison is done in
+// IEEE double with no contraction (this file is built with
+// -ffp-contract=off), so it reproduces the CPU reference bit for bit.
+#include <algorithm>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+struct CutGeom {
+  int32_t dims[3];
+  int32_t grid[kMaxLevels][3];
+  int64_t node_off[kMaxLevels];
+  int32_t B;
+  int32_t top;
+  int32_t bias;
+  int32_t lod;
+  int64_t cells;  // level-0 bricks
+};
+
+__device__ __forceinline__ bool node_suits(const CutGeom& g, const double e[3],
+                                           double K, int L, int bx, int by,
+                                           int bz) {
+  int32_t b[3] = {bx, by, bz};
+  double dl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int64_t w = (int64_t)g.B << L;
+    int64_t lo = w * b[a];
+    int64_t hi = w * (b[a] + 1);
+    if (hi > g.dims[a]) hi = g.dims[a];
+    double u = (double)lo - e[a];
+    double v = e[a] - (double)hi;
+    double m = u > v ? u : v;
+    dl[a] = m > 0.0 ? m : 0.0;
+  }
+  double d2 = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
+  double s = (double)((int64_t)1 << L);
+  return (s * s) <= (K * d2);
+}
+
+__global__ void cutmap_kernel(CutGeom g, const ViewDev* views, int n_views,
+                              int32_t* cutmap) {
+  const int64_t total = (int64_t)n_views * g.cells;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t v = i / g.cells, cell = i - v * g.cells;
+    const ViewDev& V = views[v];
+    int32_t cx = (int32_t)(cell % g.grid[0][0]);
+    int32_t cy = (int32_t)((cell / g.grid[0][0]) % g.grid[0][1]);
+    int32_t cz = (int32_t)(cell / ((int64_t)g.grid[0][0] * g.grid[0][1]));
+    double e[3] = {V.e[0], V.e[1], V.e[2]};
+    int L = g.lod ? g.top : g.bias;
+    for (; L > g.bias; --L)
+      if (node_suits(g, e, V.K, L, cx >> L, cy >> L, cz >> L)) break;
+    int32_t bx = cx >> L, by = cy >> L, bz = cz >> L;
+    cutmap[V.cut_off + cell] =
+        (int32_t)(g.node_off[L] + ((int64_t)bz * g.grid[L][1] + by) * g.grid[L][0] + bx);
+  }
+}
+
+__global__ void mark_kernel(const int32_t* cutmap, int64_t cells, uint8_t* flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cells;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[cutmap[i]] = 1;
+}
+
+CutGeom cut_geom(const Volume* v, int bias, bool lod) {
+  CutGeom g{};
+  for (int a = 0; a < 3; ++a) g.dims[a] = v->d.dims[a];
+  for (int L = 0; L < v->L; ++L) {
+    for (int a = 0; a < 3; ++a) g.grid[L][a] = v->grid[L][a];
+    g.node_off[L] = v->node_off[L];
+  }
+  g.B = v->B;
+  g.top = v->L - 1;
+  g.bias = bias;
+  g.lod = lod ? 1 : 0;
+  g.cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
+  return g;
+}
+
+}  // namespace
+
+sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
+                        bool lod, hipStream_t s) {
+  CutGeom g = cut_geom(v, bias, lod);
+  int64_t total = (int64_t)n_views * g.cells;
+  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(cutmap_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256),
+                     0, s, g, dviews, n_views, v->cutmap);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+}  // namespace sg
+
+extern "C" sg_status sg_get_lod_cut(sg_volume* vol, const sg_view* view,
+                                    const sg_render_params* params, uint64_t* nodes,
+                                    int32_t* n_nodes, uint8_t* empty, void* hip_stream) {
+  using namespace sg;
+  if (!vol || !view || !params || !n_nodes || (*n_nodes > 0 && !nodes) || *n_nodes < 0)
+    return fail(SG_ERR_INVALID_ARG, "sg_get_lod_cut: NULL argument or negative capacity");
+  Volume* v = &vol->v;
+  DeviceGuard guard(v->d.device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "sg_get_lod_cut: cannot select device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int tiles = 0;
+  sg_status st = commit(v, s);
+  if (st != SG_OK) return st;
+  st = prepare_views(v, 1, view, params, nullptr, nullptr, nullptr, s, &tiles);
+  if (st != SG_OK) return st;
+  const bool lod = (params->flags & SG_LOD) != 0;
+  st = launch_cutmap(v, reinterpret_cast<const ViewDev*>(v->view_dev), 1, params->lod_bias,
+                     lod, s);
+  if (st != SG_OK) return st;
+  const int64_t cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
+  uint8_t* dflags = nullptr;
+  SG_HIP(hipMallocAsync((void**)&dflags, (size_t)v->nodes, s));
+  SG_HIP(hipMemsetAsync(dflags, 0, (size_t)v->nodes, s));
+  int64_t blocks = std::min<int64_t>((cells + 255) / 256, 65536);
+  hipLaunchKernelGGL(mark_kernel, dim3((unsigned)blocks), dim3(256), 0, s, v->cutmap, cells,
+                     dflags);
+  SG_HIP(hipGetLastError());
+  std::vector<uint8_t> flags(v->nodes), emp(v->nodes, 0);
+  SG_HIP(hipMemcpyAsync(flags.data(), dflags, (size_t)v->nodes, hipMemcpyDeviceToHost, s));
+  const bool have_empty = !v->empty_dirty && !v->tf_dirty;
+  if (empty && have_empty)
+    SG_HIP(hipMemcpyAsync(emp.data(), v->empty + (int64_t)params->timepoint * v->nodes,
+                          (size_t)v->nodes, hipMemcpyDeviceToHost, s));
+  SG_HIP(hipStreamSynchronize(s));
+  SG_HIP(hipFreeAsync(dflags, s));
+  if (empty && !have_empty)
+    return fail(SG_ERR_STATE, "sg_get_lod_cut: empty flags need a transfer function for "
+                              "every channel");
+  std::vector<std::pair<uint64_t, uint8_t>> out;
+  for (int L = 0; L < v->L; ++L)
+    for (int64_t z = 0; z < v->grid[L][2]; ++z)
+      for (int64_t y = 0; y < v->grid[L][1]; ++y)
+        for (int64_t x = 0; x < v->grid[L][0]; ++x) {
+          int64_t n = v->node_off[L] + (z * v->grid[L][1] + y) * v->grid[L][0] + x;
+          if (!flags[n]) continue;
+          uint64_t id = ((uint64_t)L << 60) | ((uint64_t)x << 40) | ((uint64_t)y << 20) |
+                        (uint64_t)z;
+          out.emplace_back(id, emp[n]);
+        }
+  std::sort(out.begin(), out.end());
+  if ((int64_t)out.size() > *n_nodes) {
+    *n_nodes = (int32_t)out.size();
+    return fail(SG_ERR_INVALID_ARG, "sg_get_lod_cut: capacity too small");
+  }
+  *n_nodes = (int32_t)out.size();
+  for (size_t i = 0; i < out.size(); ++i) {
+    nodes[i] = out[i].first;
+    if (empty) empty[i] = out[i].second;
+  }
+  return SG_OK;
+}

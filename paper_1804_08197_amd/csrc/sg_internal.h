@@ -1,0 +1,165 @@
+// sg_internal.h -- shared definitions of the gfx950 library behind sg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sg.h"
+
+namespace sg {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxChannels = 4;
+constexpr int kMaxTfEntries = 1024;
+
+// Error plumbing: every entry point funnels through these.
+sg_status fail(sg_status s, const std::string& msg);
+sg_status hip_fail(hipError_t e, const char* what);
+#define SG_HIP(call)                                             \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) return ::sg::hip_fail(e_, #call);      \
+  } while (0)
+
+// Node record, one per pyramid node (level L, brick b): used by the ray
+// caster to turn a cut-map entry into a box and a level.
+struct NodeInfo {
+  int32_t level;
+  int32_t b[3];
+};
+
+struct Volume {
+  sg_volume_desc d{};
+  int bpv = 0;       // bytes per voxel
+  int B = 0;         // brick core edge
+  int logB = 0;
+  int S = 0;         // stored edge B + 2
+  int L = 0;         // levels
+  int32_t ldims[kMaxLevels][3]{};
+  int32_t grid[kMaxLevels][3]{};
+  int64_t node_off[kMaxLevels + 1]{};
+  int64_t nodes = 0;          // nodes per (channel, timepoint)
+  int64_t slot_bytes = 0;     // bytes per pool slot (padded)
+  int64_t slots = 0;          // pool slots
+  uint8_t* pool = nullptr;    // [slots][S^3] voxels
+  int32_t* page = nullptr;    // [T][C][nodes] -> slot
+  uint32_t* range = nullptr;  // [T][C][nodes][2] min, max of stored voxels
+  uint8_t* empty = nullptr;   // [T][nodes] 1 if every channel is transparent
+  NodeInfo* info = nullptr;   // [nodes]
+  float* tf = nullptr;        // [C][tf_n + 1][4] (last entry repeated)
+  int tf_n = 0;
+  std::vector<float> tf_host[kMaxChannels];
+  double tf_lo[kMaxChannels]{}, tf_hi[kMaxChannels]{};
+  bool tf_set[kMaxChannels]{};
+  bool tf_dirty = true;
+  std::vector<uint8_t> pending;  // [T][C] needs apron + range refresh
+  bool empty_dirty = true;
+  // per-render scratch
+  int32_t* cutmap = nullptr;  // [views][cells0]
+  int64_t cutmap_cap = 0;
+  uint8_t* view_dev = nullptr;
+  int64_t view_cap = 0;
+  uint8_t* stage_host = nullptr;  // pinned staging for small uploads
+  int64_t stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  uint32_t* mb_bits = nullptr;  // micro-block bitmap (stats only)
+  int64_t mb_words = 0;
+  uint64_t* counters = nullptr;  // device counters (stats only)
+  uint64_t bytes = 0;
+  // kernel timing (instrumentation)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<hipEvent_t> ev_rec;  // triples: before cut map, before / after ray cast
+};
+
+// Record an event from the volume's pool on `s` (timing mode only).
+sg_status timing_mark(Volume* v, hipStream_t s);
+
+// Device-side current-device guard.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+// Stage `bytes` of host data into device memory on `stream` through the
+// volume's pinned buffer (waits for the previous staged copy first).
+sg_status stage_to_device(Volume* v, const void* host, int64_t bytes,
+                          void* dev, hipStream_t stream);
+
+// Kernel launchers (one .hip file each).
+sg_status launch_upload(Volume* v, int c, int t, int level, int n,
+                        const int32_t* dcoords, const void* dsrc,
+                        hipStream_t s);
+sg_status launch_downsample(Volume* v, int c, int t, int level_dst,
+                            hipStream_t s);
+sg_status launch_apron(Volume* v, int c, int t, hipStream_t s);
+sg_status launch_range(Volume* v, int c, int t, hipStream_t s);
+sg_status launch_empty(Volume* v, hipStream_t s);
+sg_status commit(Volume* v, hipStream_t s);
+
+// Per-view constants consumed by the LOD and ray-casting kernels.
+struct ViewDev {
+  double e[3];
+  double R[9];  // row-major rotation, camera -> world
+  double tl, tr, tb, tt;
+  double K;     // (tau * theta)^2
+  int32_t W, H;
+  int32_t tiles_x;     // 16x16 pixel tiles per row
+  int32_t tile_begin;  // first workgroup (tile) of this view
+  int64_t cut_off;     // offset of this view's cut map
+  float* rgba;
+  float* depth;
+  int32_t* nsamp;
+};
+
+sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
+                        int bias, bool lod, hipStream_t s);
+// rgba may be NULL (cut queries); the render path checks it itself.
+sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
+                        const sg_render_params* p, float* const* rgba,
+                        float* const* depth, int32_t* const* nsamp,
+                        hipStream_t s, int* total_tiles);
+
+struct RenderArgs {
+  const uint8_t* pool;
+  int64_t slot_bytes;
+  const int32_t* page;   // at timepoint: [C][nodes]
+  const uint8_t* empty;  // at timepoint: [nodes]
+  const NodeInfo* info;
+  const float* tf;
+  const int32_t* cutmap;
+  const ViewDev* views;
+  uint32_t* mb_bits;
+  uint64_t* counters;
+  int64_t nodes;
+  int64_t level_mb_off[kMaxChannels * kMaxLevels];  // bit offsets (stats)
+  int32_t ldims[kMaxLevels][3];
+  float tf_scale[kMaxChannels];
+  float tf_bias[kMaxChannels];
+  float bg[4];
+  int32_t dims[3];
+  int32_t grid0[3];
+  int32_t n_views;
+  int32_t total_tiles;
+  int32_t tf_n;
+  int32_t B, S;
+  int32_t skip_empty;
+  double step;
+  float ert;
+  float depth_alpha;
+};
+
+sg_status launch_raycast(Volume* v, const RenderArgs& a, bool stats,
+                         hipStream_t s);
+
+}  // namespace sg
+
+struct sg_volume {
+  sg::Volume v;
+};

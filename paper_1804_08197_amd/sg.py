@@ -1,0 +1,286 @@
+"""ctypes binding of ``include/sg.h`` (argument marshalling only).
+
+Every function has the name of the C entry point it calls. Device buffers
+are passed as torch tensors (``data_ptr()``) and streams as torch streams or
+raw ``hipStream_t`` integers; the work itself runs in ``libsg.so``. There is
+no fallback: if the library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsg.so")
+
+SG_OK = 0
+SG_ERR_INVALID_ARG = -1
+SG_ERR_OUT_OF_MEMORY = -2
+SG_ERR_DEVICE = -3
+SG_ERR_STATE = -4
+SG_ERR_UNSUPPORTED = -5
+SG_U8, SG_U16 = 1, 2
+SG_LOD, SG_SKIP_EMPTY = 1, 2
+SG_ABI_VERSION = 1
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s: %s (%s)" % (where, detail, _status_name(status)))
+        self.status = status
+
+
+class sg_volume_desc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("channels", C.c_int32), ("timepoints", C.c_int32),
+                ("dtype", C.c_int32), ("brick", C.c_int32), ("levels", C.c_int32),
+                ("device", C.c_int32)]
+
+
+class sg_view(C.Structure):
+    _fields_ = [("cam_to_world", C.c_double * 16), ("tan_left", C.c_double),
+                ("tan_right", C.c_double), ("tan_bottom", C.c_double), ("tan_top", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class sg_render_params(C.Structure):
+    _fields_ = [("step_voxels", C.c_double), ("ert_alpha", C.c_double),
+                ("lod_tau_px", C.c_double), ("background", C.c_double * 4),
+                ("depth_alpha", C.c_double), ("lod_bias", C.c_int32), ("timepoint", C.c_int32),
+                ("flags", C.c_uint32), ("reserved", C.c_int32)]
+
+
+class sg_render_stats(C.Structure):
+    _fields_ = [("samples", C.POINTER(C.c_void_p)), ("total_samples", C.c_uint64),
+                ("microblocks", C.c_uint64)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libsg.so is not built (run __graft_entry__.build()); there is no "
+                      "fallback implementation")
+_lib = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+_lib.sg_volume_create.argtypes = [C.POINTER(sg_volume_desc), C.POINTER(_P)]
+_lib.sg_volume_destroy.argtypes = [_P]
+_lib.sg_upload_bricks.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_int32), _P, C.c_int32, _P]
+_lib.sg_build_lod.argtypes = [_P, C.c_int32, C.c_int32, _P]
+_lib.sg_volume_commit.argtypes = [_P, _P]
+_lib.sg_set_transfer_function.argtypes = [_P, C.c_int32, C.POINTER(C.c_float), C.c_int32,
+                                          C.c_double, C.c_double]
+_lib.sg_render_views.argtypes = [_P, C.c_int32, C.POINTER(sg_view),
+                                 C.POINTER(sg_render_params), C.POINTER(_P), C.POINTER(_P), _P]
+_lib.sg_render_views_stats.argtypes = [_P, C.c_int32, C.POINTER(sg_view),
+                                       C.POINTER(sg_render_params), C.POINTER(_P),
+                                       C.POINTER(_P), C.POINTER(sg_render_stats), _P]
+_lib.sg_get_lod_cut.argtypes = [_P, C.POINTER(sg_view), C.POINTER(sg_render_params),
+                                C.POINTER(C.c_uint64), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_uint8), _P]
+_lib.sg_volume_memory.argtypes = [_P, C.POINTER(C.c_uint64)]
+_lib.sg_set_kernel_timing.argtypes = [_P, C.c_int32]
+_lib.sg_get_kernel_timing.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+_lib.sg_status_string.argtypes = [C.c_int]
+_lib.sg_status_string.restype = C.c_char_p
+_lib.sg_last_error.restype = C.c_char_p
+_lib.sg_abi_version.restype = C.c_int32
+for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_build_lod",
+           "sg_volume_commit", "sg_set_transfer_function", "sg_render_views",
+           "sg_render_views_stats", "sg_get_lod_cut", "sg_volume_memory",
+           "sg_set_kernel_timing", "sg_get_kernel_timing"):
+    getattr(_lib, _f).restype = C.c_int
+
+
+def lib():
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    return _lib.sg_status_string(int(s)).decode()
+
+
+def _check(status: int, where: str):
+    if status != SG_OK:
+        raise SgError(status, where, _lib.sg_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array / int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return C.c_void_p(x)
+    if isinstance(x, np.ndarray):
+        return C.c_void_p(x.ctypes.data)
+    return C.c_void_p(x.data_ptr())
+
+
+def make_view(v) -> sg_view:
+    if isinstance(v, sg_view):
+        return v
+    o = sg_view()
+    m = np.asarray(v["cam_to_world"], dtype=np.float64).reshape(16)
+    for i in range(16):
+        o.cam_to_world[i] = float(m[i])
+    o.tan_left, o.tan_right = float(v["tan_left"]), float(v["tan_right"])
+    o.tan_bottom, o.tan_top = float(v["tan_bottom"]), float(v["tan_top"])
+    o.width, o.height = int(v["width"]), int(v["height"])
+    return o
+
+
+def make_params(p=None) -> sg_render_params:
+    if isinstance(p, sg_render_params):
+        return p
+    p = dict(p or {})
+    o = sg_render_params()
+    o.step_voxels = float(p.get("step", 0.5))
+    o.ert_alpha = float(p.get("ert", 0.99))
+    o.lod_tau_px = float(p.get("tau", 1.0))
+    bg = p.get("bg", (0.0, 0.0, 0.0, 0.0))
+    for i in range(4):
+        o.background[i] = float(bg[i])
+    o.depth_alpha = float(p.get("depth_alpha", 0.5))
+    o.lod_bias = int(p.get("bias", 0))
+    o.timepoint = int(p.get("timepoint", 0))
+    flags = 0
+    if p.get("lod", 1):
+        flags |= SG_LOD
+    if p.get("skip_empty", 1):
+        flags |= SG_SKIP_EMPTY
+    o.flags = int(p.get("flags", flags))
+    o.reserved = int(p.get("reserved", 0))
+    return o
+
+
+# ------------------------------------------------------------ entry points
+def sg_abi_version() -> int:
+    return int(_lib.sg_abi_version())
+
+
+def sg_status_string(s: int) -> str:
+    return _status_name(s)
+
+
+def sg_last_error() -> str:
+    return _lib.sg_last_error().decode()
+
+
+def sg_volume_create(dims, channels=1, timepoints=1, dtype=SG_U16, brick=64, levels=1,
+                     device=0):
+    d = sg_volume_desc()
+    for i in range(3):
+        d.dims[i] = int(dims[i])
+    d.channels, d.timepoints, d.dtype = int(channels), int(timepoints), int(dtype)
+    d.brick, d.levels, d.device = int(brick), int(levels), int(device)
+    h = C.c_void_p()
+    _check(_lib.sg_volume_create(C.byref(d), C.byref(h)), "sg_volume_create")
+    return h
+
+
+def sg_volume_destroy(vol):
+    _check(_lib.sg_volume_destroy(vol), "sg_volume_destroy")
+
+
+def sg_upload_bricks(vol, channel, timepoint, level, coords, src, src_on_device=None,
+                     stream=None):
+    coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
+    if src_on_device is None:
+        src_on_device = not isinstance(src, np.ndarray) and getattr(src, "is_cuda", False)
+    if isinstance(src, np.ndarray):
+        src = np.ascontiguousarray(src)
+    _check(_lib.sg_upload_bricks(vol, int(channel), int(timepoint), int(level), len(coords),
+                                 coords.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(src),
+                                 int(bool(src_on_device)), _stream(stream)),
+           "sg_upload_bricks")
+
+
+def sg_build_lod(vol, channel, timepoint, stream=None):
+    _check(_lib.sg_build_lod(vol, int(channel), int(timepoint), _stream(stream)), "sg_build_lod")
+
+
+def sg_volume_commit(vol, stream=None):
+    _check(_lib.sg_volume_commit(vol, _stream(stream)), "sg_volume_commit")
+
+
+def sg_set_transfer_function(vol, channel, rgba, domain_lo, domain_hi):
+    t = np.ascontiguousarray(rgba, dtype=np.float32).reshape(-1, 4)
+    _check(_lib.sg_set_transfer_function(vol, int(channel),
+                                         t.ctypes.data_as(C.POINTER(C.c_float)), t.shape[0],
+                                         float(domain_lo), float(domain_hi)),
+           "sg_set_transfer_function")
+
+
+def _views(views):
+    arr = (sg_view * len(views))(*[make_view(v) for v in views])
+    return arr
+
+
+def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
+    n = len(views)
+    varr = _views(views)
+    p = make_params(params)
+    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+    dep = None
+    if out_depth is not None:
+        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    _check(_lib.sg_render_views(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
+           "sg_render_views")
+
+
+def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samples=None,
+                          stream=None):
+    n = len(views)
+    varr = _views(views)
+    p = make_params(params)
+    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+    dep = None
+    if out_depth is not None:
+        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    st = sg_render_stats()
+    if out_samples is not None:
+        smp = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_samples])
+        st.samples = C.cast(smp, C.POINTER(C.c_void_p))
+    _check(_lib.sg_render_views_stats(vol, n, varr, C.byref(p), rgba, dep, C.byref(st),
+                                      _stream(stream)), "sg_render_views_stats")
+    return {"total_samples": int(st.total_samples), "microblocks": int(st.microblocks)}
+
+
+def sg_get_lod_cut(vol, view, params, capacity=1 << 20, stream=None):
+    v = make_view(view)
+    p = make_params(params)
+    nodes = np.zeros(capacity, dtype=np.uint64)
+    empty = np.zeros(capacity, dtype=np.uint8)
+    n = C.c_int32(capacity)
+    _check(_lib.sg_get_lod_cut(vol, C.byref(v), C.byref(p),
+                               nodes.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n),
+                               empty.ctypes.data_as(C.POINTER(C.c_uint8)), _stream(stream)),
+           "sg_get_lod_cut")
+    return nodes[:n.value].copy(), empty[:n.value].astype(bool)
+
+
+def sg_volume_memory(vol) -> int:
+    b = C.c_uint64()
+    _check(_lib.sg_volume_memory(vol, C.byref(b)), "sg_volume_memory")
+    return int(b.value)
+
+
+def sg_set_kernel_timing(vol, enable=True):
+    _check(_lib.sg_set_kernel_timing(vol, int(bool(enable))), "sg_set_kernel_timing")
+
+
+def sg_get_kernel_timing(vol):
+    """(renders, cut-map ms, ray-cast ms) summed since the last query."""
+    n, a, b = C.c_int32(), C.c_double(), C.c_double()
+    _check(_lib.sg_get_kernel_timing(vol, C.byref(n), C.byref(a), C.byref(b)),
+           "sg_get_kernel_timing")
+    return int(n.value), float(a.value), float(b.value)

@@ -1,0 +1,137 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/sg.h, the ctypes structures match the C layout,
+and argument errors are reported without touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sg.h")
+
+
+@pytest.fixture(scope="module")
+def sg():
+    lib = os.path.join(ROOT, "paper_1804_08197_amd", "libsg.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_1804_08197_amd import sg as mod
+    return mod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sg_volume_create", "sg_upload_bricks", "sg_set_transfer_function",
+              "sg_render_views", "sg_volume_destroy", "sg_build_lod", "sg_volume_commit",
+              "sg_get_lod_cut", "sg_render_views_stats", "sg_status_string", "sg_last_error",
+              "sg_abi_version", "sg_volume_memory"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(sg):
+    lib = sg.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", sg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (sg_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layout_matches_c(sg):
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "sg.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(sg_volume_desc), sizeof(sg_view),
+         sizeof(sg_render_params), sizeof(sg_render_stats));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(sg_view, width), offsetof(sg_render_params, lod_bias),
+         offsetof(sg_render_params, flags), offsetof(sg_render_params, depth_alpha),
+         offsetof(sg_render_stats, microblocks));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe],
+                       check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(x) for x in lines[0].split()]
+    offs = [int(x) for x in lines[1].split()]
+    assert sizes == [C.sizeof(sg.sg_volume_desc), C.sizeof(sg.sg_view),
+                     C.sizeof(sg.sg_render_params), C.sizeof(sg.sg_render_stats)]
+    assert offs == [sg.sg_view.width.offset, sg.sg_render_params.lod_bias.offset,
+                    sg.sg_render_params.flags.offset, sg.sg_render_params.depth_alpha.offset,
+                    sg.sg_render_stats.microblocks.offset]
+
+
+def test_version_and_status_strings(sg):
+    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 1
+    for code, name in [(0, "SG_OK"), (-1, "SG_ERR_INVALID_ARG"), (-2, "SG_ERR_OUT_OF_MEMORY"),
+                       (-3, "SG_ERR_DEVICE"), (-4, "SG_ERR_STATE"), (-5, "SG_ERR_UNSUPPORTED")]:
+        assert sg.sg_status_string(code) == name
+    assert sg.sg_status_string(42) == "SG_ERR_UNKNOWN"
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dims=(0, 8, 8)), dict(dims=(8, 8, 8), channels=5), dict(dims=(8, 8, 8), channels=0),
+    dict(dims=(8, 8, 8), timepoints=0), dict(dims=(8, 8, 8), dtype=3),
+    dict(dims=(8, 8, 8), brick=48), dict(dims=(8, 8, 8), brick=1), dict(dims=(8, 8, 8), brick=512),
+    dict(dims=(8, 8, 8), levels=0), dict(dims=(8, 8, 8), levels=17),
+    dict(dims=(8, 8, 8), device=-1)])
+def test_create_rejects_bad_descriptions_without_a_device(sg, kw):
+    with pytest.raises(sg.SgError) as ex:
+        sg.sg_volume_create(**kw)
+    assert ex.value.status == sg.SG_ERR_INVALID_ARG
+    assert sg.sg_last_error()
+
+
+def test_null_arguments_are_invalid(sg):
+    lib = sg.lib()
+    assert lib.sg_volume_create(None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_volume_destroy(None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_volume_commit(None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_build_lod(None, 0, 0, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_upload_bricks(None, 0, 0, 0, 0, None, None, 0, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_set_transfer_function(None, 0, None, 256, 0.0, 1.0) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_render_views(None, 1, None, None, None, None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_render_views_stats(None, 1, None, None, None, None, None, None) == \
+        sg.SG_ERR_INVALID_ARG
+    assert lib.sg_get_lod_cut(None, None, None, None, None, None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_volume_memory(None, None) == sg.SG_ERR_INVALID_ARG
+
+
+def test_valid_description_without_gpu_reports_device_error(sg):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: covered by the GPU tests")
+    with pytest.raises(sg.SgError) as ex:
+        sg.sg_volume_create((64, 64, 64), brick=16, levels=3)
+    assert ex.value.status == sg.SG_ERR_DEVICE
+
+
+def test_pack_bricks_layout():
+    from paper_1804_08197_amd import pack_bricks
+    v = np.arange(5 * 6 * 7, dtype=np.uint16).reshape(5, 6, 7)
+    coords, cores = pack_bricks(v, 4)
+    assert coords.shape == (8, 3) and cores.shape == (8, 4, 4, 4)
+    for (bx, by, bz), core in zip(coords, cores):
+        for z in range(4):
+            for y in range(4):
+                for x in range(4):
+                    gz, gy, gx = min(4 * bz + z, 4), min(4 * by + y, 5), min(4 * bx + x, 6)
+                    assert core[z, y, x] == v[gz, gy, gx]
