@@ -53,7 +53,10 @@ typedef enum { SG_U8 = 1, SG_U16 = 2 } sg_dtype;
 enum {
   SG_LOD = 1u << 0,        /* screen-space LOD cut (Sec 5.2); without it every
                               node is rendered at level lod_bias             */
-  SG_SKIP_EMPTY = 1u << 1  /* skip nodes whose opacity is zero everywhere     */
+  SG_SKIP_EMPTY = 1u << 1, /* skip nodes whose opacity is zero everywhere     */
+  SG_GATHER = 1u << 2      /* tuning/testing: trilinear stencils read the brick
+                              pool directly instead of LDS-staged brick tiles;
+                              the image is bit-identical either way          */
 };
 
 typedef struct sg_volume sg_volume; /* opaque */
@@ -96,7 +99,7 @@ typedef struct {
   double depth_alpha;   /* depth output: first sample with alpha >= this (0.5) */
   int32_t lod_bias;     /* finest level used (0 = full resolution)            */
   int32_t timepoint;    /* 0 .. timepoints-1                                  */
-  uint32_t flags;       /* SG_LOD | SG_SKIP_EMPTY                             */
+  uint32_t flags;       /* SG_LOD | SG_SKIP_EMPTY | SG_GATHER                 */
   int32_t reserved;     /* must be 0                                          */
 } sg_render_params;
 

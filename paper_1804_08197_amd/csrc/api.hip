@@ -127,6 +127,7 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   v->logB = 0;
   while ((1 << v->logB) < v->B) ++v->logB;
   v->S = v->B + 2;
+  v->Sx = ((v->S * v->bpv + 3) / 4) * 4 / v->bpv;
   v->L = d->levels;
   int64_t nodes = 0;
   for (int L = 0; L < v->L; ++L) {
@@ -141,7 +142,7 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   }
   v->node_off[v->L] = nodes;
   v->nodes = nodes;
-  const int64_t S3 = (int64_t)v->S * v->S * v->S;
+  const int64_t S3 = (int64_t)v->S * v->S * v->Sx;
   v->slot_bytes = ((S3 * v->bpv + 64 + 255) / 256) * 256;
   v->slots = (int64_t)d->timepoints * d->channels * nodes;
   if (v->slots > 0x7FFFFFFF) {

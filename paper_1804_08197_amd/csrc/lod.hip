@@ -119,10 +119,10 @@ extern "C" sg_status sg_get_lod_cut(sg_volume* vol, const sg_view* view,
   DeviceGuard guard(v->d.device);
   if (!guard.ok) return fail(SG_ERR_DEVICE, "sg_get_lod_cut: cannot select device");
   hipStream_t s = (hipStream_t)hip_stream;
-  int tiles = 0;
+  int view_blocks = 0;
   sg_status st = commit(v, s);
   if (st != SG_OK) return st;
-  st = prepare_views(v, 1, view, params, nullptr, nullptr, nullptr, s, &tiles);
+  st = prepare_views(v, 1, view, params, nullptr, nullptr, nullptr, s, &view_blocks);
   if (st != SG_OK) return st;
   const bool lod = (params->flags & SG_LOD) != 0;
   st = launch_cutmap(v, reinterpret_cast<const ViewDev*>(v->view_dev), 1, params->lod_bias,

@@ -4,8 +4,8 @@
 //
 // Launch: one 256-thread workgroup per 16x16 pixel tile, four wave64s of
 // 8x8 pixels each; the tiles of all views form one grid (stereo pair or
-// batch in one launch, Sec 5.3). Workgroup ids are remapped so that each of
-// the 8 XCDs (each with its own L2) receives a contiguous band of tiles.
+// batch in one launch, Sec 5.3). Workgroup ids are remapped so that blocks
+// of 4x4 tiles are dealt to the 8 XCDs (each with its own L2) in turn.
 //
 // Per ray:
 //  * FP64 set-up: direction from the pixel tangents, entry/exit against the
@@ -20,10 +20,19 @@
 //    D = step * 2^L level-0 units at the midpoints of the sub-intervals (the
 //    last one partial). Sample positions are evaluated in FP32 in the node's
 //    brick-local coordinates (small magnitudes), from an FP64 segment origin.
-//  * Trilinear interpolation reads the 8 stencil voxels from the node's pool
-//    slot; the apron makes clamping unnecessary. The transfer function lives
-//    in LDS. a = 1 - exp(-rho s), C += (1 - A) a rgb, A += (1 - A) a; the ray
-//    stops when A >= ert (early ray termination).
+//  * Trilinear interpolation of the node's brick (the apron makes clamping
+//    unnecessary), transfer function from LDS, a = 1 - exp(-rho s),
+//    C += (1 - A) a rgb, A += (1 - A) a; the ray stops when A >= ert.
+//
+// Two kernels share all of the per-ray arithmetic, so they give bit-identical
+// images:
+//  * staged (default): the 64 rays of a wave walk their nodes in lockstep,
+//    in the octree's front-to-back order for the view's eye (every ray meets
+//    nodes in that order, so each lane still sees its own segments in
+//    order). For the node at hand the wave stages, slab by slab along the
+//    dominant ray axis, the part of the brick its rays cross into LDS with
+//    coalesced dword loads, and the trilinear stencils read LDS.
+//  * gather: every lane reads its stencils straight from the pool.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -34,6 +43,8 @@
 namespace sg {
 
 namespace {
+
+constexpr int kStageBytesPerWave = 8192;
 
 // 1 - exp(-x) for x >= 0 with small absolute and relative error: a Taylor
 // polynomial below 1/16 (avoids the cancellation of 1 - exp(-x)), the
@@ -74,287 +85,649 @@ __device__ __forceinline__ bool box_interval(const double e[3], const double d[3
   return a < b;
 }
 
-template <typename T>
-__device__ __forceinline__ float ld(const T* p) {
+template <typename P>
+__device__ __forceinline__ float ld(P p) {
   return (float)(*p);
 }
 
-template <typename T, int CH, bool STATS>
-__global__ __launch_bounds__(256) void raycast_kernel(RenderArgs a) {
-  extern __shared__ float4 s_tf[];
-  const int ntf = CH * (a.tf_n + 1);
-  for (int i = threadIdx.x; i < ntf; i += 256)
-    s_tf[i] = reinterpret_cast<const float4*>(a.tf)[i];
-  __syncthreads();
+// Trilinear value of the stencil whose (0,0,0) corner is at p0; sy / sz are
+// the row and plane strides of the array p0 points into.
+template <typename P>
+__device__ __forceinline__ float trilinear(P p0, int sy, int sz, float fx, float fy, float fz) {
+  const float c00 = lerpf(ld(p0), ld(p0 + 1), fx);
+  const float c10 = lerpf(ld(p0 + sy), ld(p0 + sy + 1), fx);
+  const float c01 = lerpf(ld(p0 + sz), ld(p0 + sz + 1), fx);
+  const float c11 = lerpf(ld(p0 + sz + sy), ld(p0 + sz + sy + 1), fx);
+  const float c0 = lerpf(c00, c10, fy);
+  const float c1 = lerpf(c01, c11, fy);
+  return lerpf(c0, c1, fz);
+}
 
-  // XCD-aware tile order: hardware places workgroup i on XCD i % 8.
-  const int G = a.total_tiles;
-  const int q8 = G >> 3;
-  const int bid = blockIdx.x;
-  const int tile = bid < (q8 << 3) ? (bid & 7) * q8 + (bid >> 3) : bid;
-  int v = 0;
-  {
-    int lo = 0, hi = a.n_views - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (a.views[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-    }
-    v = lo;
-  }
-  const ViewDev& V = a.views[v];
-  const int lt = tile - V.tile_begin;
-  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int px = tx * 16 + (w & 1) * 8 + (lane & 7);
-  const int py = ty * 16 + (w >> 1) * 8 + (lane >> 3);
-  if (px >= V.W || py >= V.H) return;
+// ----------------------------------------------------------------- per ray
+struct Ray {
+  double e[3], d[3];
+  double tn, tf;
+  double tnext[3], inv[3];
+  int c[3], st[3];
+  bool alive;   // has entered the volume and is not terminated / exhausted
+  // current segment (valid when alive)
+  int node, L, b[3];
+  double t0, t1;
+  uint64_t key;
+  // sampling state of the current segment (brick-local FP32 frame)
+  float q0[3], dq[3], Df, s_last;
+  int n, k;
+  // accumulation
+  float Cr, Cg, Cb, A, depth;
+  int nsamp;
+};
 
-  // --- ray set-up in FP64 (no contraction in this file)
+__device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const ViewDev& V, int px,
+                                          int py) {
   const double sx = V.tl + (((double)px + 0.5) / (double)V.W) * (V.tr - V.tl);
   const double sy = V.tt - (((double)py + 0.5) / (double)V.H) * (V.tt - V.tb);
-  double e[3], d[3];
-  {
-    double w3[3];
+  double w3[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      e[i] = V.e[i];
-      w3[i] = (V.R[3 * i + 0] * sx + V.R[3 * i + 1] * sy) + V.R[3 * i + 2] * (-1.0);
-    }
-    double len = sqrt((w3[0] * w3[0] + w3[1] * w3[1]) + w3[2] * w3[2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) d[i] = w3[i] / len;
+  for (int i = 0; i < 3; ++i) {
+    r.e[i] = V.e[i];
+    w3[i] = (V.R[3 * i + 0] * sx + V.R[3 * i + 1] * sy) + V.R[3 * i + 2] * (-1.0);
   }
+  const double len = sqrt((w3[0] * w3[0] + w3[1] * w3[1]) + w3[2] * w3[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.d[i] = w3[i] / len;
+  r.Cr = r.Cg = r.Cb = r.A = 0.f;
+  r.depth = INFINITY;
+  r.nsamp = 0;
+  r.n = r.k = 0;
+  const double lo[3] = {0.0, 0.0, 0.0};
+  const double hi[3] = {(double)a.dims[0], (double)a.dims[1], (double)a.dims[2]};
+  box_interval(r.e, r.d, lo, hi, r.tn, r.tf);
+  if (r.tn < 0.0) r.tn = 0.0;
+  r.alive = r.tn < r.tf;
+  if (!r.alive) return;
+  const double Bd = (double)a.B;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double p = r.e[i] + r.tn * r.d[i];
+    const int ci = (int)floor(p / Bd);
+    r.c[i] = ci < 0 ? 0 : (ci > a.grid0[i] - 1 ? a.grid0[i] - 1 : ci);
+    if (r.d[i] > 0.0) {
+      r.st[i] = 1;
+      r.inv[i] = 1.0 / r.d[i];
+      r.tnext[i] = (Bd * (double)(r.c[i] + 1) - r.e[i]) * r.inv[i];
+    } else if (r.d[i] < 0.0) {
+      r.st[i] = -1;
+      r.inv[i] = 1.0 / r.d[i];
+      r.tnext[i] = (Bd * (double)r.c[i] - r.e[i]) * r.inv[i];
+    } else {
+      r.st[i] = 0;
+      r.inv[i] = 0.0;
+      r.tnext[i] = INFINITY;
+    }
+  }
+}
 
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
-  float depth = INFINITY;
-  const bool want_depth = V.depth != nullptr;
-  int nsamp = 0;
-  double tn, tf;
-  {
-    const double lo[3] = {0.0, 0.0, 0.0};
-    const double hi[3] = {(double)a.dims[0], (double)a.dims[1], (double)a.dims[2]};
-    box_interval(e, d, lo, hi, tn, tf);
-    if (tn < 0.0) tn = 0.0;
-  }
-  if (tn < tf) {
-    // --- DDA over level-0 brick cells
-    const double Bd = (double)a.B;
-    int c[3], st[3];
-    double tnext[3], inv[3];
+// Front-to-back key of node (L, b) for eye e: the octree path from a virtual
+// root covering the volume, each child index flipped so that the child on
+// the eye's side of each splitting plane comes first. Sorting nodes of a
+// cut by this key orders them front to back for every ray from e.
+__device__ __forceinline__ uint64_t visibility_key(const RenderArgs& a, const double e[3], int L,
+                                                   const int b[3]) {
+  uint64_t key = 0;
+  for (int l = a.key_levels - 1; l >= L; --l) {
+    uint32_t code = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      double p = e[i] + tn * d[i];
-      int ci = (int)floor(p / Bd);
-      c[i] = ci < 0 ? 0 : (ci > a.grid0[i] - 1 ? a.grid0[i] - 1 : ci);
-      if (d[i] > 0.0) {
-        st[i] = 1;
-        inv[i] = 1.0 / d[i];
-        tnext[i] = (Bd * (double)(c[i] + 1) - e[i]) * inv[i];
-      } else if (d[i] < 0.0) {
-        st[i] = -1;
-        inv[i] = 1.0 / d[i];
-        tnext[i] = (Bd * (double)c[i] - e[i]) * inv[i];
-      } else {
-        st[i] = 0;
-        inv[i] = 0.0;
-        tnext[i] = INFINITY;
-      }
+      const int cb = b[i] >> (l - L);
+      const double split = (double)((int64_t)a.B << l) * (double)(2 * (cb >> 1) + 1);
+      const uint32_t f = (uint32_t)(cb & 1) ^ (uint32_t)(e[i] >= split);
+      code = (code << 1) | f;
     }
-    const int32_t* cutmap = a.cutmap + V.cut_off;
-    bool alive = true;
-    while (alive) {
-      const int32_t node =
-          cutmap[((int64_t)c[2] * a.grid0[1] + c[1]) * a.grid0[0] + c[0]];
-      const NodeInfo ni = a.info[node];
-      const int L = ni.level;
-      // node box (level-0 units, clipped to the volume)
-      double blo[3], bhi[3];
+    key = (key << 3) | code;
+  }
+  return key << (3 * L);
+}
+
+// Advance the ray to its next segment that needs samples: a cut node whose
+// parameter interval is non-empty and that is not skipped as empty. With
+// `first` the current DDA cell is examined before stepping.
+__device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const ViewDev& V,
+                                             bool first) {
+  const int32_t* cutmap = a.cutmap + V.cut_off;
+  const double Bd = (double)a.B;
+  bool step = !first;
+  while (true) {
+    if (step) {
+      // leave the current node: step cells until one outside the node's box
       int clo[3], chi[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        int64_t wdt = (int64_t)a.B << L;
-        int64_t l0 = wdt * ni.b[i];
-        int64_t h0 = wdt * (ni.b[i] + 1);
-        if (h0 > a.dims[i]) h0 = a.dims[i];
-        blo[i] = (double)l0;
-        bhi[i] = (double)h0;
-        clo[i] = ni.b[i] << L;
-        chi[i] = min(((ni.b[i] + 1) << L) - 1, a.grid0[i] - 1);
+        clo[i] = r.b[i] << r.L;
+        chi[i] = min(((r.b[i] + 1) << r.L) - 1, a.grid0[i] - 1);
       }
-      double t0, t1;
-      box_interval(e, d, blo, bhi, t0, t1);
-      if (t0 < tn) t0 = tn;
-      if (t1 > tf) t1 = tf;
-      const bool skip = a.skip_empty && a.empty[node];
-      if (t0 < t1 && !skip) {
-        // --- segment integration at level L
-        const double Dd = a.step * (double)((int64_t)1 << L);
-        const double len = t1 - t0;
-        const int n = (int)ceil(len / Dd);
-        const float s_last = (float)(len - (double)(n - 1) * Dd);
-        const float Df = (float)Dd;
-        const double inv_s = 1.0 / (double)((int64_t)1 << L);
-        float q0[3], dq[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double o = (double)((int64_t)a.B * ((int64_t)ni.b[i] << L));
-          q0[i] = (float)(((e[i] - o) + t0 * d[i]) * inv_s + 0.5);
-          dq[i] = (float)(d[i] * inv_s);
-        }
-        const T* slot[CH];
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-          slot[ch] = reinterpret_cast<const T*>(
-              a.pool + (int64_t)a.page[(int64_t)ch * a.nodes + node] * a.slot_bytes);
-        const int S = a.S;
-        const int S2 = S * S;
-        for (int k = 0; k < n; ++k) {
-          const float s = k == n - 1 ? s_last : Df;
-          const float tau = fmaf((float)k, Df, 0.5f * s);
-          const float qx = fmaf(tau, dq[0], q0[0]);
-          const float qy = fmaf(tau, dq[1], q0[1]);
-          const float qz = fmaf(tau, dq[2], q0[2]);
-          // stencil origin, kept inside the slot (it always is for samples
-          // inside the node box; the clamp only guards memory safety)
-          const int ix = min(max((int)qx, 0), a.B);
-          const int iy = min(max((int)qy, 0), a.B);
-          const int iz = min(max((int)qz, 0), a.B);
-          const float fx = qx - (float)ix, fy = qy - (float)iy, fz = qz - (float)iz;
-          const int base = (iz * S + iy) * S + ix;
-          float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
-#pragma unroll
-          for (int ch = 0; ch < CH; ++ch) {
-            const T* p0 = slot[ch] + base;
-            const T* p1 = p0 + S2;
-            float c00 = lerpf(ld(p0), ld(p0 + 1), fx);
-            float c10 = lerpf(ld(p0 + S), ld(p0 + S + 1), fx);
-            float c01 = lerpf(ld(p1), ld(p1 + 1), fx);
-            float c11 = lerpf(ld(p1 + S), ld(p1 + S + 1), fx);
-            float c0 = lerpf(c00, c10, fy);
-            float c1 = lerpf(c01, c11, fy);
-            float val = lerpf(c0, c1, fz);
-            float u = fmaf(val, a.tf_scale[ch], a.tf_bias[ch]);
-            u = fminf(fmaxf(u, 0.0f), (float)(a.tf_n - 1));
-            const int k0 = (int)u;
-            const float wt = u - (float)k0;
-            const float4 t0v = s_tf[ch * (a.tf_n + 1) + k0];
-            const float4 t1v = s_tf[ch * (a.tf_n + 1) + k0 + 1];
-            const float r = lerpf(t0v.x, t1v.x, wt);
-            const float g = lerpf(t0v.y, t1v.y, wt);
-            const float b = lerpf(t0v.z, t1v.z, wt);
-            const float rh = lerpf(t0v.w, t1v.w, wt);
-            if (CH == 1) {
-              er = r;
-              eg = g;
-              eb = b;
-              rho = rh;
-            } else {
-              rho += rh;
-              er = fmaf(rh, r, er);
-              eg = fmaf(rh, g, eg);
-              eb = fmaf(rh, b, eb);
-            }
-            if (STATS) {
-              // distinct 4^3 blocks of this level read by the stencil
-              const int32_t* nL = a.ldims[L];
-              int gl[3] = {a.B * ni.b[0] - 1 + ix, a.B * ni.b[1] - 1 + iy,
-                           a.B * ni.b[2] - 1 + iz};
-              int lo3[3], hi3[3], m3[3];
-#pragma unroll
-              for (int i = 0; i < 3; ++i) {
-                int g0 = gl[i] < 0 ? 0 : (gl[i] > nL[i] - 1 ? nL[i] - 1 : gl[i]);
-                int g1 = gl[i] + 1 > nL[i] - 1 ? nL[i] - 1 : gl[i] + 1;
-                lo3[i] = g0 >> 2;
-                hi3[i] = g1 >> 2;
-                m3[i] = (nL[i] + 3) >> 2;
-              }
-              const int64_t off = a.level_mb_off[ch * kMaxLevels + L];
-              for (int zz = lo3[2]; zz <= hi3[2]; ++zz)
-                for (int yy = lo3[1]; yy <= hi3[1]; ++yy)
-                  for (int xx = lo3[0]; xx <= hi3[0]; ++xx) {
-                    int64_t bit = off + ((int64_t)zz * m3[1] + yy) * m3[0] + xx;
-                    atomicOr(a.mb_bits + (bit >> 5), 1u << (bit & 31));
-                  }
-            }
-          }
-          if (CH > 1) {
-            const float inv_r = rho > 0.f ? 1.0f / rho : 0.f;
-            er *= inv_r;
-            eg *= inv_r;
-            eb *= inv_r;
-          }
-          const float al = one_minus_exp_neg(rho * s);
-          const float wgt = (1.0f - A) * al;
-          Cr = fmaf(wgt, er, Cr);
-          Cg = fmaf(wgt, eg, Cg);
-          Cb = fmaf(wgt, eb, Cb);
-          A += wgt;
-          if (STATS) ++nsamp;
-          if (want_depth && depth == INFINITY && A >= a.depth_alpha)
-            depth = (float)(t0 + (double)tau);
-          if (A >= a.ert) {
-            alive = false;
-            break;
-          }
-        }
-      }
-      if (!alive) break;
-      // --- advance the DDA out of this node
       bool inside = true;
       while (inside) {
         int ax = 0;
-        if (tnext[1] < tnext[ax]) ax = 1;
-        if (tnext[2] < tnext[ax]) ax = 2;
-        if (!(tnext[ax] < tf)) {
-          alive = false;
-          break;
+        if (r.tnext[1] < r.tnext[ax]) ax = 1;
+        if (r.tnext[2] < r.tnext[ax]) ax = 2;
+        if (!(r.tnext[ax] < r.tf)) {
+          r.alive = false;
+          return;
         }
-        c[ax] += st[ax];
-        if (c[ax] < 0 || c[ax] >= a.grid0[ax]) {
-          alive = false;
-          break;
+        r.c[ax] += r.st[ax];
+        if (r.c[ax] < 0 || r.c[ax] >= a.grid0[ax]) {
+          r.alive = false;
+          return;
         }
-        tnext[ax] = (Bd * (double)(c[ax] + (st[ax] > 0 ? 1 : 0)) - e[ax]) * inv[ax];
-        inside = c[0] >= clo[0] && c[0] <= chi[0] && c[1] >= clo[1] && c[1] <= chi[1] &&
-                 c[2] >= clo[2] && c[2] <= chi[2];
+        r.tnext[ax] = (Bd * (double)(r.c[ax] + (r.st[ax] > 0 ? 1 : 0)) - r.e[ax]) * r.inv[ax];
+        inside = r.c[0] >= clo[0] && r.c[0] <= chi[0] && r.c[1] >= clo[1] &&
+                 r.c[1] <= chi[1] && r.c[2] >= clo[2] && r.c[2] <= chi[2];
+      }
+    }
+    step = true;
+    r.node = cutmap[((int64_t)r.c[2] * a.grid0[1] + r.c[1]) * a.grid0[0] + r.c[0]];
+    const NodeInfo ni = a.info[r.node];
+    r.L = ni.level;
+    double blo[3], bhi[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      r.b[i] = ni.b[i];
+      const int64_t wdt = (int64_t)a.B << r.L;
+      const int64_t l0 = wdt * ni.b[i];
+      int64_t h0 = wdt * (ni.b[i] + 1);
+      if (h0 > a.dims[i]) h0 = a.dims[i];
+      blo[i] = (double)l0;
+      bhi[i] = (double)h0;
+    }
+    double t0, t1;
+    box_interval(r.e, r.d, blo, bhi, t0, t1);
+    if (t0 < r.tn) t0 = r.tn;
+    if (t1 > r.tf) t1 = r.tf;
+    if (!(t0 < t1) || (a.skip_empty && a.empty[r.node])) continue;
+    r.t0 = t0;
+    r.t1 = t1;
+    // sampling frame: stored index of the brick, FP32 from an FP64 origin
+    const double Dd = a.step * (double)((int64_t)1 << r.L);
+    const double len = t1 - t0;
+    r.n = (int)ceil(len / Dd);
+    r.k = 0;
+    r.s_last = (float)(len - (double)(r.n - 1) * Dd);
+    r.Df = (float)Dd;
+    const double inv_s = 1.0 / (double)((int64_t)1 << r.L);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double o = (double)((int64_t)a.B * ((int64_t)r.b[i] << r.L));
+      r.q0[i] = (float)(((r.e[i] - o) + t0 * r.d[i]) * inv_s + 0.5);
+      r.dq[i] = (float)(r.d[i] * inv_s);
+    }
+    return;
+  }
+}
+
+// Ray parameter (from the segment start, level-0 units) of sample k.
+__device__ __forceinline__ float sample_tau(const Ray& r, int k) {
+  const float s = k == r.n - 1 ? r.s_last : r.Df;
+  return fmaf((float)k, r.Df, 0.5f * s);
+}
+
+// Shade and composite sample r.k; `fetch(ch, ix, iy, iz, fx, fy, fz)`
+// returns the trilinear value of channel ch at stored index (ix, iy, iz)
+// plus fraction. Returns false once the ray has terminated.
+template <int CH, bool STATS, typename F>
+__device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
+                                            bool want_depth, F&& fetch, int (*mb_key)[3]) {
+  const int k = r.k;
+  const float s = k == r.n - 1 ? r.s_last : r.Df;
+  const float tau = fmaf((float)k, r.Df, 0.5f * s);
+  const float qx = fmaf(tau, r.dq[0], r.q0[0]);
+  const float qy = fmaf(tau, r.dq[1], r.q0[1]);
+  const float qz = fmaf(tau, r.dq[2], r.q0[2]);
+  // stencil origin, kept inside the slot (it always is for samples inside
+  // the node box; the clamp only guards memory safety)
+  const int ix = min(max((int)qx, 0), a.B);
+  const int iy = min(max((int)qy, 0), a.B);
+  const int iz = min(max((int)qz, 0), a.B);
+  const float fx = qx - (float)ix, fy = qy - (float)iy, fz = qz - (float)iz;
+  float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    const float val = fetch(ch, ix, iy, iz, fx, fy, fz);
+    float u = fmaf(val, a.tf_scale[ch], a.tf_bias[ch]);
+    u = fminf(fmaxf(u, 0.0f), (float)(a.tf_n - 1));
+    const int k0 = (int)u;
+    const float wt = u - (float)k0;
+    const float4 t0v = s_tf[ch * (a.tf_n + 1) + k0];
+    const float4 t1v = s_tf[ch * (a.tf_n + 1) + k0 + 1];
+    const float cr = lerpf(t0v.x, t1v.x, wt);
+    const float cg = lerpf(t0v.y, t1v.y, wt);
+    const float cb = lerpf(t0v.z, t1v.z, wt);
+    const float rh = lerpf(t0v.w, t1v.w, wt);
+    if (CH == 1) {
+      er = cr;
+      eg = cg;
+      eb = cb;
+      rho = rh;
+    } else {
+      rho += rh;
+      er = fmaf(rh, cr, er);
+      eg = fmaf(rh, cg, eg);
+      eb = fmaf(rh, cb, eb);
+    }
+    if (STATS) {
+      // distinct 4^3 blocks of this level read by the stencil; consecutive
+      // samples mostly reuse the previous blocks, so mark only on change
+      const int32_t* nL = a.ldims[r.L];
+      const int gl[3] = {a.B * r.b[0] - 1 + ix, a.B * r.b[1] - 1 + iy, a.B * r.b[2] - 1 + iz};
+      int lo3[3], hi3[3], m3[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int g0 = gl[i] < 0 ? 0 : (gl[i] > nL[i] - 1 ? nL[i] - 1 : gl[i]);
+        const int g1 = gl[i] + 1 > nL[i] - 1 ? nL[i] - 1 : gl[i] + 1;
+        lo3[i] = g0 >> 2;
+        hi3[i] = g1 >> 2;
+        m3[i] = (nL[i] + 3) >> 2;
+      }
+      const int key0 = (lo3[0] | (lo3[1] << 16)) ^ (r.L << 27);
+      const int key1 = lo3[2] | (hi3[0] << 16);
+      const int key2 = hi3[1] | (hi3[2] << 16);
+      int* mk = mb_key[ch];
+      if (!(key0 == mk[0] && key1 == mk[1] && key2 == mk[2])) {
+        mk[0] = key0;
+        mk[1] = key1;
+        mk[2] = key2;
+        const int64_t off = a.level_mb_off[ch * kMaxLevels + r.L];
+        for (int zz = lo3[2]; zz <= hi3[2]; ++zz)
+          for (int yy = lo3[1]; yy <= hi3[1]; ++yy)
+            for (int xx = lo3[0]; xx <= hi3[0]; ++xx) {
+              const int64_t bit = off + ((int64_t)zz * m3[1] + yy) * m3[0] + xx;
+              atomicOr(a.mb_bits + (bit >> 5), 1u << (bit & 31));
+            }
       }
     }
   }
-  const float omA = 1.0f - A;
+  if (CH > 1) {
+    const float inv_r = rho > 0.f ? 1.0f / rho : 0.f;
+    er *= inv_r;
+    eg *= inv_r;
+    eb *= inv_r;
+  }
+  const float al = one_minus_exp_neg(rho * s);
+  const float wgt = (1.0f - r.A) * al;
+  r.Cr = fmaf(wgt, er, r.Cr);
+  r.Cg = fmaf(wgt, eg, r.Cg);
+  r.Cb = fmaf(wgt, eb, r.Cb);
+  r.A += wgt;
+  r.k = k + 1;
+  if (STATS) ++r.nsamp;
+  if (want_depth && r.depth == INFINITY && r.A >= a.depth_alpha)
+    r.depth = (float)(r.t0 + (double)tau);
+  if (r.A >= a.ert) {
+    r.alive = false;
+    return false;
+  }
+  return true;
+}
+
+// Pool slot pointers of a node, one per channel.
+template <typename T, int CH>
+__device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T* slot[CH]) {
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch)
+    slot[ch] = reinterpret_cast<const T*>(
+        a.pool + (int64_t)a.page[(int64_t)ch * a.nodes + node] * a.slot_bytes);
+}
+
+__device__ __forceinline__ void write_pixel(const Ray& r, const RenderArgs& a, const ViewDev& V,
+                                            int px, int py) {
+  const float omA = 1.0f - r.A;
   const int64_t pix = (int64_t)py * V.W + px;
   float4 out;
-  out.x = fmaf(omA, a.bg[0], Cr);
-  out.y = fmaf(omA, a.bg[1], Cg);
-  out.z = fmaf(omA, a.bg[2], Cb);
-  out.w = fmaf(omA, a.bg[3], A);
+  out.x = fmaf(omA, a.bg[0], r.Cr);
+  out.y = fmaf(omA, a.bg[1], r.Cg);
+  out.z = fmaf(omA, a.bg[2], r.Cb);
+  out.w = fmaf(omA, a.bg[3], r.A);
   reinterpret_cast<float4*>(V.rgba)[pix] = out;
-  if (V.depth) V.depth[pix] = depth;
+  if (V.depth) V.depth[pix] = r.depth;
+}
+
+// Tile of this lane. Workgroups go to the 8 XCDs round-robin (workgroup i
+// on XCD i % 8). Tiles are grouped into blocks of 4x4 tiles (64x64 pixels,
+// about one brick's footprint at the selected level) and the blocks are dealt
+// to the XCDs in turn: the 16 tiles of a block share one XCD's L2, and every
+// XCD gets an even share of the image (heavy regions are spread out).
+struct TileLane {
+  int view, px, py;
+  bool in_image;
+  bool tile_valid;
+};
+
+__device__ __forceinline__ TileLane tile_lane(const RenderArgs& a) {
+  const int bid = blockIdx.x;
+  const int x = bid & 7, j = bid >> 3;
+  const int block = (j >> 4) * 8 + x;
+  const int t = j & 15;
+  TileLane out;
+  out.view = 0;
+  out.px = out.py = 0;
+  out.in_image = false;
+  out.tile_valid = block < a.total_blocks;
+  if (!out.tile_valid) return out;
+  int lo = 0, hi = a.n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.views[mid].block_begin <= block) lo = mid; else hi = mid - 1;
+  }
+  const ViewDev& V = a.views[lo];
+  const int lb = block - V.block_begin;
+  const int bx = lb % V.blocks_x, by = lb / V.blocks_x;
+  const int tx = bx * 4 + (t & 3), ty = by * 4 + (t >> 2);
+  out.tile_valid = tx < V.tiles_x && ty < V.tiles_y;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  out.view = lo;
+  out.px = tx * 16 + (w & 1) * 8 + (lane & 7);
+  out.py = ty * 16 + (w >> 1) * 8 + (lane >> 3);
+  out.in_image = out.tile_valid && out.px < V.W && out.py < V.H;
+  return out;
+}
+
+template <int CH>
+__device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
+  const int ntf = CH * (a.tf_n + 1);
+  for (int i = threadIdx.x; i < ntf; i += 256) s_tf[i] = reinterpret_cast<const float4*>(a.tf)[i];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ gather kernel
+template <typename T, int CH, bool STATS>
+__global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
+  extern __shared__ float4 s_tf[];
+  load_tf<CH>(a, s_tf);
+  const TileLane tl = tile_lane(a);
+  if (!tl.in_image) return;
+  const ViewDev& V = a.views[tl.view];
+  const bool want_depth = V.depth != nullptr;
+  int mb_key[CH][3];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
+  Ray r;
+  ray_setup(r, a, V, tl.px, tl.py);
+  if (r.alive) next_segment(r, a, V, true);
+  const int sy = a.Sx, sz = a.S * a.Sx;
+  while (r.alive) {
+    const T* slot[CH];
+    slot_ptrs<T, CH>(a, r.node, slot);
+    auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+      return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
+    };
+    bool go = true;
+    while (go && r.k < r.n) go = sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key);
+    if (!go) break;
+    next_segment(r, a, V, false);
+  }
+  write_pixel(r, a, V, tl.px, tl.py);
   if (STATS) {
-    if (V.nsamp) V.nsamp[pix] = nsamp;
-    atomicAdd((unsigned long long*)a.counters, (unsigned long long)nsamp);
+    if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
+    atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
+  }
+}
+
+// ------------------------------------------------------------ staged kernel
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = (uint64_t)__shfl_xor((unsigned long long)v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Stencil corner bounds (per axis; the stencil also reads corner + 1) of
+// samples ka and kb of the lane's segment, hence of every sample between.
+__device__ __forceinline__ void stencil_bounds(const Ray& r, int ka, int kb, int B, int lo[3],
+                                               int hi[3]) {
+  const float ta = sample_tau(r, ka), tb = sample_tau(r, kb);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int ia = min(max((int)fmaf(ta, r.dq[i], r.q0[i]), 0), B);
+    const int ib = min(max((int)fmaf(tb, r.dq[i], r.q0[i]), 0), B);
+    lo[i] = min(ia, ib);
+    hi[i] = max(ia, ib);
+  }
+}
+
+__device__ __forceinline__ float pick(const float v[3], int m) {
+  return m == 0 ? v[0] : (m == 1 ? v[1] : v[2]);
+}
+__device__ __forceinline__ int pick(const int v[3], int m) {
+  return m == 0 ? v[0] : (m == 1 ? v[1] : v[2]);
+}
+
+template <typename T, int CH, bool STATS>
+__global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
+  extern __shared__ float4 smem[];
+  float4* s_tf = smem;
+  load_tf<CH>(a, s_tf);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
+                                  w * kStageBytesPerWave);
+  // voxels per channel, a multiple of 4 so every channel's region is
+  // dword-aligned in LDS
+  constexpr int cap = (kStageBytesPerWave / (int)sizeof(T) / CH) & ~3;
+  constexpr int align = 4 / (int)sizeof(T);                        // voxels per dword
+
+  const TileLane tl = tile_lane(a);
+  if (!tl.tile_valid) return;  // uniform over the workgroup; no barrier follows
+  const ViewDev& V = a.views[tl.view];
+  const bool want_depth = V.depth != nullptr;
+  int mb_key[CH][3];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
+  Ray r;
+  r.alive = false;
+  r.Cr = r.Cg = r.Cb = r.A = 0.f;
+  r.depth = INFINITY;
+  r.nsamp = 0;
+  r.n = r.k = 0;
+  if (tl.in_image) {
+    ray_setup(r, a, V, tl.px, tl.py);
+    if (r.alive) next_segment(r, a, V, true);
+    if (r.alive) r.key = visibility_key(a, r.e, r.L, r.b);
+  }
+  const int B = a.B, S = a.S, Sx = a.Sx;
+
+  while (true) {
+    // --- the wave's next node: smallest front-to-back key among its rays
+    const uint64_t K = wave_min_u64(r.alive ? r.key : ~0ull);
+    if (K == ~0ull) break;
+    const bool mine = r.alive && r.key == K;
+    const uint64_t mask = __ballot(mine);
+    const int first = __ffsll((unsigned long long)mask) - 1;
+    const int node = uniform(__shfl(r.node, first));
+    const T* slot[CH];
+    slot_ptrs<T, CH>(a, node, slot);
+
+    // --- dominant axis of the node's first ray; every ray of the node must
+    // advance along it with the same sign, else everything reads the pool
+    const float d0[3] = {__shfl(r.dq[0], first), __shfl(r.dq[1], first),
+                         __shfl(r.dq[2], first)};
+    int m = 0;
+    if (fabsf(d0[1]) > fabsf(d0[0])) m = 1;
+    if (fabsf(d0[2]) > fabsf(pick(d0, m))) m = 2;
+    m = uniform(m);
+    const int sgn = uniform(pick(d0, m) > 0.f ? 1 : -1);
+    const float my_dqm = pick(r.dq, m);
+    const float my_qm0 = pick(r.q0, m);
+    const float my_sum = fabsf(r.dq[0]) + fabsf(r.dq[1]) + fabsf(r.dq[2]);
+    const bool bad = mine && !((float)sgn * my_dqm >= 0.25f * my_sum);
+    const bool axis_ok = __ballot(bad) == 0;
+
+    // --- main-axis range of the node's stencils over the wave's rays
+    int nlo[3] = {1 << 20, 1 << 20, 1 << 20}, nhi[3] = {-1, -1, -1};
+    if (mine) stencil_bounds(r, r.k, r.n - 1, B, nlo, nhi);
+    const int mlo = uniform(wave_min_i(pick(nlo, m)));
+    const int mhi = uniform(wave_max_i(pick(nhi, m)));
+
+    // --- slabs along the main axis, in the rays' direction of travel
+    int j = sgn > 0 ? mlo : mhi;  // next owned stencil layer
+    int D = 8;
+    while (true) {
+      const bool more = mine && r.alive && r.k < r.n;
+      if (__ballot(more) == 0) break;
+      const bool in_range = axis_ok && (sgn > 0 ? j <= mhi : j >= mlo);
+      // owned stencil layers [jl, jh]; staged region = owned layers + 1
+      int jl = j, jh = j;
+      int o[3] = {0, 0, 0}, wd[3] = {0, 0, 0};
+      bool fits = false;
+      if (in_range) {
+        for (int tries = 0; tries < 8; ++tries) {
+          jl = sgn > 0 ? j : max(j - D + 1, mlo);
+          jh = sgn > 0 ? min(j + D - 1, mhi) : j;
+          int lo3[3] = {1 << 20, 1 << 20, 1 << 20}, hi3[3] = {-1, -1, -1};
+          if (more) {
+            // last sample of this lane still inside the slab (one extra
+            // sample is included; the bounds stay conservative)
+            const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
+            const float tlim = (edge - my_qm0) / my_dqm;
+            int kb = (int)ceilf(tlim / r.Df - 0.5f);
+            kb = min(max(kb, r.k), r.n - 1);
+            stencil_bounds(r, r.k, kb, B, lo3, hi3);
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            if (i == m) {
+              o[i] = jl;
+              wd[i] = jh - jl + 2;
+            } else {
+              const int l = uniform(wave_min_i(lo3[i]));
+              const int h = uniform(wave_max_i(hi3[i]));
+              o[i] = l <= h ? l : 0;
+              wd[i] = l <= h ? h - l + 2 : 0;
+            }
+          }
+          // dword-aligned rows: x origin rounded down, width rounded up
+          const int ox = (o[0] / align) * align;
+          wd[0] = ((o[0] + wd[0] - ox + align - 1) / align) * align;
+          o[0] = ox;
+          wd[0] = min(wd[0], Sx - o[0]);
+          wd[1] = min(wd[1], S - o[1]);
+          wd[2] = min(wd[2], S - o[2]);
+          const int vox = wd[0] * wd[1] * wd[2];
+          if (vox > 0 && vox <= cap) {
+            fits = true;
+            break;
+          }
+          if (D == 1) break;
+          D = max(1, D / 2);
+        }
+      }
+      if (fits) {
+        // --- stage the region of every channel: dword loads along rows
+        const int dpr = wd[0] / align;  // dwords per row
+        const int total = dpr * wd[1] * wd[2];
+        const float inv_dpr = 1.0f / (float)dpr, inv_wy = 1.0f / (float)wd[1];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(slot[ch]);
+          uint32_t* dst = reinterpret_cast<uint32_t*>(stage + ch * cap);
+          for (int i = lane; i < total; i += 64) {
+            const int row = (int)(((float)i + 0.5f) * inv_dpr);
+            const int col = i - row * dpr;
+            const int rz = (int)(((float)row + 0.5f) * inv_wy);
+            const int ry = row - rz * wd[1];
+            const int g = ((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0];
+            dst[i] = src[g / align + col];
+          }
+        }
+        wave_sync();
+      }
+      // --- sample this slab; stencils outside the staged region (or all of
+      // them when nothing is staged) read the pool
+      if (more) {
+        const int sy_l = wd[0], sz_l = wd[0] * wd[1];
+        auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+          const int lx = ix - o[0], ly = iy - o[1], lz = iz - o[2];
+          if (fits && lx >= 0 && lx <= wd[0] - 2 && ly >= 0 && ly <= wd[1] - 2 && lz >= 0 &&
+              lz <= wd[2] - 2)
+            return trilinear(stage + ch * cap + (lz * wd[1] + ly) * wd[0] + lx, sy_l, sz_l, fx,
+                             fy, fz);
+          return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
+        };
+        while (r.k < r.n) {
+          if (in_range) {
+            const float qm = fmaf(sample_tau(r, r.k), my_dqm, my_qm0);
+            const int im = min(max((int)qm, 0), B);
+            if (sgn > 0 ? im > jh : im < jl) break;
+          }
+          if (!sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) break;
+        }
+      }
+      wave_sync();
+      if (!in_range) continue;  // this pass read the pool for all that was left
+      j = sgn > 0 ? jh + 1 : jl - 1;
+      if (fits) D = min(D * 2, 64);
+    }
+    // --- rays that finished this node move on to their next segment
+    if (mine && r.alive) {
+      next_segment(r, a, V, false);
+      if (r.alive) r.key = visibility_key(a, r.e, r.L, r.b);
+    }
+  }
+  if (tl.in_image) {
+    write_pixel(r, a, V, tl.px, tl.py);
+    if (STATS) {
+      if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
+      atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
+    }
   }
 }
 
 template <typename T, int CH>
-sg_status launch_t(const RenderArgs& a, bool stats, hipStream_t s) {
-  const size_t lds = (size_t)CH * (a.tf_n + 1) * sizeof(float4);
-  if (stats)
-    hipLaunchKernelGGL((raycast_kernel<T, CH, true>), dim3(a.total_tiles), dim3(256), lds, s,
-                       a);
-  else
-    hipLaunchKernelGGL((raycast_kernel<T, CH, false>), dim3(a.total_tiles), dim3(256), lds,
-                       s, a);
+sg_status launch_t(const RenderArgs& a, bool stats, bool gather, hipStream_t s) {
+  const size_t tf_lds = (size_t)CH * (a.tf_n + 1) * sizeof(float4);
+  if (gather) {
+    if (stats)
+      hipLaunchKernelGGL((raycast_gather<T, CH, true>), dim3(a.grid), dim3(256), tf_lds,
+                         s, a);
+    else
+      hipLaunchKernelGGL((raycast_gather<T, CH, false>), dim3(a.grid), dim3(256), tf_lds,
+                         s, a);
+  } else {
+    const size_t lds = tf_lds + 4 * kStageBytesPerWave;
+    if (stats)
+      hipLaunchKernelGGL((raycast_staged<T, CH, true>), dim3(a.grid), dim3(256), lds, s,
+                         a);
+    else
+      hipLaunchKernelGGL((raycast_staged<T, CH, false>), dim3(a.grid), dim3(256), lds, s,
+                         a);
+  }
   SG_HIP(hipGetLastError());
   return SG_OK;
 }
 
 template <typename T>
-sg_status launch_ch(const RenderArgs& a, int C, bool stats, hipStream_t s) {
+sg_status launch_ch(const RenderArgs& a, int C, bool stats, bool gather, hipStream_t s) {
   switch (C) {
-    case 1: return launch_t<T, 1>(a, stats, s);
-    case 2: return launch_t<T, 2>(a, stats, s);
-    case 3: return launch_t<T, 3>(a, stats, s);
-    default: return launch_t<T, 4>(a, stats, s);
+    case 1: return launch_t<T, 1>(a, stats, gather, s);
+    case 2: return launch_t<T, 2>(a, stats, gather, s);
+    case 3: return launch_t<T, 3>(a, stats, gather, s);
+    default: return launch_t<T, 4>(a, stats, gather, s);
   }
 }
 
@@ -363,26 +736,27 @@ bool finite(double x) { return std::isfinite(x); }
 }  // namespace
 
 sg_status launch_raycast(Volume* v, const RenderArgs& a, bool stats, hipStream_t s) {
-  if (v->bpv == 1) return launch_ch<uint8_t>(a, v->d.channels, stats, s);
-  return launch_ch<uint16_t>(a, v->d.channels, stats, s);
+  if (v->bpv == 1) return launch_ch<uint8_t>(a, v->d.channels, stats, a.gather != 0, s);
+  return launch_ch<uint16_t>(a, v->d.channels, stats, a.gather != 0, s);
 }
 
 sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         const sg_render_params* p, float* const* rgba,
                         float* const* depth, int32_t* const* nsamp, hipStream_t s,
-                        int* total_tiles) {
+                        int* total_blocks) {
   if (n_views < 1 || n_views > 4096 || !views || !p)
     return fail(SG_ERR_INVALID_ARG, "views: n_views must be in [1, 4096]");
-  if (!(finite(p->step_voxels) && p->step_voxels >= 1.0 / 64 && p->step_voxels <= 64.0) || !finite(p->ert_alpha) ||
+  if (!(finite(p->step_voxels) && p->step_voxels >= 1.0 / 64 && p->step_voxels <= 64.0) ||
+      !finite(p->ert_alpha) ||
       !(finite(p->lod_tau_px) && p->lod_tau_px > 0.0) || !finite(p->depth_alpha) ||
       p->lod_bias < 0 || p->lod_bias >= v->L || p->timepoint < 0 ||
-      p->timepoint >= v->d.timepoints || (p->flags & ~(uint32_t)(SG_LOD | SG_SKIP_EMPTY)) ||
-      p->reserved != 0)
+      p->timepoint >= v->d.timepoints ||
+      (p->flags & ~(uint32_t)(SG_LOD | SG_SKIP_EMPTY | SG_GATHER)) || p->reserved != 0)
     return fail(SG_ERR_INVALID_ARG, "render params out of range");
   for (int i = 0; i < 4; ++i)
     if (!finite(p->background[i])) return fail(SG_ERR_INVALID_ARG, "background not finite");
   std::vector<ViewDev> hv(n_views);
-  int64_t tiles = 0;
+  int64_t blocks = 0;
   const int64_t cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
   for (int i = 0; i < n_views; ++i) {
     const sg_view& w = views[i];
@@ -417,14 +791,16 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
     o.W = w.width;
     o.H = w.height;
     o.tiles_x = (w.width + 15) / 16;
-    o.tile_begin = (int32_t)tiles;
-    tiles += (int64_t)o.tiles_x * ((w.height + 15) / 16);
+    o.tiles_y = (w.height + 15) / 16;
+    o.blocks_x = (o.tiles_x + 3) / 4;
+    o.block_begin = (int32_t)blocks;
+    blocks += (int64_t)o.blocks_x * ((o.tiles_y + 3) / 4);
     o.cut_off = (int64_t)i * cells;
     o.rgba = rgba ? rgba[i] : nullptr;
     o.depth = depth ? depth[i] : nullptr;
     o.nsamp = nsamp ? nsamp[i] : nullptr;
   }
-  if (tiles > 0x7FFFFFFF) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
+  if (blocks > (1 << 24)) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
   const int64_t need_cut = (int64_t)n_views * cells;
   if (need_cut > v->cutmap_cap) {
     SG_HIP(hipStreamSynchronize(s));
@@ -447,7 +823,7 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
   }
   sg_status st = stage_to_device(v, hv.data(), vbytes, v->view_dev, s);
   if (st != SG_OK) return st;
-  *total_tiles = (int)tiles;
+  *total_blocks = (int)blocks;
   return SG_OK;
 }
 
@@ -460,16 +836,16 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   if (!views) return fail(SG_ERR_INVALID_ARG, "views is NULL");
   for (int c = 0; c < v->d.channels; ++c)
     if (!v->tf_set[c]) return fail(SG_ERR_STATE, "a channel has no transfer function");
-  const size_t lds = (size_t)v->d.channels * (v->tf_n + 1) * 16;
-  if (lds > 65536) return fail(SG_ERR_UNSUPPORTED, "transfer tables exceed 64 KiB of LDS");
+  const size_t lds = (size_t)v->d.channels * (v->tf_n + 1) * 16 + 4 * kStageBytesPerWave;
+  if (lds > 65536) return fail(SG_ERR_UNSUPPORTED, "transfer tables exceed the LDS budget");
   DeviceGuard guard(v->d.device);
   if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
   hipStream_t s = (hipStream_t)hip_stream;
   sg_status st = commit(v, s);
   if (st != SG_OK) return st;
-  int tiles = 0;
+  int blocks = 0;
   st = prepare_views(v, n_views, views, params, out_rgba, out_depth,
-                     stats ? stats->samples : nullptr, s, &tiles);
+                     stats ? stats->samples : nullptr, s, &blocks);
   if (st != SG_OK) return st;
   const ViewDev* dv = reinterpret_cast<const ViewDev*>(v->view_dev);
   const bool timed = v->timing && !stats;
@@ -498,16 +874,22 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
     a.tf_bias[c] = (float)(-v->tf_lo[c] * sc);
   }
   for (int i = 0; i < 4; ++i) a.bg[i] = (float)params->background[i];
+  int key_levels = 0;
   for (int i = 0; i < 3; ++i) {
     a.dims[i] = v->d.dims[i];
     a.grid0[i] = v->grid[0][i];
+    while (((int64_t)v->B << key_levels) < v->d.dims[i]) ++key_levels;
   }
+  a.key_levels = key_levels;
   a.n_views = n_views;
-  a.total_tiles = tiles;
+  a.total_blocks = blocks;
+  a.grid = ((blocks + 7) / 8) * 8 * 16;
   a.tf_n = v->tf_n;
   a.B = v->B;
   a.S = v->S;
+  a.Sx = v->Sx;
   a.skip_empty = (params->flags & SG_SKIP_EMPTY) ? 1 : 0;
+  a.gather = (params->flags & SG_GATHER) ? 1 : 0;
   a.step = params->step_voxels;
   a.ert = (float)params->ert_alpha;
   a.depth_alpha = (float)params->depth_alpha;

@@ -37,6 +37,7 @@ struct Volume {
   int B = 0;         // brick core edge
   int logB = 0;
   int S = 0;         // stored edge B + 2
+  int Sx = 0;        // row stride in voxels (S rounded up to 4 bytes)
   int L = 0;         // levels
   int32_t ldims[kMaxLevels][3]{};
   int32_t grid[kMaxLevels][3]{};
@@ -110,8 +111,9 @@ struct ViewDev {
   double tl, tr, tb, tt;
   double K;     // (tau * theta)^2
   int32_t W, H;
-  int32_t tiles_x;     // 16x16 pixel tiles per row
-  int32_t tile_begin;  // first workgroup (tile) of this view
+  int32_t tiles_x, tiles_y;  // 16x16 pixel tiles
+  int32_t blocks_x;          // 4x4-tile blocks per row
+  int32_t block_begin;       // first block of this view
   int64_t cut_off;     // offset of this view's cut map
   float* rgba;
   float* depth;
@@ -124,7 +126,7 @@ sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
 sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         const sg_render_params* p, float* const* rgba,
                         float* const* depth, int32_t* const* nsamp,
-                        hipStream_t s, int* total_tiles);
+                        hipStream_t s, int* total_blocks);
 
 struct RenderArgs {
   const uint8_t* pool;
@@ -146,10 +148,13 @@ struct RenderArgs {
   int32_t dims[3];
   int32_t grid0[3];
   int32_t n_views;
-  int32_t total_tiles;
+  int32_t total_blocks;  // 4x4-tile blocks over all views
+  int32_t grid;          // workgroups launched
   int32_t tf_n;
-  int32_t B, S;
+  int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
+  int32_t key_levels;   // levels of the virtual octree over the volume
   int32_t skip_empty;
+  int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
   double step;
   float ert;
   float depth_alpha;

@@ -22,7 +22,7 @@ SG_ERR_DEVICE = -3
 SG_ERR_STATE = -4
 SG_ERR_UNSUPPORTED = -5
 SG_U8, SG_U16 = 1, 2
-SG_LOD, SG_SKIP_EMPTY = 1, 2
+SG_LOD, SG_SKIP_EMPTY, SG_GATHER = 1, 2, 4
 SG_ABI_VERSION = 1
 
 
@@ -157,6 +157,8 @@ def make_params(p=None) -> sg_render_params:
         flags |= SG_LOD
     if p.get("skip_empty", 1):
         flags |= SG_SKIP_EMPTY
+    if p.get("gather", 0):
+        flags |= SG_GATHER
     o.flags = int(p.get("flags", flags))
     o.reserved = int(p.get("reserved", 0))
     return o
