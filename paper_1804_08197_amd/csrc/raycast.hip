@@ -207,19 +207,33 @@ __device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const 
       }
       bool inside = true;
       while (inside) {
-        int ax = 0;
-        if (r.tnext[1] < r.tnext[ax]) ax = 1;
-        if (r.tnext[2] < r.tnext[ax]) ax = 2;
-        if (!(r.tnext[ax] < r.tf)) {
+        // next plane crossing; the axis is chosen with constant indices only
+        // so that the ray state stays in registers
+        const bool x_min = r.tnext[0] <= r.tnext[1] && r.tnext[0] <= r.tnext[2];
+        const bool y_min = !x_min && r.tnext[1] <= r.tnext[2];
+        const double tmin = x_min ? r.tnext[0] : (y_min ? r.tnext[1] : r.tnext[2]);
+        if (!(tmin < r.tf)) {
           r.alive = false;
           return;
         }
-        r.c[ax] += r.st[ax];
-        if (r.c[ax] < 0 || r.c[ax] >= a.grid0[ax]) {
+        bool out;
+        if (x_min) {
+          r.c[0] += r.st[0];
+          out = r.c[0] < 0 || r.c[0] >= a.grid0[0];
+          r.tnext[0] = (Bd * (double)(r.c[0] + (r.st[0] > 0 ? 1 : 0)) - r.e[0]) * r.inv[0];
+        } else if (y_min) {
+          r.c[1] += r.st[1];
+          out = r.c[1] < 0 || r.c[1] >= a.grid0[1];
+          r.tnext[1] = (Bd * (double)(r.c[1] + (r.st[1] > 0 ? 1 : 0)) - r.e[1]) * r.inv[1];
+        } else {
+          r.c[2] += r.st[2];
+          out = r.c[2] < 0 || r.c[2] >= a.grid0[2];
+          r.tnext[2] = (Bd * (double)(r.c[2] + (r.st[2] > 0 ? 1 : 0)) - r.e[2]) * r.inv[2];
+        }
+        if (out) {
           r.alive = false;
           return;
         }
-        r.tnext[ax] = (Bd * (double)(r.c[ax] + (r.st[ax] > 0 ? 1 : 0)) - r.e[ax]) * r.inv[ax];
         inside = r.c[0] >= clo[0] && r.c[0] <= chi[0] && r.c[1] >= clo[1] &&
                  r.c[1] <= chi[1] && r.c[2] >= clo[2] && r.c[2] <= chi[2];
       }
@@ -578,64 +592,71 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
     const bool bad = mine && !((float)sgn * my_dqm >= 0.25f * my_sum);
     const bool axis_ok = __ballot(bad) == 0;
 
-    // --- main-axis range of the node's stencils over the wave's rays
-    int nlo[3] = {1 << 20, 1 << 20, 1 << 20}, nhi[3] = {-1, -1, -1};
-    if (mine) stencil_bounds(r, r.k, r.n - 1, B, nlo, nhi);
-    const int mlo = uniform(wave_min_i(pick(nlo, m)));
-    const int mhi = uniform(wave_max_i(pick(nhi, m)));
-
-    // --- slabs along the main axis, in the rays' direction of travel
-    int j = sgn > 0 ? mlo : mhi;  // next owned stencil layer
+    // --- slabs along the main axis, in the rays' direction of travel. Each
+    // slab starts at the first stencil layer any ray still needs, owns D
+    // layers, and stages them plus the one the stencils reach into.
+    const int big = 1 << 20;
     int D = 8;
     while (true) {
       const bool more = mine && r.alive && r.k < r.n;
       if (__ballot(more) == 0) break;
-      const bool in_range = axis_ok && (sgn > 0 ? j <= mhi : j >= mlo);
-      // owned stencil layers [jl, jh]; staged region = owned layers + 1
-      int jl = j, jh = j;
+      if (!axis_ok) {
+        // rays of this node do not share a dominant direction: read the pool
+        if (more) {
+          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+            return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
+          };
+          while (r.k < r.n && sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
+          }
+        }
+        continue;
+      }
+      const int my_im = more ? min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B)
+                             : (sgn > 0 ? big : -big);
+      const int j = uniform(sgn > 0 ? wave_min_i(my_im) : wave_max_i(my_im));
+      // owned stencil layers [jl, jh]; each lane takes samples k..kb
+      int jl = j, jh = j, kb = r.k;
       int o[3] = {0, 0, 0}, wd[3] = {0, 0, 0};
       bool fits = false;
-      if (in_range) {
-        for (int tries = 0; tries < 8; ++tries) {
-          jl = sgn > 0 ? j : max(j - D + 1, mlo);
-          jh = sgn > 0 ? min(j + D - 1, mhi) : j;
-          int lo3[3] = {1 << 20, 1 << 20, 1 << 20}, hi3[3] = {-1, -1, -1};
-          if (more) {
-            // last sample of this lane still inside the slab (one extra
-            // sample is included; the bounds stay conservative)
-            const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
-            const float tlim = (edge - my_qm0) / my_dqm;
-            int kb = (int)ceilf(tlim / r.Df - 0.5f);
-            kb = min(max(kb, r.k), r.n - 1);
-            stencil_bounds(r, r.k, kb, B, lo3, hi3);
-          }
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            if (i == m) {
-              o[i] = jl;
-              wd[i] = jh - jl + 2;
-            } else {
-              const int l = uniform(wave_min_i(lo3[i]));
-              const int h = uniform(wave_max_i(hi3[i]));
-              o[i] = l <= h ? l : 0;
-              wd[i] = l <= h ? h - l + 2 : 0;
-            }
-          }
-          // dword-aligned rows: x origin rounded down, width rounded up
-          const int ox = (o[0] / align) * align;
-          wd[0] = ((o[0] + wd[0] - ox + align - 1) / align) * align;
-          o[0] = ox;
-          wd[0] = min(wd[0], Sx - o[0]);
-          wd[1] = min(wd[1], S - o[1]);
-          wd[2] = min(wd[2], S - o[2]);
-          const int vox = wd[0] * wd[1] * wd[2];
-          if (vox > 0 && vox <= cap) {
-            fits = true;
-            break;
-          }
-          if (D == 1) break;
-          D = max(1, D / 2);
+      for (int tries = 0; tries < 8; ++tries) {
+        jl = sgn > 0 ? j : max(j - D + 1, 0);
+        jh = sgn > 0 ? min(j + D - 1, B) : j;
+        int lo3[3] = {big, big, big}, hi3[3] = {-1, -1, -1};
+        if (more) {
+          // first sample at or past the slab's far edge (its bounds are
+          // included; samples past kb wait for the next slab)
+          const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
+          const float tlim = (edge - my_qm0) / my_dqm;
+          kb = (int)ceilf(tlim / r.Df - 0.5f);
+          kb = min(max(kb, r.k), r.n - 1);
+          stencil_bounds(r, r.k, kb, B, lo3, hi3);
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (i == m) {
+            o[i] = jl;
+            wd[i] = jh - jl + 2;
+          } else {
+            const int l = uniform(wave_min_i(lo3[i]));
+            const int h = uniform(wave_max_i(hi3[i]));
+            o[i] = l <= h ? l : 0;
+            wd[i] = l <= h ? h - l + 2 : 0;
+          }
+        }
+        // dword-aligned rows: x origin rounded down, width rounded up
+        const int ox = (o[0] / align) * align;
+        wd[0] = ((o[0] + wd[0] - ox + align - 1) / align) * align;
+        o[0] = ox;
+        wd[0] = min(wd[0], Sx - o[0]);
+        wd[1] = min(wd[1], S - o[1]);
+        wd[2] = min(wd[2], S - o[2]);
+        const int vox = wd[0] * wd[1] * wd[2];
+        if (vox > 0 && vox <= cap) {
+          fits = true;
+          break;
+        }
+        if (D == 1) break;
+        D = max(1, D / 2);
       }
       if (fits) {
         // --- stage the region of every channel: dword loads along rows
@@ -656,31 +677,35 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
           }
         }
         wave_sync();
-      }
-      // --- sample this slab; stencils outside the staged region (or all of
-      // them when nothing is staged) read the pool
-      if (more) {
-        const int sy_l = wd[0], sz_l = wd[0] * wd[1];
+        if (more) {
+          // every sample k..kb with its layer in [jl, jh] has its stencil in
+          // the staged region (positions are monotone along the segment)
+          const int sy_l = wd[0], sz_l = wd[0] * wd[1];
+          const int ox0 = o[0], oy0 = o[1], oz0 = o[2];
+          const T* st_base = stage;
+          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+            return trilinear(st_base + ch * cap + ((iz - oz0) * wd[1] + (iy - oy0)) * sy_l +
+                                 (ix - ox0),
+                             sy_l, sz_l, fx, fy, fz);
+          };
+          while (r.k <= kb) {
+            const int im = min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B);
+            if (im < jl || im > jh) break;
+            if (!sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) break;
+          }
+        }
+        wave_sync();
+      } else if (more) {
+        // the slab does not fit even one layer deep: read the pool for it
         auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-          const int lx = ix - o[0], ly = iy - o[1], lz = iz - o[2];
-          if (fits && lx >= 0 && lx <= wd[0] - 2 && ly >= 0 && ly <= wd[1] - 2 && lz >= 0 &&
-              lz <= wd[2] - 2)
-            return trilinear(stage + ch * cap + (lz * wd[1] + ly) * wd[0] + lx, sy_l, sz_l, fx,
-                             fy, fz);
           return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
         };
         while (r.k < r.n) {
-          if (in_range) {
-            const float qm = fmaf(sample_tau(r, r.k), my_dqm, my_qm0);
-            const int im = min(max((int)qm, 0), B);
-            if (sgn > 0 ? im > jh : im < jl) break;
-          }
+          const int im = min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B);
+          if (im < jl || im > jh) break;
           if (!sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) break;
         }
       }
-      wave_sync();
-      if (!in_range) continue;  // this pass read the pool for all that was left
-      j = sgn > 0 ? jh + 1 : jl - 1;
       if (fits) D = min(D * 2, 64);
     }
     // --- rays that finished this node move on to their next segment
