@@ -60,7 +60,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--render-only", action="store_true",
+                    help="profiling: only warm-up and timed renders (no counting pass, no "
+                         "oracle), one line of timings")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="profiling: run a plain device-to-device copy of this many bytes "
+                         "3 times (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (multi-GPU sort-last compositing is "
               "a design, not an implementation); run with --gpus 1", file=sys.stderr)
@@ -75,7 +84,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
     dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
-    want_cpu = args.cpu_seconds > 0
+    want_cpu = args.cpu_seconds > 0 and not args.render_only
 
     t0 = time.time()
     tv = TubeVolume().to_device()
@@ -101,6 +110,19 @@ def main():
     views = workload_views()
     outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
     npix = sum(v["width"] * v["height"] for v in views)
+
+    if args.render_only:
+        for _ in range(args.warmup):
+            sg.sg_render_views(h, views, PARAMS, outs)
+        torch.cuda.synchronize()
+        sg.sg_set_kernel_timing(h, True)
+        for _ in range(args.steps):
+            sg.sg_render_views(h, views, PARAMS, outs)
+        n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+        print(json.dumps({"renders": n_k, "raycast_kernel_ms": ray_ms / n_k,
+                          "cutmap_kernel_ms": cut_ms / n_k}), flush=True)
+        sg.sg_volume_destroy(h)
+        return
 
     # counting pass (untimed): samples and distinct 4^3 micro-blocks read
     stats = sg.sg_render_views_stats(h, views, PARAMS, outs)
@@ -154,6 +176,27 @@ def main():
         out["cpu_baseline"] = cpu_baseline(host, tf, views, samples, npix, args.cpu_seconds)
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of known size: its FETCH_SIZE /
+    WRITE_SIZE readings calibrate the byte counters for the roofline."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(3):
+        ev[0].record()
+        b.copy_(a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    print(json.dumps({"copy_bytes": n * 4, "ms": times,
+                      "GB_per_s_read_plus_write": 2 * n * 4 / (min(times) * 1e-3) / 1e9}),
+          flush=True)
 
 
 def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):

@@ -110,6 +110,10 @@ typedef struct {
   uint64_t total_samples;  /* out: samples evaluated over all views          */
   uint64_t microblocks;    /* out: distinct 4^3 voxel blocks (per channel and
                               level) read by the trilinear stencils          */
+  uint64_t node_visits;    /* out: (wave, node) pairs sampled (staged kernel)
+                              or (ray, node) segments sampled (gather)       */
+  uint64_t slabs;          /* out: LDS staging passes (staged kernel)        */
+  uint64_t staged_bytes;   /* out: bytes copied from the pool into LDS       */
 } sg_render_stats;
 
 /* Create a volume on desc->device: allocates the brick pool for every

@@ -35,6 +35,7 @@
 //  * gather: every lane reads its stencils straight from the pool.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -44,7 +45,7 @@ namespace sg {
 
 namespace {
 
-constexpr int kStageBytesPerWave = 8192;
+constexpr int kStageBytesDefault = 8192;  // per wave; tunable with SG_STAGE_BYTES
 
 // 1 - exp(-x) for x >= 0 with small absolute and relative error: a Taylor
 // polynomial below 1/16 (avoids the cancellation of 1 - exp(-x)), the
@@ -287,7 +288,7 @@ __device__ __forceinline__ float sample_tau(const Ray& r, int k) {
 // Shade and composite sample r.k; `fetch(ch, ix, iy, iz, fx, fy, fz)`
 // returns the trilinear value of channel ch at stored index (ix, iy, iz)
 // plus fraction. Returns false once the ray has terminated.
-template <int CH, bool STATS, typename F>
+template <int CH, bool STATS, bool CLAMP = true, typename F>
 __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
                                             bool want_depth, F&& fetch, int (*mb_key)[3]) {
   const int k = r.k;
@@ -296,11 +297,13 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
-  // stencil origin, kept inside the slot (it always is for samples inside
-  // the node box; the clamp only guards memory safety)
-  const int ix = min(max((int)qx, 0), a.B);
-  const int iy = min(max((int)qy, 0), a.B);
-  const int iz = min(max((int)qz, 0), a.B);
+  // stencil origin. Samples inside the node box always have it in
+  // [0, B]; reads from the pool clamp it anyway to guard memory safety
+  // (LDS reads need no guard: out-of-range LDS addresses cannot fault and
+  // the staged region is proven to contain every staged stencil).
+  const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
+  const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
+  const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
   const float fx = qx - (float)ix, fy = qy - (float)iy, fz = qz - (float)iz;
   float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
 #pragma unroll
@@ -470,6 +473,7 @@ __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
   while (r.alive) {
     const T* slot[CH];
     slot_ptrs<T, CH>(a, r.node, slot);
+    if (STATS) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
     auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
       return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
     };
@@ -512,6 +516,24 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Component-wise minimum of two 16-bit lanes packed in a word, over the wave.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t wave_min_u16x2(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
+    const u16x2 m = __builtin_elementwise_min(__builtin_bit_cast(u16x2, v),
+                                              __builtin_bit_cast(u16x2, w));
+    v = __builtin_bit_cast(uint32_t, m);
+  }
+  return v;
+}
+
+// Main-axis stencil layer of sample k (same arithmetic as the sample).
+__device__ __forceinline__ int sample_layer(const Ray& r, int k, float dqm, float qm0, int B) {
+  return min(max((int)fmaf(sample_tau(r, k), dqm, qm0), 0), B);
+}
+
 // Stencil corner bounds (per axis; the stencil also reads corner + 1) of
 // samples ka and kb of the lane's segment, hence of every sample between.
 __device__ __forceinline__ void stencil_bounds(const Ray& r, int ka, int kb, int B, int lo[3],
@@ -540,10 +562,10 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   load_tf<CH>(a, s_tf);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
-                                  w * kStageBytesPerWave);
+                                  w * a.stage_bytes);
   // voxels per channel, a multiple of 4 so every channel's region is
   // dword-aligned in LDS
-  constexpr int cap = (kStageBytesPerWave / (int)sizeof(T) / CH) & ~3;
+  const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~3;
   constexpr int align = 4 / (int)sizeof(T);                        // voxels per dword
 
   const TileLane tl = tile_lane(a);
@@ -576,6 +598,7 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
     const int node = uniform(__shfl(r.node, first));
     const T* slot[CH];
     slot_ptrs<T, CH>(a, node, slot);
+    if (STATS && lane == 0) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
 
     // --- dominant axis of the node's first ray; every ray of the node must
     // advance along it with the same sign, else everything reads the pool
@@ -592,16 +615,25 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
     const bool bad = mine && !((float)sgn * my_dqm >= 0.25f * my_sum);
     const bool axis_ok = __ballot(bad) == 0;
 
-    // --- slabs along the main axis, in the rays' direction of travel. Each
-    // slab starts at the first stencil layer any ray still needs, owns D
-    // layers, and stages them plus the one the stencils reach into.
-    const int big = 1 << 20;
+    // --- slabs along the main axis, in the rays' direction of travel. The
+    // first slab starts at the first stencil layer any ray needs; each owns
+    // D layers and stages them plus the one the stencils reach into. Every
+    // lane takes exactly its samples whose layer lies in the slab, so the
+    // next slab starts right after it.
+    const int big = 0xFFFF;
+    const bool more0 = mine && r.alive && r.k < r.n;
+    int j;
+    {
+      const int my_im = more0 ? sample_layer(r, r.k, my_dqm, my_qm0, B) : (sgn > 0 ? big : -1);
+      j = uniform(sgn > 0 ? wave_min_i(my_im) : wave_max_i(my_im));
+    }
     int D = 8;
     while (true) {
       const bool more = mine && r.alive && r.k < r.n;
       if (__ballot(more) == 0) break;
-      if (!axis_ok) {
-        // rays of this node do not share a dominant direction: read the pool
+      if (!axis_ok || (sgn > 0 ? j > B : j < 0)) {
+        // no shared dominant direction (or, defensively, nothing left in
+        // range): read the pool for all remaining samples
         if (more) {
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
             return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
@@ -611,34 +643,50 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         }
         continue;
       }
-      const int my_im = more ? min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B)
-                             : (sgn > 0 ? big : -big);
-      const int j = uniform(sgn > 0 ? wave_min_i(my_im) : wave_max_i(my_im));
-      // owned stencil layers [jl, jh]; each lane takes samples k..kb
-      int jl = j, jh = j, kb = r.k;
+      int jl = j, jh = j, kb = r.k - 1;
       int o[3] = {0, 0, 0}, wd[3] = {0, 0, 0};
       bool fits = false;
       for (int tries = 0; tries < 8; ++tries) {
         jl = sgn > 0 ? j : max(j - D + 1, 0);
         jh = sgn > 0 ? min(j + D - 1, B) : j;
-        int lo3[3] = {big, big, big}, hi3[3] = {-1, -1, -1};
+        // this lane's samples in the slab: k .. kb, found exactly
+        kb = r.k - 1;
+        uint32_t plo = 0xFFFFFFFFu, phi = 0xFFFFFFFFu;  // packed min(lo), min(~hi)
         if (more) {
-          // first sample at or past the slab's far edge (its bounds are
-          // included; samples past kb wait for the next slab)
           const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
           const float tlim = (edge - my_qm0) / my_dqm;
-          kb = (int)ceilf(tlim / r.Df - 0.5f);
-          kb = min(max(kb, r.k), r.n - 1);
-          stencil_bounds(r, r.k, kb, B, lo3, hi3);
+          kb = (int)ceilf(tlim / r.Df - 0.5f) - 1;
+          kb = min(max(kb, r.k - 1), r.n - 1);
+          while (kb + 1 < r.n) {
+            const int im = sample_layer(r, kb + 1, my_dqm, my_qm0, B);
+            if (im < jl || im > jh) break;
+            ++kb;
+          }
+          while (kb >= r.k) {
+            const int im = sample_layer(r, kb, my_dqm, my_qm0, B);
+            if (im >= jl && im <= jh) break;
+            --kb;
+          }
+          if (kb >= r.k) {
+            int lo3[3], hi3[3];
+            stencil_bounds(r, r.k, kb, B, lo3, hi3);
+            const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;  // cross axes
+            plo = (uint32_t)pick(lo3, ua) | ((uint32_t)pick(lo3, ub) << 16);
+            phi = (uint32_t)(0xFFFF - pick(hi3, ua)) | ((uint32_t)(0xFFFF - pick(hi3, ub)) << 16);
+          }
         }
+        const uint32_t rlo = (uint32_t)uniform((int)wave_min_u16x2(plo));
+        const uint32_t rhi = (uint32_t)uniform((int)wave_min_u16x2(phi));
+        const int la = (int)(rlo & 0xFFFF), lb = (int)(rlo >> 16);
+        const int ha = 0xFFFF - (int)(rhi & 0xFFFF), hb = 0xFFFF - (int)(rhi >> 16);
+        const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           if (i == m) {
             o[i] = jl;
             wd[i] = jh - jl + 2;
           } else {
-            const int l = uniform(wave_min_i(lo3[i]));
-            const int h = uniform(wave_max_i(hi3[i]));
+            const int l = i == ua ? la : lb, h = i == ua ? ha : hb;
             o[i] = l <= h ? l : 0;
             wd[i] = l <= h ? h - l + 2 : 0;
           }
@@ -651,62 +699,67 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         wd[1] = min(wd[1], S - o[1]);
         wd[2] = min(wd[2], S - o[2]);
         const int vox = wd[0] * wd[1] * wd[2];
-        if (vox > 0 && vox <= cap) {
-          fits = true;
+        if (vox <= cap) {
+          fits = vox > 0;
+          // next slab's depth from this slab's cross-section
+          const int area = max(1, vox / max(1, wd[m]));
+          D = min(max(cap / area - 1, 1), 64);
           break;
         }
         if (D == 1) break;
         D = max(1, D / 2);
       }
       if (fits) {
-        // --- stage the region of every channel: dword loads along rows
-        const int dpr = wd[0] / align;  // dwords per row
-        const int total = dpr * wd[1] * wd[2];
-        const float inv_dpr = 1.0f / (float)dpr, inv_wy = 1.0f / (float)wd[1];
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch) {
-          const uint32_t* src = reinterpret_cast<const uint32_t*>(slot[ch]);
-          uint32_t* dst = reinterpret_cast<uint32_t*>(stage + ch * cap);
-          for (int i = lane; i < total; i += 64) {
-            const int row = (int)(((float)i + 0.5f) * inv_dpr);
-            const int col = i - row * dpr;
+        // --- stage the region of every channel: each lane copies one dword
+        // of a row; lanes_per_row is a power of two >= dwords per row
+        const int dpr = wd[0] / align;
+        const int lpr_log = min(dpr <= 1 ? 0 : 32 - __clz(dpr - 1), 6);
+        const int lpr = 1 << lpr_log;
+        const int rows_per_pass = 64 >> lpr_log;
+        const int rows = wd[1] * wd[2];
+        const int my_col = lane & (lpr - 1);
+        const float inv_wy = 1.0f / (float)wd[1];
+        for (int row0 = 0; row0 < rows; row0 += rows_per_pass) {
+          const int row = row0 + (lane >> lpr_log);
+          if (row < rows) {
             const int rz = (int)(((float)row + 0.5f) * inv_wy);
             const int ry = row - rz * wd[1];
-            const int g = ((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0];
-            dst[i] = src[g / align + col];
+            const int g = (((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0]) / align;
+            for (int col = my_col; col < dpr; col += lpr) {
+#pragma unroll
+              for (int ch = 0; ch < CH; ++ch)
+                reinterpret_cast<uint32_t*>(stage + ch * cap)[row * dpr + col] =
+                    reinterpret_cast<const uint32_t*>(slot[ch])[g + col];
+            }
           }
         }
         wave_sync();
-        if (more) {
-          // every sample k..kb with its layer in [jl, jh] has its stencil in
-          // the staged region (positions are monotone along the segment)
+        if (STATS && lane == 0) {
+          atomicAdd((unsigned long long*)a.counters + 2, 1ull);
+          atomicAdd((unsigned long long*)a.counters + 3,
+                    (unsigned long long)(rows * dpr * 4 * CH));
+        }
+        if (kb >= r.k) {
           const int sy_l = wd[0], sz_l = wd[0] * wd[1];
-          const int ox0 = o[0], oy0 = o[1], oz0 = o[2];
-          const T* st_base = stage;
+          const int base_off = (o[2] * wd[1] + o[1]) * wd[0] + o[0];  // region origin
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            return trilinear(st_base + ch * cap + ((iz - oz0) * wd[1] + (iy - oy0)) * sy_l +
-                                 (ix - ox0),
-                             sy_l, sz_l, fx, fy, fz);
+            return trilinear(stage + ch * cap + ((iz * wd[1] + iy) * sy_l + ix - base_off), sy_l,
+                             sz_l, fx, fy, fz);
           };
-          while (r.k <= kb) {
-            const int im = min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B);
-            if (im < jl || im > jh) break;
-            if (!sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) break;
+          while (r.k <= kb &&
+                 sample_once<CH, STATS, false>(r, a, s_tf, want_depth, fetch, mb_key)) {
           }
         }
         wave_sync();
-      } else if (more) {
+      } else if (kb >= r.k) {
         // the slab does not fit even one layer deep: read the pool for it
         auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
           return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
         };
-        while (r.k < r.n) {
-          const int im = min(max((int)fmaf(sample_tau(r, r.k), my_dqm, my_qm0), 0), B);
-          if (im < jl || im > jh) break;
-          if (!sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) break;
+        while (r.k <= kb && sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
         }
       }
-      if (fits) D = min(D * 2, 64);
+      j = sgn > 0 ? jh + 1 : jl - 1;
     }
     // --- rays that finished this node move on to their next segment
     if (mine && r.alive) {
@@ -723,6 +776,14 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   }
 }
 
+template <typename K>
+sg_status allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return SG_OK;
+}
+
 template <typename T, int CH>
 sg_status launch_t(const RenderArgs& a, bool stats, bool gather, hipStream_t s) {
   const size_t tf_lds = (size_t)CH * (a.tf_n + 1) * sizeof(float4);
@@ -734,7 +795,10 @@ sg_status launch_t(const RenderArgs& a, bool stats, bool gather, hipStream_t s) 
       hipLaunchKernelGGL((raycast_gather<T, CH, false>), dim3(a.grid), dim3(256), tf_lds,
                          s, a);
   } else {
-    const size_t lds = tf_lds + 4 * kStageBytesPerWave;
+    const size_t lds = tf_lds + 4 * (size_t)a.stage_bytes;
+    sg_status st = stats ? allow_lds(raycast_staged<T, CH, true>, lds)
+                         : allow_lds(raycast_staged<T, CH, false>, lds);
+    if (st != SG_OK) return st;
     if (stats)
       hipLaunchKernelGGL((raycast_staged<T, CH, true>), dim3(a.grid), dim3(256), lds, s,
                          a);
@@ -861,8 +925,13 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   if (!views) return fail(SG_ERR_INVALID_ARG, "views is NULL");
   for (int c = 0; c < v->d.channels; ++c)
     if (!v->tf_set[c]) return fail(SG_ERR_STATE, "a channel has no transfer function");
-  const size_t lds = (size_t)v->d.channels * (v->tf_n + 1) * 16 + 4 * kStageBytesPerWave;
-  if (lds > 65536) return fail(SG_ERR_UNSUPPORTED, "transfer tables exceed the LDS budget");
+  int stage_bytes = kStageBytesDefault;
+  if (const char* e = std::getenv("SG_STAGE_BYTES")) {
+    const int x = std::atoi(e);
+    if (x >= 1024 && x <= 32768) stage_bytes = x & ~15;
+  }
+  const size_t lds = (size_t)v->d.channels * (v->tf_n + 1) * 16 + 4 * (size_t)stage_bytes;
+  if (lds > 160 * 1024) return fail(SG_ERR_UNSUPPORTED, "transfer tables exceed the LDS budget");
   DeviceGuard guard(v->d.device);
   if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -915,6 +984,7 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   a.Sx = v->Sx;
   a.skip_empty = (params->flags & SG_SKIP_EMPTY) ? 1 : 0;
   a.gather = (params->flags & SG_GATHER) ? 1 : 0;
+  a.stage_bytes = stage_bytes;
   a.step = params->step_voxels;
   a.ert = (float)params->ert_alpha;
   a.depth_alpha = (float)params->depth_alpha;
@@ -956,6 +1026,9 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
     for (uint32_t x : hb) pop += (uint64_t)__builtin_popcount(x);
     stats->total_samples = cnt[0];
     stats->microblocks = pop;
+    stats->node_visits = cnt[1];
+    stats->slabs = cnt[2];
+    stats->staged_bytes = cnt[3];
     return SG_OK;
   }
   st = launch_raycast(v, a, false, s);

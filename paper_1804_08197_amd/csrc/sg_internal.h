@@ -155,6 +155,7 @@ struct RenderArgs {
   int32_t key_levels;   // levels of the virtual octree over the volume
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
+  int32_t stage_bytes;  // LDS staging bytes per wave
   double step;
   float ert;
   float depth_alpha;

@@ -53,7 +53,8 @@ class sg_render_params(C.Structure):
 
 class sg_render_stats(C.Structure):
     _fields_ = [("samples", C.POINTER(C.c_void_p)), ("total_samples", C.c_uint64),
-                ("microblocks", C.c_uint64)]
+                ("microblocks", C.c_uint64), ("node_visits", C.c_uint64), ("slabs", C.c_uint64),
+                ("staged_bytes", C.c_uint64)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -254,7 +255,9 @@ def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samp
         st.samples = C.cast(smp, C.POINTER(C.c_void_p))
     _check(_lib.sg_render_views_stats(vol, n, varr, C.byref(p), rgba, dep, C.byref(st),
                                       _stream(stream)), "sg_render_views_stats")
-    return {"total_samples": int(st.total_samples), "microblocks": int(st.microblocks)}
+    return {"total_samples": int(st.total_samples), "microblocks": int(st.microblocks),
+            "node_visits": int(st.node_visits), "slabs": int(st.slabs),
+            "staged_bytes": int(st.staged_bytes)}
 
 
 def sg_get_lod_cut(vol, view, params, capacity=1 << 20, stream=None):
