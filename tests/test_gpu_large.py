@@ -1,0 +1,192 @@
+"""GPU parity at the full workload sizes, on sampled outputs.
+
+* tubes: 2048^3 uint16, 64^3 bricks, 6 levels, stereo 1440x1600 per eye, in
+  the launch configuration the benchmark times.
+* cells: 3 channels of 1024x1024x512 uint16, two resident timepoints, one
+  launch for all channels, stereo 1440x1600 per eye.
+* batched uneven views of the 128^3 blobs volume in one launch.
+
+The oracle renders random pixels plus a centre crop of each eye (with the
+early-termination bracket); cuts and empty flags are compared in full.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+from tests.helpers import ERT, TOL, as_f64_tf, bracket_error
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def sample_pixels(view, n, seed, crop=32):
+    rng = np.random.default_rng(seed)
+    W, H = view["width"], view["height"]
+    px = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], axis=1)
+    cx, cy = W // 2, H // 2
+    yy, xx = np.mgrid[cy - crop // 2:cy + crop // 2, cx - crop // 2:cx + crop // 2]
+    return np.concatenate([px, np.stack([xx.ravel(), yy.ravel()], 1)]).astype(np.int32)
+
+
+def compare_pixels(sc, view, params, got_rgba, got_ns, pix, cut, emp):
+    refs = [sc.render(view, dict(params, ert=e), pixels=pix, cut=cut, empty=emp, count=True)
+            for e in (params["ert"], params["ert"] - 1e-5, params["ert"] + 1e-5)]
+    g = got_rgba[pix[:, 1], pix[:, 0]].astype(np.float64)
+    best, needed = bracket_error(g, refs)
+    assert best.max() <= TOL, "max abs err %g" % best.max()
+    ns = got_ns[pix[:, 1], pix[:, 0]]
+    ok = np.zeros(len(pix), bool)
+    for r in refs:
+        ok |= ns == r["nsamp"]
+    assert (~ok).sum() <= max(2, 2e-3 * len(pix)), "sample counts differ at %d px" % (~ok).sum()
+    return float(best.max()), needed, int(np.sum([r["total_samples"] for r in refs[:1]]))
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU (no CPU fallback exists)"
+    return torch
+
+
+def render_with_counts(h, views, params):
+    import torch
+
+    from paper_1804_08197_amd import sg
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    sg.sg_render_views(h, views, params, outs)  # the timed entry point
+    torch.cuda.synchronize()
+    rgba = [o.cpu().numpy() for o in outs]
+    smp = [torch.zeros(v["height"], v["width"], dtype=torch.int32, device="cuda") for v in views]
+    outs2 = [torch.empty_like(o) for o in outs]
+    st = sg.sg_render_views_stats(h, views, params, outs2, None, smp)
+    for a, b in zip(outs, outs2):  # the instrumented render draws the same image
+        assert torch.equal(a, b)
+    return rgba, [s.cpu().numpy() for s in smp], st
+
+
+def test_tubes_2048_stereo_parity(gpu):
+    import bench
+    import oracle
+    from gen.large import TubeVolume, upload_generated
+    from paper_1804_08197_amd import sg
+    log("tubes: generating 2048^3 on the GPU")
+    tv = TubeVolume().to_device()
+    dims, B, L = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
+    h = sg.sg_volume_create(dims, dtype=sg.SG_U16, brick=B, levels=L)
+    try:
+        host = np.empty(dims[::-1], dtype=np.uint16)
+        upload_generated(h, tv, B, host_out=host, slab_bricks=2)
+        tf = gen.tf_hot()
+        sg.sg_set_transfer_function(h, 0, tf, *gen.TUBE_DOMAIN)
+        views = bench.workload_views()
+        params = dict(bench.PARAMS)
+        log("tubes: rendering")
+        rgba, ns, st = render_with_counts(h, views, params)
+        log("tubes: oracle pyramid")
+        sc = oracle.Scene([host], B, L, [as_f64_tf(tf)], [gen.TUBE_DOMAIN])
+        for i, v in enumerate(views):
+            ids, emp_gpu = sg.sg_get_lod_cut(h, v, params)
+            cut = sc.cut(v, params)
+            assert np.array_equal(ids, cut), "eye %d: LOD cut differs" % i
+            emp = sc.empty(cut)
+            assert np.array_equal(emp_gpu, emp), "eye %d: empty flags differ" % i
+            pix = sample_pixels(v, 2500, 100 + i)
+            err, needed, _ = compare_pixels(sc, v, params, rgba[i], ns[i], pix, cut, emp)
+            log("tubes eye %d: cut %d nodes, %d px, max err %.3g, bracket used %d" % (
+                i, len(cut), len(pix), err, needed))
+        # the frame is non-trivial
+        assert st["total_samples"] > 1e8
+        assert max(float(r[..., 3].max()) for r in rgba) > 0.99
+    finally:
+        sg.sg_volume_destroy(h)
+
+
+def cell_views():
+    c = np.array([512.0, 512.0, 256.0])
+    head = c + 1280.0 * gen.unit((0.3, -1.0, 0.45))
+    t = math.tan(math.radians(50.0))
+    return gen.stereo(head, c, 65.536, 1440, 1600, t, 0.9 * t)
+
+
+def test_cells_multichannel_timepoints_parity(gpu):
+    import oracle
+    from gen.large import CellVolume, upload_generated
+    from paper_1804_08197_amd import sg
+    dims, B, L = gen.CELLS_DIMS, gen.CELLS_BRICK, gen.CELLS_LEVELS
+    tps = (0, 50)
+    h = sg.sg_volume_create(dims, channels=3, timepoints=len(tps), dtype=sg.SG_U16, brick=B,
+                            levels=L)
+    try:
+        hosts = {}
+        for ti, t in enumerate(tps):
+            for c in range(3):
+                log("cells: generating channel %d timepoint %d" % (c, t))
+                cv = CellVolume(c, t).to_device()
+                host = np.empty(dims[::-1], dtype=np.uint16)
+                upload_generated(h, cv, B, channel=c, timepoint=ti, host_out=host, slab_bricks=4)
+                hosts[(ti, c)] = host
+        tfs = [gen.tf_tint(tint) for tint in gen.CELL_TINTS]
+        for c in range(3):
+            sg.sg_set_transfer_function(h, c, tfs[c], *gen.CELL_DOMAIN)
+        views = cell_views()
+        for ti in range(len(tps)):
+            params = {"ert": ERT, "tau": 1.0, "timepoint": ti}
+            rgba, ns, st = render_with_counts(h, views, params)
+            sc = oracle.Scene([hosts[(ti, c)] for c in range(3)], B, L,
+                              [as_f64_tf(t) for t in tfs], [gen.CELL_DOMAIN] * 3)
+            for i, v in enumerate(views):
+                ids, emp_gpu = sg.sg_get_lod_cut(h, v, params)
+                cut = sc.cut(v, params)
+                assert np.array_equal(ids, cut)
+                emp = sc.empty(cut)
+                assert np.array_equal(emp_gpu, emp)
+                pix = sample_pixels(v, 1500, 200 + 10 * ti + i)
+                err, needed, _ = compare_pixels(sc, v, params, rgba[i], ns[i], pix, cut, emp)
+                log("cells t=%d eye %d: cut %d (%d empty), max err %.3g, bracket %d, samples %d"
+                    % (tps[ti], i, len(cut), int(emp.sum()), err, needed, st["total_samples"]))
+            assert st["total_samples"] > 1e7
+    finally:
+        sg.sg_volume_destroy(h)
+
+
+def test_batched_uneven_views_parity(gpu):
+    import torch
+
+    import oracle
+    from paper_1804_08197_amd import sg, upload_volume
+    vol = gen.blobs128()
+    tf = gen.tf_identity()
+    h = sg.sg_volume_create((128, 128, 128), dtype=sg.SG_U8, brick=32, levels=3)
+    try:
+        upload_volume(h, vol, 32)
+        sg.sg_set_transfer_function(h, 0, tf, 0, 255)
+        views = gen.orbit_views((64, 64, 64), (1.5 * 221.7, 4 * 221.7), 16, 1004, (512, 2048),
+                                (512, 2048), tan_top=math.tan(math.radians(30)))
+        params = {"ert": ERT, "tau": 1.0}
+        outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+        sg.sg_render_views(h, views, params, outs)
+        torch.cuda.synchronize()
+        sc = oracle.Scene([vol], 32, 3, [as_f64_tf(tf)], [(0, 255)])
+        for i, v in enumerate(views):
+            got = outs[i].cpu().numpy()
+            pix = sample_pixels(v, 400, 300 + i, crop=16)
+            refs = [sc.render(v, dict(params, ert=e), pixels=pix)
+                    for e in (ERT, ERT - 1e-5, ERT + 1e-5)]
+            best, _ = bracket_error(got[pix[:, 1], pix[:, 0]].astype(np.float64), refs)
+            assert best.max() <= TOL, "view %d err %g" % (i, best.max())
+            if i < 4:  # a view rendered alone equals its slice of the batch
+                single = torch.empty_like(outs[i])
+                sg.sg_render_views(h, [v], params, [single])
+                assert torch.equal(single, outs[i])
+        log("batched: %d views, %.1f Mpx" % (len(views),
+                                              sum(v["width"] * v["height"] for v in views) / 1e6))
+    finally:
+        sg.sg_volume_destroy(h)
