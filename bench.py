@@ -149,13 +149,14 @@ def main():
     log("%.3f ms/step (wall), raycast kernel %.3f ms, cutmap %.4f ms" % (
         ms_step, ray_ms / n_k, cut_ms / n_k))
 
+    traffic = measured_traffic()
     bytes_alg = mb * 64 * 2 + npix * 16
     flops_alg = samples * FLOP_PER_SAMPLE
     hbm = {"bound": "hbm", "achieved": bytes_alg / ray_avg_s / 1e9, "peak": HBM_PEAK / 1e9,
-           "unit": "GB/s", "traffic": None}
+           "unit": "GB/s", "traffic": traffic}
     hbm["frac"] = hbm["achieved"] / hbm["peak"]
     alu = {"bound": "alu", "achieved": flops_alg / ray_avg_s / 1e12, "peak": FP32_PEAK / 1e12,
-           "unit": "TFLOP/s", "traffic": None}
+           "unit": "TFLOP/s", "traffic": traffic}
     alu["frac"] = alu["achieved"] / alu["peak"]
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
 
@@ -176,6 +177,23 @@ def main():
         out["cpu_baseline"] = cpu_baseline(host, tf, views, samples, npix, args.cpu_seconds)
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per ray-casting dispatch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (calibrated against a copy of known
+    size), or None once the kernel source has changed since they were
+    taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "raycast_tubes2048_stereo.traffic.json")
+    try:
+        rec = json.load(open(rec_path))
+        src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["traffic_bytes_per_dispatch"]
 
 
 def copy_calibration(nbytes):
@@ -212,7 +230,7 @@ def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
     rng = np.random.default_rng(2024)
     threads = oracle.max_threads()
     done_pix, done_samp, spent, n = 0, 0, 0.0, 64
-    while spent < seconds:
+    while spent < seconds and done_pix < npix // 4:
         for i, v in enumerate(views):
             pix = np.stack([rng.integers(0, v["width"], n), rng.integers(0, v["height"], n)], 1)
             t = time.perf_counter()
@@ -224,9 +242,9 @@ def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
     frame_s = spent / done_pix * npix
     return {"value": 1.0 / frame_s, "unit": "stereo frames/s", "cores": threads,
             "kind": "oracle", "samples_per_s": done_samp / spent,
-            "sample": "%d random pixels of both eyes (%.2f%% of the frame), %.1fs of CPU wall "
-                      "time, extrapolated by pixel count" % (done_pix, 100.0 * done_pix / npix,
-                                                             spent)}
+            "sample": "%d uniformly random pixels of both eyes (%.1f%% of the frame's pixel "
+                      "count), %.1fs of wall time on %d threads, extrapolated to the frame by "
+                      "pixel count" % (done_pix, 100.0 * done_pix / npix, spent, threads)}
 
 
 if __name__ == "__main__":
