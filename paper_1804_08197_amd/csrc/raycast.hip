@@ -710,34 +710,35 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         D = max(1, D / 2);
       }
       if (fits) {
-        // --- stage the region of every channel: each lane copies one dword
-        // of a row; lanes_per_row is a power of two >= dwords per row
+        // --- stage the region of every channel: pass p moves dwords
+        // p .. p+63 of the region (row-major, dpr dwords per row) straight
+        // from the pool into LDS (global_load_lds: lane i writes LDS dword
+        // base + i), 64 dwords per pass
         const int dpr = wd[0] / align;
-        const int lpr_log = min(dpr <= 1 ? 0 : 32 - __clz(dpr - 1), 6);
-        const int lpr = 1 << lpr_log;
-        const int rows_per_pass = 64 >> lpr_log;
         const int rows = wd[1] * wd[2];
-        const int my_col = lane & (lpr - 1);
-        const float inv_wy = 1.0f / (float)wd[1];
-        for (int row0 = 0; row0 < rows; row0 += rows_per_pass) {
-          const int row = row0 + (lane >> lpr_log);
-          if (row < rows) {
+        const int total = dpr * rows;
+        const float inv_dpr = 1.0f / (float)dpr, inv_wy = 1.0f / (float)wd[1];
+        for (int p0 = 0; p0 < total; p0 += 64) {
+          const int i = p0 + lane;
+          if (i < total) {
+            const int row = (int)(((float)i + 0.5f) * inv_dpr);
+            const int col = i - row * dpr;
             const int rz = (int)(((float)row + 0.5f) * inv_wy);
             const int ry = row - rz * wd[1];
-            const int g = (((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0]) / align;
-            for (int col = my_col; col < dpr; col += lpr) {
+            const int g = (((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0]) / align + col;
 #pragma unroll
-              for (int ch = 0; ch < CH; ++ch)
-                reinterpret_cast<uint32_t*>(stage + ch * cap)[row * dpr + col] =
-                    reinterpret_cast<const uint32_t*>(slot[ch])[g + col];
-            }
+            for (int ch = 0; ch < CH; ++ch)
+              __builtin_amdgcn_global_load_lds(
+                  reinterpret_cast<const uint32_t*>(slot[ch]) + g,
+                  reinterpret_cast<uint32_t*>(stage + ch * cap) + p0, 4, 0, 0);
           }
         }
+        __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads have landed
         wave_sync();
         if (STATS && lane == 0) {
           atomicAdd((unsigned long long*)a.counters + 2, 1ull);
           atomicAdd((unsigned long long*)a.counters + 3,
-                    (unsigned long long)(rows * dpr * 4 * CH));
+                    (unsigned long long)(total * 4 * CH));
         }
         if (kb >= r.k) {
           const int sy_l = wd[0], sz_l = wd[0] * wd[1];
