@@ -67,7 +67,7 @@ __global__ void cutmap_kernel(CutGeom g, const ViewDev* views, int n_views,
     int L = g.lod ? g.top : g.bias;
     for (; L > g.bias; --L)
       if (node_suits(g, e, V.K, L, cx >> L, cy >> L, cz >> L)) break;
-    int32_t bx = cx >> L, by = cy >> L, bz = cz >> L;
+    const int32_t bx = cx >> L, by = cy >> L, bz = cz >> L;
     cutmap[V.cut_off + cell] =
         (int32_t)(g.node_off[L] + ((int64_t)bz * g.grid[L][1] + by) * g.grid[L][0] + bx);
   }

@@ -48,10 +48,10 @@ namespace {
 constexpr int kStageBytesDefault = 8192;  // per wave; tunable with SG_STAGE_BYTES
 
 // 1 - exp(-x) for x >= 0 with small absolute and relative error: a Taylor
-// polynomial below 1/16 (avoids the cancellation of 1 - exp(-x)), the
-// exponential above.
+// polynomial below 1/16 (avoids the cancellation of 1 - exp(-x); truncation
+// error below x^5/120 < 1e-8), the exponential above.
 __device__ __forceinline__ float one_minus_exp_neg(float x) {
-  float p = x * (1.0f - x * (0.5f - x * (0.16666667f - x * (0.041666668f - x * 0.0083333333f))));
+  float p = x * (1.0f - x * (0.5f - x * (0.16666667f - x * 0.041666668f)));
   float q = 1.0f - __expf(-x);
   return x < 0.0625f ? p : q;
 }
@@ -117,6 +117,7 @@ struct Ray {
   uint64_t key;
   // sampling state of the current segment (brick-local FP32 frame)
   float q0[3], dq[3], Df, s_last;
+  float tau, tau_last;  // ray parameter of sample k and of the last sample
   int n, k;
   // accumulation
   float Cr, Cg, Cb, A, depth;
@@ -166,27 +167,6 @@ __device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const Vie
       r.tnext[i] = INFINITY;
     }
   }
-}
-
-// Front-to-back key of node (L, b) for eye e: the octree path from a virtual
-// root covering the volume, each child index flipped so that the child on
-// the eye's side of each splitting plane comes first. Sorting nodes of a
-// cut by this key orders them front to back for every ray from e.
-__device__ __forceinline__ uint64_t visibility_key(const RenderArgs& a, const double e[3], int L,
-                                                   const int b[3]) {
-  uint64_t key = 0;
-  for (int l = a.key_levels - 1; l >= L; --l) {
-    uint32_t code = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int cb = b[i] >> (l - L);
-      const double split = (double)((int64_t)a.B << l) * (double)(2 * (cb >> 1) + 1);
-      const uint32_t f = (uint32_t)(cb & 1) ^ (uint32_t)(e[i] >= split);
-      code = (code << 1) | f;
-    }
-    key = (key << 3) | code;
-  }
-  return key << (3 * L);
 }
 
 // Advance the ray to its next segment that needs samples: a cut node whose
@@ -243,10 +223,12 @@ __device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const 
     r.node = cutmap[((int64_t)r.c[2] * a.grid0[1] + r.c[1]) * a.grid0[0] + r.c[0]];
     const NodeInfo ni = a.info[r.node];
     r.L = ni.level;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r.b[i] = ni.b[i];
+    if (a.skip_empty && a.empty[r.node]) continue;  // before any box arithmetic
     double blo[3], bhi[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      r.b[i] = ni.b[i];
       const int64_t wdt = (int64_t)a.B << r.L;
       const int64_t l0 = wdt * ni.b[i];
       int64_t h0 = wdt * (ni.b[i] + 1);
@@ -258,7 +240,8 @@ __device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const 
     box_interval(r.e, r.d, blo, bhi, t0, t1);
     if (t0 < r.tn) t0 = r.tn;
     if (t1 > r.tf) t1 = r.tf;
-    if (!(t0 < t1) || (a.skip_empty && a.empty[r.node])) continue;
+    if (!(t0 < t1)) continue;
+    r.key = visibility_key(a.key_levels, a.B, r.e, r.L, r.b);
     r.t0 = t0;
     r.t1 = t1;
     // sampling frame: stored index of the brick, FP32 from an FP64 origin
@@ -268,6 +251,8 @@ __device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const 
     r.k = 0;
     r.s_last = (float)(len - (double)(r.n - 1) * Dd);
     r.Df = (float)Dd;
+    r.tau = 0.5f * r.Df;  // (k + 1/2) D is exact: D is a power of two
+    r.tau_last = fmaf((float)(r.n - 1), r.Df, 0.5f * r.s_last);
     const double inv_s = 1.0 / (double)((int64_t)1 << r.L);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -292,8 +277,9 @@ template <int CH, bool STATS, bool CLAMP = true, typename F>
 __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
                                             bool want_depth, F&& fetch, int (*mb_key)[3]) {
   const int k = r.k;
-  const float s = k == r.n - 1 ? r.s_last : r.Df;
-  const float tau = fmaf((float)k, r.Df, 0.5f * s);
+  const bool last = k == r.n - 1;
+  const float s = last ? r.s_last : r.Df;
+  const float tau = last ? r.tau_last : r.tau;  // = sample_tau(r, k)
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
@@ -304,7 +290,9 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
   const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
   const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
-  const float fx = qx - (float)ix, fy = qy - (float)iy, fz = qz - (float)iz;
+  // q >= 0, so fract(q) = q - floor(q) = q - ix (exact)
+  const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
+              fz = __builtin_amdgcn_fractf(qz);
   float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) {
@@ -375,6 +363,7 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   r.Cb = fmaf(wgt, eb, r.Cb);
   r.A += wgt;
   r.k = k + 1;
+  r.tau += r.Df;
   if (STATS) ++r.nsamp;
   if (want_depth && r.depth == INFINITY && r.A >= a.depth_alpha)
     r.depth = (float)(r.t0 + (double)tau);
@@ -584,7 +573,6 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   if (tl.in_image) {
     ray_setup(r, a, V, tl.px, tl.py);
     if (r.alive) next_segment(r, a, V, true);
-    if (r.alive) r.key = visibility_key(a, r.e, r.L, r.b);
   }
   const int B = a.B, S = a.S, Sx = a.Sx;
 
@@ -743,9 +731,10 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         if (kb >= r.k) {
           const int sy_l = wd[0], sz_l = wd[0] * wd[1];
           const int base_off = (o[2] * wd[1] + o[1]) * wd[0] + o[0];  // region origin
+          const int wy = wd[1];
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            return trilinear(stage + ch * cap + ((iz * wd[1] + iy) * sy_l + ix - base_off), sy_l,
-                             sz_l, fx, fy, fz);
+            const int idx = __mul24(__mul24(iz, wy) + iy, sy_l) + ix - base_off;
+            return trilinear(stage + ch * cap + idx, sy_l, sz_l, fx, fy, fz);
           };
           while (r.k <= kb &&
                  sample_once<CH, STATS, false>(r, a, s_tf, want_depth, fetch, mb_key)) {
@@ -763,10 +752,7 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
       j = sgn > 0 ? jh + 1 : jl - 1;
     }
     // --- rays that finished this node move on to their next segment
-    if (mine && r.alive) {
-      next_segment(r, a, V, false);
-      if (r.alive) r.key = visibility_key(a, r.e, r.L, r.b);
-    }
+    if (mine && r.alive) next_segment(r, a, V, false);
   }
   if (tl.in_image) {
     write_pixel(r, a, V, tl.px, tl.py);

@@ -31,6 +31,28 @@ struct NodeInfo {
   int32_t b[3];
 };
 
+// Front-to-back key of node (L, b) for eye e: the octree path from a virtual
+// root of key_levels levels over the volume, each child index flipped so
+// that the child on the eye's side of each splitting plane comes first.
+// Nodes of a cut sorted by this key are in front-to-back order for every ray
+// from e (the order in which Sec 5.2 renders its blocks).
+__device__ __forceinline__ uint64_t visibility_key(int key_levels, int B, const double e[3],
+                                                   int L, const int b[3]) {
+  uint64_t key = 0;
+  for (int l = key_levels - 1; l >= L; --l) {
+    uint32_t code = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int cb = b[i] >> (l - L);
+      const double split = (double)((int64_t)B << l) * (double)(2 * (cb >> 1) + 1);
+      const uint32_t f = (uint32_t)(cb & 1) ^ (uint32_t)(e[i] >= split);
+      code = (code << 1) | f;
+    }
+    key = (key << 3) | code;
+  }
+  return key << (3 * L);
+}
+
 struct Volume {
   sg_volume_desc d{};
   int bpv = 0;       // bytes per voxel
@@ -59,7 +81,7 @@ struct Volume {
   std::vector<uint8_t> pending;  // [T][C] needs apron + range refresh
   bool empty_dirty = true;
   // per-render scratch
-  int32_t* cutmap = nullptr;  // [views][cells0]
+  int32_t* cutmap = nullptr;  // [views][cells0] cut node of each level-0 cell
   int64_t cutmap_cap = 0;
   uint8_t* view_dev = nullptr;
   int64_t view_cap = 0;
@@ -136,6 +158,7 @@ struct RenderArgs {
   const NodeInfo* info;
   const float* tf;
   const int32_t* cutmap;
+  int32_t key_levels;   // levels of the virtual octree over the volume
   const ViewDev* views;
   uint32_t* mb_bits;
   uint64_t* counters;
@@ -152,7 +175,6 @@ struct RenderArgs {
   int32_t grid;          // workgroups launched
   int32_t tf_n;
   int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
-  int32_t key_levels;   // levels of the virtual octree over the volume
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
   int32_t stage_bytes;  // LDS staging bytes per wave
