@@ -485,37 +485,61 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wave reductions without LDS traffic: within each 16-lane row, DPP lane
+// swaps (quad_perm xor 1, quad_perm xor 2, half-row mirror, row mirror)
+// leave the row's result in every lane; the four row results are then read
+// as scalars. Every lane of the wave must be active at the call (a swap
+// from an inactive lane returns the lane's own value).
+template <int C>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, C, 0xF, 0xF, false);
+}
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_i(int v, Op op) {
+  v = op(v, dpp_i<0xB1>(v));
+  v = op(v, dpp_i<0x4E>(v));
+  v = op(v, dpp_i<0x141>(v));
+  v = op(v, dpp_i<0x140>(v));
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return op(op(a, b), op(c, d));
+}
 __device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
+  return wave_reduce_i(v, [](int x, int y) { return min(x, y); });
 }
 __device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
+  return wave_reduce_i(v, [](int x, int y) { return max(x, y); });
+}
+template <int C>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int lo = dpp_i<C>((int)(uint32_t)v), hi = dpp_i<C>((int)(uint32_t)(v >> 32));
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t rl_u64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t w = (uint64_t)__shfl_xor((unsigned long long)v, o);
-    v = w < v ? w : v;
-  }
-  return v;
+  v = umin64(v, dpp_u64<0xB1>(v));
+  v = umin64(v, dpp_u64<0x4E>(v));
+  v = umin64(v, dpp_u64<0x141>(v));
+  v = umin64(v, dpp_u64<0x140>(v));
+  return umin64(umin64(rl_u64(v, 0), rl_u64(v, 16)), umin64(rl_u64(v, 32), rl_u64(v, 48)));
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
 
 // Component-wise minimum of two 16-bit lanes packed in a word, over the wave.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t wave_min_u16x2(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t w = (uint32_t)__shfl_xor((int)v, o);
-    const u16x2 m = __builtin_elementwise_min(__builtin_bit_cast(u16x2, v),
-                                              __builtin_bit_cast(u16x2, w));
-    v = __builtin_bit_cast(uint32_t, m);
-  }
-  return v;
+  return (uint32_t)wave_reduce_i((int)v, [](int x, int y) {
+    return (int)__builtin_bit_cast(uint32_t, __builtin_elementwise_min(
+        __builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, y)));
+  });
 }
 
 // Main-axis stencil layer of sample k (same arithmetic as the sample).
@@ -583,15 +607,15 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
     const bool mine = r.alive && r.key == K;
     const uint64_t mask = __ballot(mine);
     const int first = __ffsll((unsigned long long)mask) - 1;
-    const int node = uniform(__shfl(r.node, first));
+    const int node = uniform(__builtin_amdgcn_readlane(r.node, first));
     const T* slot[CH];
     slot_ptrs<T, CH>(a, node, slot);
     if (STATS && lane == 0) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
 
     // --- dominant axis of the node's first ray; every ray of the node must
     // advance along it with the same sign, else everything reads the pool
-    const float d0[3] = {__shfl(r.dq[0], first), __shfl(r.dq[1], first),
-                         __shfl(r.dq[2], first)};
+    const float d0[3] = {lane_f(r.dq[0], first), lane_f(r.dq[1], first),
+                         lane_f(r.dq[2], first)};
     int m = 0;
     if (fabsf(d0[1]) > fabsf(d0[0])) m = 1;
     if (fabsf(d0[2]) > fabsf(pick(d0, m))) m = 2;
@@ -695,7 +719,9 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
           break;
         }
         if (D == 1) break;
-        D = max(1, D / 2);
+        // the cross-section of a thinner slab is no larger (its samples are
+        // a subset), so this depth fits unless even one layer does not
+        D = max(1, min(D - 1, cap / max(1, vox / max(1, wd[m])) - 1));
       }
       if (fits) {
         // --- stage the region of every channel: pass p moves dwords
