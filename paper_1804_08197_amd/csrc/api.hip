@@ -127,7 +127,7 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   v->logB = 0;
   while ((1 << v->logB) < v->B) ++v->logB;
   v->S = v->B + 2;
-  v->Sx = ((v->S * v->bpv + 3) / 4) * 4 / v->bpv;
+  v->Sx = ((v->S * v->bpv + kRowAlignBytes - 1) / kRowAlignBytes) * kRowAlignBytes / v->bpv;
   v->L = d->levels;
   int64_t nodes = 0;
   for (int L = 0; L < v->L; ++L) {

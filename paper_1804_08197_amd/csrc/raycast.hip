@@ -576,10 +576,11 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
                                   w * a.stage_bytes);
-  // voxels per channel, a multiple of 4 so every channel's region is
-  // dword-aligned in LDS
-  const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~3;
-  constexpr int align = 4 / (int)sizeof(T);                        // voxels per dword
+  // staging moves chunks of kRowAlignBytes (pool rows are aligned to
+  // them); the capacity per channel is a whole number of chunks so every
+  // channel's region starts chunk-aligned in LDS
+  constexpr int align = kRowAlignBytes / (int)sizeof(T);  // voxels per chunk
+  const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~(align - 1);
 
   const TileLane tl = tile_lane(a);
   if (!tl.tile_valid) return;  // uniform over the workgroup; no barrier follows
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
             wd[i] = l <= h ? h - l + 2 : 0;
           }
         }
-        // dword-aligned rows: x origin rounded down, width rounded up
+        // chunk-aligned rows: x origin rounded down, width rounded up
         const int ox = (o[0] / align) * align;
         wd[0] = ((o[0] + wd[0] - ox + align - 1) / align) * align;
         o[0] = ox;
@@ -724,27 +725,34 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         D = max(1, min(D - 1, cap / max(1, vox / max(1, wd[m])) - 1));
       }
       if (fits) {
-        // --- stage the region of every channel: pass p moves dwords
-        // p .. p+63 of the region (row-major, dpr dwords per row) straight
-        // from the pool into LDS (global_load_lds: lane i writes LDS dword
-        // base + i), 64 dwords per pass
-        const int dpr = wd[0] / align;
+        // --- stage the region of every channel: pass p moves chunks
+        // p .. p+63 of the region (row-major, cpr chunks per row) straight
+        // from the pool into LDS (global_load_lds: lane i writes chunk i
+        // after the LDS base of the pass)
+        // Chunk i of the region is row = i / cpr, plane rz = row / wd[1];
+        // in the slot it sits at base + i + row * skip_row + rz * skip_plane
+        // (the chunks a row or a plane of the slot has beyond the region's).
+        // The quotients come from (x + 1/2) * (1/d) in FP32: its relative
+        // error is below 2^-23 and (x + 1/2) / d lies at least 1/(2d) from
+        // an integer, so the floor is exact for every x < 2^22.
+        const int cpr = wd[0] / align, P = Sx / align;
         const int rows = wd[1] * wd[2];
-        const int total = dpr * rows;
-        const float inv_dpr = 1.0f / (float)dpr, inv_wy = 1.0f / (float)wd[1];
+        const int total = cpr * rows;
+        const float inv_cpr = 1.0f / (float)cpr, inv_wy = 1.0f / (float)wd[1];
+        const int base = ((o[2] * S + o[1]) * Sx + o[0]) / align;
+        const int skip_row = P - cpr, skip_plane = (S - wd[1]) * P;
         for (int p0 = 0; p0 < total; p0 += 64) {
           const int i = p0 + lane;
           if (i < total) {
-            const int row = (int)(((float)i + 0.5f) * inv_dpr);
-            const int col = i - row * dpr;
+            const int row = (int)(((float)i + 0.5f) * inv_cpr);
             const int rz = (int)(((float)row + 0.5f) * inv_wy);
-            const int ry = row - rz * wd[1];
-            const int g = (((o[2] + rz) * S + (o[1] + ry)) * Sx + o[0]) / align + col;
+            const int g = base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane);
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch)
               __builtin_amdgcn_global_load_lds(
-                  reinterpret_cast<const uint32_t*>(slot[ch]) + g,
-                  reinterpret_cast<uint32_t*>(stage + ch * cap) + p0, 4, 0, 0);
+                  reinterpret_cast<const uint8_t*>(slot[ch]) + (size_t)g * kRowAlignBytes,
+                  reinterpret_cast<uint8_t*>(stage + ch * cap) + p0 * kRowAlignBytes,
+                  kRowAlignBytes, 0, 0);
           }
         }
         __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads have landed
@@ -752,7 +760,7 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
         if (STATS && lane == 0) {
           atomicAdd((unsigned long long*)a.counters + 2, 1ull);
           atomicAdd((unsigned long long*)a.counters + 3,
-                    (unsigned long long)(total * 4 * CH));
+                    (unsigned long long)(total * kRowAlignBytes * CH));
         }
         if (kb >= r.k) {
           const int sy_l = wd[0], sz_l = wd[0] * wd[1];

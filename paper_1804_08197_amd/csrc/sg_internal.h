@@ -14,6 +14,11 @@ namespace sg {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxChannels = 4;
 constexpr int kMaxTfEntries = 1024;
+// Pool rows (x runs of a brick slot) start on 4-byte boundaries, the unit
+// in which the ray caster copies brick regions into LDS. (16-byte units move
+// four times the bytes per load but widen every staged row to 8 u16 voxels,
+// which costs more slabs than it saves loads on the tube workload.)
+constexpr int kRowAlignBytes = 4;
 
 // Error plumbing: every entry point funnels through these.
 sg_status fail(sg_status s, const std::string& msg);
@@ -59,7 +64,7 @@ struct Volume {
   int B = 0;         // brick core edge
   int logB = 0;
   int S = 0;         // stored edge B + 2
-  int Sx = 0;        // row stride in voxels (S rounded up to 4 bytes)
+  int Sx = 0;        // row stride in voxels (S rounded up to kRowAlignBytes)
   int L = 0;         // levels
   int32_t ldims[kMaxLevels][3]{};
   int32_t grid[kMaxLevels][3]{};
