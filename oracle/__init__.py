@@ -37,7 +37,7 @@ class View(C.Structure):
     _fields_ = [("cam_to_world", C.c_double * 16),
                 ("tan_left", C.c_double), ("tan_right", C.c_double),
                 ("tan_bottom", C.c_double), ("tan_top", C.c_double),
-                ("width", C.c_int32), ("height", C.c_int32)]
+                ("width", C.c_int32), ("height", C.c_int32), ("lens", C.c_double * 4)]
 
 
 class _Scene(C.Structure):
@@ -51,7 +51,12 @@ class Params(C.Structure):
     _fields_ = [("step", C.c_double), ("ert", C.c_double), ("tau", C.c_double),
                 ("bg", C.c_double * 4), ("depth_alpha", C.c_double),
                 ("bias", C.c_int32), ("lod_on", C.c_int32), ("skip_empty", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("model", C.c_int32), ("n_planes", C.c_int32),
+                ("planes", (C.c_double * 4) * 4), ("roi_on", C.c_int32), ("pad2", C.c_int32),
+                ("roi", C.c_double * 6)]
+
+
+MODELS = {"ea": 0, "eo": 1, "mip": 2}
 
 
 _lib = None
@@ -90,9 +95,14 @@ def lib():
         L.sgo_lod_cut.restype = C.c_int64
         L.sgo_nodes_empty.argtypes = [C.POINTER(_Scene), C.POINTER(C.c_uint64), C.c_int64,
                                       C.POINTER(C.c_uint8)]
+        L.sgo_nodes_empty_model.argtypes = [C.POINTER(_Scene), C.c_int32,
+                                            C.POINTER(C.c_uint64), C.c_int64,
+                                            C.POINTER(C.c_uint8)]
+        L.sgo_clip.argtypes = [C.POINTER(Params), d3, d3, C.c_double, d3, d3]
+        L.sgo_clip.restype = C.c_int32
         L.sgo_render.argtypes = [C.POINTER(_Scene), C.POINTER(View), C.POINTER(Params),
                                  C.POINTER(C.c_uint64), C.c_int64, C.POINTER(C.c_uint8),
-                                 C.c_int64, i3, d3, d3, C.POINTER(C.c_int64),
+                                 C.c_int64, i3, d3, d3, d3, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_void_p), C.c_int32]
         L.sgo_render.restype = C.c_int64
         L.sgo_max_threads.restype = C.c_int32
@@ -129,6 +139,9 @@ def make_view(v: dict) -> View:
     out.tan_left, out.tan_right = float(v["tan_left"]), float(v["tan_right"])
     out.tan_bottom, out.tan_top = float(v["tan_bottom"]), float(v["tan_top"])
     out.width, out.height = int(v["width"]), int(v["height"])
+    lens = v.get("lens") or (0.0, 0.0, 0.0, 0.0)
+    for i in range(4):
+        out.lens[i] = float(lens[i])
     return out
 
 
@@ -144,6 +157,20 @@ def make_params(p: dict) -> Params:
     out.bias = int(p.get("bias", 0))
     out.lod_on = int(p.get("lod", 1))
     out.skip_empty = int(p.get("skip_empty", 1))
+    model = p.get("model", 0)
+    out.model = MODELS[model] if isinstance(model, str) else int(model)
+    planes = p.get("planes") or ()
+    if len(planes) > 4:
+        raise ValueError("at most 4 cut planes")
+    out.n_planes = len(planes)
+    for j, q in enumerate(planes):
+        for i in range(4):
+            out.planes[j][i] = float(q[i])
+    roi = p.get("roi")
+    out.roi_on = int(roi is not None)
+    if roi is not None:
+        for i in range(6):
+            out.roi[i] = float(np.asarray(roi, dtype=np.float64).reshape(6)[i])
     return out
 
 
@@ -242,6 +269,14 @@ def entry_exit(dims0, e, d):
     return bool(hit), t0.value, t1.value
 
 
+def clip(params: dict, e, d, t0, t1, limit=np.inf):
+    """O16: the ray interval [t0, t1] clipped by cut planes, ROI and a ray limit."""
+    p = make_params(params)
+    a, b = C.c_double(t0), C.c_double(t1)
+    ok = lib().sgo_clip(C.byref(p), _d3(e), _d3(d), float(limit), C.byref(a), C.byref(b))
+    return bool(ok), a.value, b.value
+
+
 def lod_k(view: dict, tau: float) -> float:
     v = make_view(view)
     return float(lib().sgo_lod_k(C.byref(v), float(tau)))
@@ -309,16 +344,22 @@ class Scene:
         p = make_params(params)
         return lod_cut(self.dims, self.brick, self.levels, view, p.tau, p.bias, bool(p.lod_on))
 
-    def empty(self, ids: np.ndarray) -> np.ndarray:
+    def empty(self, ids: np.ndarray, model=0) -> np.ndarray:
+        """Skip flags of the cut nodes for an optical model (O9, O17)."""
         ids = np.ascontiguousarray(ids, dtype=np.uint64)
         out = np.zeros(max(len(ids), 1), dtype=np.uint8)
         s = self._struct()
-        lib().sgo_nodes_empty(C.byref(s), _ptr(ids, C.c_uint64), len(ids), _ptr(out, C.c_uint8))
+        m = MODELS[model] if isinstance(model, str) else int(model)
+        lib().sgo_nodes_empty_model(C.byref(s), m, _ptr(ids, C.c_uint64), len(ids),
+                                    _ptr(out, C.c_uint8))
         return out[:len(ids)].astype(bool)
 
     def render(self, view: dict, params: dict, pixels=None, depth=False, count=False,
-               microblocks=False, threads=0, cut=None, empty=None):
+               microblocks=False, threads=0, cut=None, empty=None, limit=None):
         """Render a view (all pixels, or the (x, y) rows of ``pixels``).
+
+        ``limit`` is an optional (H, W) array of ray limits (distance along
+        the ray of opaque geometry, +inf where there is none).
 
         Returns a dict with ``rgba`` (H, W, 4) or (npix, 4) float64 and,
         on request, ``depth``, ``nsamp``, per-level micro-block bitmaps and
@@ -330,7 +371,10 @@ class Scene:
             cut = self.cut(view, params)
         cut = np.ascontiguousarray(cut, dtype=np.uint64)
         if empty is None:
-            empty = self.empty(cut) if p.skip_empty else np.zeros(len(cut), bool)
+            empty = self.empty(cut, p.model) if p.skip_empty else np.zeros(len(cut), bool)
+        lim = None
+        if limit is not None:
+            lim = np.ascontiguousarray(limit, dtype=np.float64).reshape(v.height, v.width)
         emp = np.ascontiguousarray(empty, dtype=np.uint8)
         if pixels is None:
             npix = v.width * v.height
@@ -356,7 +400,7 @@ class Scene:
         total = lib().sgo_render(
             C.byref(s), C.byref(v), C.byref(p), _ptr(cut, C.c_uint64), len(cut),
             _ptr(emp, C.c_uint8) if len(emp) else None, npix, pix_ptr,
-            _ptr(rgba, C.c_double), _ptr(dep, C.c_double) if dep is not None else None,
+            _ptr(lim, C.c_double) if lim is not None else None, _ptr(rgba, C.c_double), _ptr(dep, C.c_double) if dep is not None else None,
             _ptr(ns, C.c_int64) if ns is not None else None,
             C.cast(mb_ptr, C.POINTER(C.c_void_p)) if mb_ptr is not None else None, int(threads))
         if total < 0:

@@ -24,6 +24,12 @@
  *   O11 integration       Sec 5.1 emission-absorption integral, early termination
  *   O12 channels          Sec 8 (multi-channel intensity)
  *   O13 output            Sec 5.6 (alpha channel, pre-multiplied colour)
+ *   O15 wrapped-space rays Sec 5.3 (rays spread uniformly over the wrapped image)
+ *   O16 ray clipping      Sec 6 (cut plane tool, ROI tool), Sec 5.6 (rays
+ *                         ending at the depth of opaque geometry)
+ *   O17 optical models    Sec 5.1 (emission-only, maximum intensity
+ *                         projection, emission-absorption), Sec 5.6 (zero
+ *                         alpha of the emission-only image)
  *
  * Parity status: every function here is pinned by a CPU test (closed forms,
  * library special cases, brute force); the full-image renders of the
@@ -47,6 +53,8 @@ typedef struct {
   double cam_to_world[16]; /* row-major 4x4; eye = (m[3], m[7], m[11]) */
   double tan_left, tan_right, tan_bottom, tan_top;
   int32_t width, height;
+  double lens[4]; /* k1, k2, cx, cy of the wrapped-space ray map (O15);
+                     k1 = k2 = 0: rectilinear */
 } sgo_view;
 
 typedef struct {
@@ -72,6 +80,14 @@ typedef struct {
   int32_t lod_on;     /* 1: screen-space LOD cut; 0: every node at level bias */
   int32_t skip_empty; /* 1: drop segments of empty nodes */
   int32_t pad;
+  int32_t model;      /* O17: 0 emission-absorption, 1 emission-only,
+                         2 maximum intensity projection */
+  int32_t n_planes;   /* O16: cut planes in use, 0..4 */
+  double planes[4][4]; /* plane j keeps the points p with
+                          (n . p) + w <= 0, stored (nx, ny, nz, w) */
+  int32_t roi_on;     /* O16: 1 = keep only the box roi */
+  int32_t pad2;
+  double roi[6];      /* lo x, y, z, hi x, y, z (level-0 units) */
 } sgo_params;
 
 /* ------------------------------------------------------------ small utils */
@@ -275,6 +291,17 @@ void sgo_ray(const sgo_view *v, int32_t x, int32_t y, double e[3],
   double sy = v->tan_top -
               (((double)y + 0.5) / (double)v->height) *
                   (v->tan_top - v->tan_bottom);
+  /* O15, wrapped space (Sec 5.3): the pixels of the wrapped image are
+   * spread uniformly and each is moved, radially about the lens centre
+   * (cx, cy), to the tangent the lens shows it at: with r^2 the squared
+   * distance from the centre, the offset grows by 1 + k1 r^2 + k2 r^4. */
+  if (v->lens[0] != 0.0 || v->lens[1] != 0.0) {
+    double dx = sx - v->lens[2], dy = sy - v->lens[3];
+    double r2 = dx * dx + dy * dy;
+    double f = 1.0 + r2 * (v->lens[0] + r2 * v->lens[1]);
+    sx = v->lens[2] + dx * f;
+    sy = v->lens[3] + dy * f;
+  }
   double w[3];
   for (int a = 0; a < 3; ++a) {
     e[a] = m[4 * a + 3];
@@ -325,6 +352,47 @@ int32_t sgo_entry_exit(const int32_t dims0[3], const double e[3],
   *tn = a;
   *tf = b;
   return a < b;
+}
+
+/* O16 clipping: narrow the ray interval [*t0, *t1] to the part that is
+ * kept by every cut plane (Sec 6: the volume is seen as if the portion above
+ * the plane were missing), inside the region of interest (Sec 6: data
+ * outside the ROI cut out of the rendering) and in front of the opaque
+ * geometry at distance `limit` along the ray (Sec 5.6: the ray is
+ * terminated at the distance read from the depth texture; +inf = none).
+ * Plane j keeps e + t d where a + t b <= 0 with a = (n . e) + w and
+ * b = n . d: t <= -a/b for b > 0, t >= -a/b for b < 0, every t or none for
+ * b = 0. Returns 1 if the interval stays non-empty. */
+int32_t sgo_clip(const sgo_params *pr, const double e[3], const double d[3],
+                 double limit, double *t0, double *t1) {
+  double a0 = *t0, a1 = *t1;
+  for (int32_t j = 0; j < pr->n_planes; ++j) {
+    const double *q = pr->planes[j];
+    double a = ((q[0] * e[0] + q[1] * e[1]) + q[2] * e[2]) + q[3];
+    double b = (q[0] * d[0] + q[1] * d[1]) + q[2] * d[2];
+    if (b > 0.0) {
+      double t = -a / b;
+      if (t < a1) a1 = t;
+    } else if (b < 0.0) {
+      double t = -a / b;
+      if (t > a0) a0 = t;
+    } else if (a > 0.0) {
+      a1 = a0;
+    }
+  }
+  if (pr->roi_on) {
+    double r0, r1;
+    if (!sgo_box_interval(e, d, pr->roi, pr->roi + 3, &r0, &r1)) {
+      a1 = a0;
+    } else {
+      if (r0 > a0) a0 = r0;
+      if (r1 < a1) a1 = r1;
+    }
+  }
+  if (limit < a1) a1 = limit;
+  *t0 = a0;
+  *t1 = a1;
+  return a0 < a1;
 }
 
 /* ------------------------------------------------------------------ O8 */
@@ -455,16 +523,48 @@ int32_t sgo_node_empty(const sgo_scene *sc, int32_t L, const int32_t b[3]) {
   return 1;
 }
 
-/* Empty flags for a list of node identifiers. */
-void sgo_nodes_empty(const sgo_scene *sc, const uint64_t *ids, int64_t n,
-                     uint8_t *out) {
+/* The emission-only counterpart (O17): a node is dark when, for every
+ * channel, the emitted colour (r, g, b) of every table entry a sample in it
+ * can touch (the same guarded entry range as above) is exactly zero; its
+ * samples then add nothing to the emission integral. */
+int32_t sgo_node_dark(const sgo_scene *sc, int32_t L, const int32_t b[3]) {
+  int32_t n[3];
+  sgo_level_dims(sc->dims, L, n);
+  int32_t N = sc->tf_n;
+  for (int32_t ch = 0; ch < sc->channels; ++ch) {
+    double mn, mx;
+    sgo_brick_minmax(sc->lvl[ch * sc->levels + L], sc->bpv, n, sc->brick, b,
+                     &mn, &mx);
+    double lo = sc->tf_lo[ch], hi = sc->tf_hi[ch];
+    int64_t klo = clampi((int64_t)floor(tf_index(mn, lo, hi, N)) - 1, 0, N - 1);
+    int64_t khi = clampi((int64_t)floor(tf_index(mx, lo, hi, N)) + 2, 0, N - 1);
+    const double *t = sc->tf + (size_t)ch * N * 4;
+    for (int64_t k = klo; k <= khi; ++k)
+      if (t[4 * k] != 0.0 || t[4 * k + 1] != 0.0 || t[4 * k + 2] != 0.0)
+        return 0;
+  }
+  return 1;
+}
+
+/* Empty flags for a list of node identifiers: model 0 (emission-absorption)
+ * tests the extinction (sgo_node_empty), model 1 (emission-only) the
+ * emitted colour (sgo_node_dark); model 2 (maximum intensity) has none. */
+void sgo_nodes_empty_model(const sgo_scene *sc, int32_t model,
+                           const uint64_t *ids, int64_t n, uint8_t *out) {
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t i = 0; i < n; ++i) {
     int32_t q[4];
     sgo_node_decode(ids[i], q);
     int32_t b[3] = {q[1], q[2], q[3]};
-    out[i] = (uint8_t)sgo_node_empty(sc, q[0], b);
+    out[i] = model == 0 ? (uint8_t)sgo_node_empty(sc, q[0], b)
+             : model == 1 ? (uint8_t)sgo_node_dark(sc, q[0], b)
+                          : 0;
   }
+}
+
+void sgo_nodes_empty(const sgo_scene *sc, const uint64_t *ids, int64_t n,
+                     uint8_t *out) {
+  sgo_nodes_empty_model(sc, 0, ids, n, out);
 }
 
 /* ---------------------------------------------------------- O10 .. O13 */
@@ -472,6 +572,7 @@ void sgo_nodes_empty(const sgo_scene *sc, const uint64_t *ids, int64_t n,
 typedef struct {
   double t0, t1;
   uint64_t id;
+  int64_t idx; /* position in the cut */
   int32_t L;
 } seg_t;
 
@@ -535,9 +636,36 @@ static void shade(const sgo_scene *sc, int32_t L, const double p[3],
   for (int c = 0; c < 3; ++c) rgb[c] = r > 0.0 ? acc[c] / r : 0.0;
 }
 
+/* Per-channel trilinear values of one sample (O5), marking micro-blocks. */
+static void sample_channels(const sgo_scene *sc, int32_t L, const double p[3],
+                            double v[SGO_MAX_CHANNELS], uint8_t *const *mb) {
+  int32_t n[3];
+  sgo_level_dims(sc->dims, L, n);
+  for (int32_t ch = 0; ch < sc->channels; ++ch) {
+    v[ch] = sgo_sample(sc->lvl[ch * sc->levels + L], sc->bpv, n, L, p);
+    if (mb) mark_microblocks(mb[ch * sc->levels + L], n, L, p);
+  }
+}
+
+/* Emitted colour of channel values v: the sum over channels of tau_c(v_c)
+ * (Sec 5.1 emission c = tau[f]; Sec 8, channel intensities add). */
+static void emission(const sgo_scene *sc, const double v[SGO_MAX_CHANNELS],
+                     double rgb[3]) {
+  rgb[0] = rgb[1] = rgb[2] = 0.0;
+  for (int32_t ch = 0; ch < sc->channels; ++ch) {
+    double o[4];
+    sgo_tf_eval(sc->tf + (size_t)ch * sc->tf_n * 4, sc->tf_n, sc->tf_lo[ch],
+                sc->tf_hi[ch], v[ch], o);
+    for (int c = 0; c < 3; ++c) rgb[c] += o[c];
+  }
+}
+
 /* Render the given pixels of one view.
- *   cut, cut_empty : the view's LOD cut (sgo_lod_cut) and empty flags
+ *   cut, cut_empty : the view's LOD cut (sgo_lod_cut) and the flags of the
+ *                    params' model (sgo_nodes_empty_model)
  *   pix            : npix (x, y) pairs, or NULL for every pixel row-major
+ *   limit          : NULL, or the view's width*height ray limits (O16),
+ *                    row-major, +inf where there is no geometry
  *   rgba           : npix * 4 premultiplied colour and alpha (O13)
  *   depth          : npix, t of the first sample with alpha >= depth_alpha,
  *                    +inf if none (optional)
@@ -545,24 +673,49 @@ static void shade(const sgo_scene *sc, int32_t L, const double p[3],
  *   mb             : [channel * levels + L] micro-block bitmaps (optional)
  * Returns the total number of samples, or -1 on bad arguments.
  *
- * Emission-absorption (Sec 5.1): along each segment of level L the step is
- * D = step 2^L level-0 units, n = ceil(len / D) samples at the midpoints of
- * the sub-intervals (the last one partial). Sample k of length s_k adds
- *   a = 1 - exp(-rho s_k);  C += (1 - A) a rgb;  A += (1 - A) a,
- * and the ray stops once A >= ert (early termination, Sec 5.1). Segments
- * are the cut nodes crossed by the ray, in order of entry (front to back,
- * Sec 5.2). */
+ * Segments are the cut nodes crossed by the ray inside its clipped interval
+ * (O7, O16), in order of entry (front to back, Sec 5.2). Along a segment of
+ * level L the step is D = step 2^L level-0 units, n = ceil(len / D) samples
+ * at the midpoints of the sub-intervals (the last one partial, length s_k).
+ * Per sample (O17):
+ *   emission-absorption (Sec 5.1): a = 1 - exp(-rho s_k); C += (1 - A) a rgb;
+ *     A += (1 - A) a; the ray stops once A >= ert (early termination);
+ *   emission-only (Sec 5.1): C += rgb s_k with rgb the summed emission;
+ *     A stays 0 (Sec 5.6), no termination;
+ *   maximum intensity: m_c = max(m_c, v_c) per channel; at the end C is the
+ *     summed emission of the maxima, A = 0; with skip_empty a node whose
+ *     stored maximum cannot raise any m_c is passed over (exact: trilinear
+ *     values never exceed the stencil's largest voxel). */
 int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
                    const uint64_t *cut, int64_t ncut, const uint8_t *cut_empty,
-                   int64_t npix, const int32_t *pix, double *rgba,
-                   double *depth, int64_t *nsamp, uint8_t *const *mb,
-                   int32_t nthreads) {
+                   int64_t npix, const int32_t *pix, const double *limit,
+                   double *rgba, double *depth, int64_t *nsamp,
+                   uint8_t *const *mb, int32_t nthreads) {
   if (!sc || !v || !pr || !rgba || sc->channels < 1 ||
-      sc->channels > SGO_MAX_CHANNELS || v->width < 1 || v->height < 1)
+      sc->channels > SGO_MAX_CHANNELS || v->width < 1 || v->height < 1 ||
+      pr->model < 0 || pr->model > 2 || pr->n_planes < 0 || pr->n_planes > 4)
     return -1;
   int64_t total = (int64_t)v->width * v->height;
   if (!pix) npix = total;
   int64_t sum = 0;
+  const int32_t model = pr->model, nch = sc->channels;
+  /* stored maxima of the cut nodes, per channel (maximum intensity skip) */
+  double *nmax = NULL;
+  if (model == 2 && pr->skip_empty && ncut > 0) {
+    nmax = (double *)malloc(sizeof(double) * (size_t)(ncut * nch));
+    for (int64_t i = 0; i < ncut; ++i) {
+      int32_t q[4], n[3];
+      sgo_node_decode(cut[i], q);
+      int32_t b[3] = {q[1], q[2], q[3]};
+      sgo_level_dims(sc->dims, q[0], n);
+      for (int32_t ch = 0; ch < nch; ++ch) {
+        double mn, mx;
+        sgo_brick_minmax(sc->lvl[ch * sc->levels + q[0]], sc->bpv, n, sc->brick,
+                         b, &mn, &mx);
+        nmax[i * nch + ch] = mx;
+      }
+    }
+  }
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -578,17 +731,29 @@ int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
       double e[3], d[3], tn, tf;
       sgo_ray(v, x, y, e, d);
       double C[3] = {0.0, 0.0, 0.0}, A = 0.0, dep = INFINITY;
+      double vmax[SGO_MAX_CHANNELS];
+      int sampled = 0;
+      for (int32_t ch = 0; ch < nch; ++ch) vmax[ch] = -INFINITY;
       int64_t ns = 0;
-      if (sgo_entry_exit(sc->dims, e, d, &tn, &tf)) {
+      double lim = limit ? limit[(int64_t)y * v->width + x] : INFINITY;
+      if (sgo_entry_exit(sc->dims, e, d, &tn, &tf) &&
+          sgo_clip(pr, e, d, lim, &tn, &tf)) {
         int64_t m = 0;
         for (int64_t i = 0; i < ncut; ++i) {
-          if (pr->skip_empty && cut_empty && cut_empty[i]) continue;
+          if (pr->skip_empty && model != 2 && cut_empty && cut_empty[i]) continue;
           int32_t q[4];
           sgo_node_decode(cut[i], q);
           int32_t b[3] = {q[1], q[2], q[3]};
           double lo[3], hi[3], a0, a1;
           sgo_node_box(sc->dims, sc->brick, q[0], b, lo, hi);
           if (!sgo_box_interval(e, d, lo, hi, &a0, &a1)) continue;
+          /* a ray that runs inside a face shared by two nodes belongs to
+           * the node on the face's upper side (voxel cells are half-open,
+           * O1); the volume's own upper faces stay closed */
+          int on_face = 0;
+          for (int a = 0; a < 3; ++a)
+            if (d[a] == 0.0 && e[a] == hi[a] && hi[a] < (double)sc->dims[a]) on_face = 1;
+          if (on_face) continue;
           if (a0 < tn) a0 = tn;
           if (a1 > tf) a1 = tf;
           if (!(a0 < a1)) continue;
@@ -596,11 +761,18 @@ int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
           segs[m].t1 = a1;
           segs[m].id = cut[i];
           segs[m].L = q[0];
+          segs[m].idx = i;
           ++m;
         }
         qsort(segs, (size_t)m, sizeof(seg_t), cmp_seg);
         int done = 0;
         for (int64_t i = 0; i < m && !done; ++i) {
+          if (nmax && sampled) {
+            int raise = 0;
+            for (int32_t ch = 0; ch < nch; ++ch)
+              if (nmax[segs[i].idx * nch + ch] > vmax[ch]) raise = 1;
+            if (!raise) continue;
+          }
           int32_t L = segs[i].L;
           double D = pr->step * ldexp(1.0, L);
           double len = segs[i].t1 - segs[i].t0;
@@ -609,21 +781,36 @@ int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
             double s = D < len - (double)k * D ? D : len - (double)k * D;
             double t = segs[i].t0 + (double)k * D + s / 2.0;
             double pt[3] = {e[0] + t * d[0], e[1] + t * d[1], e[2] + t * d[2]};
-            double rgb[3], rho;
-            shade(sc, L, pt, rgb, &rho, mb);
             ++ns;
-            double a = 1.0 - exp(-rho * s);
-            double w = (1.0 - A) * a;
-            for (int c = 0; c < 3; ++c) C[c] += w * rgb[c];
-            A += w;
-            if (depth && dep == INFINITY && A >= pr->depth_alpha) dep = t;
-            if (A >= pr->ert) {
-              done = 1;
-              break;
+            if (model == 0) {
+              double rgb[3], rho;
+              shade(sc, L, pt, rgb, &rho, mb);
+              double a = 1.0 - exp(-rho * s);
+              double w = (1.0 - A) * a;
+              for (int c = 0; c < 3; ++c) C[c] += w * rgb[c];
+              A += w;
+              if (depth && dep == INFINITY && A >= pr->depth_alpha) dep = t;
+              if (A >= pr->ert) {
+                done = 1;
+                break;
+              }
+            } else {
+              double val[SGO_MAX_CHANNELS];
+              sample_channels(sc, L, pt, val, mb);
+              if (model == 1) {
+                double rgb[3];
+                emission(sc, val, rgb);
+                for (int c = 0; c < 3; ++c) C[c] += rgb[c] * s;
+              } else {
+                for (int32_t ch = 0; ch < nch; ++ch)
+                  if (val[ch] > vmax[ch]) vmax[ch] = val[ch];
+                sampled = 1;
+              }
             }
           }
         }
       }
+      if (model == 2 && sampled) emission(sc, vmax, C);
       double *o = rgba + 4 * p;
       for (int c = 0; c < 3; ++c) o[c] = C[c] + (1.0 - A) * pr->bg[c];
       o[3] = A + (1.0 - A) * pr->bg[3];
@@ -633,6 +820,7 @@ int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
     }
     free(segs);
   }
+  free(nmax);
   return sum;
 }
 
