@@ -7,7 +7,9 @@
  * blocks in a multi-resolution pyramid, top-down LOD selection, front-to-back
  * block order), Sec 5.3 (one render per eye of a head-mounted display),
  * Sec 4.1/4.2 (volume chunks uploaded to a GPU-resident cache), Sec 5.6
- * (pre-multiplied alpha output) and Sec 8 (transfer functions, multichannel).
+ * (pre-multiplied alpha output; rays ending at the depth of opaque geometry),
+ * Sec 6 (cut plane and region-of-interest tools) and Sec 8 (transfer
+ * functions, multichannel).
  *
  * Conventions shared by every call
  *  - World space is level-0 voxel units: voxel (i, j, k) covers
@@ -36,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 1
+#define SG_ABI_VERSION 2
 
 typedef enum {
   SG_OK = 0,
@@ -49,11 +51,26 @@ typedef enum {
 
 typedef enum { SG_U8 = 1, SG_U16 = 2 } sg_dtype;
 
+/* Optical models (Sec 5.1), sg_render_params.model. */
+typedef enum {
+  SG_MODEL_EMISSION_ABSORPTION = 0, /* C += (1-A) a rgb, A += (1-A) a with
+                                       a = 1 - exp(-rho s); early termination */
+  SG_MODEL_EMISSION_ONLY = 1,       /* C += rgb s, rgb the summed emission of
+                                       the channels; A stays 0 (Sec 5.6)     */
+  SG_MODEL_MAX_INTENSITY = 2        /* per channel the largest trilinear value
+                                       along the ray; C = summed emission of
+                                       those maxima, A = 0                   */
+} sg_model;
+
 /* sg_render_params.flags */
 enum {
   SG_LOD = 1u << 0,        /* screen-space LOD cut (Sec 5.2); without it every
                               node is rendered at level lod_bias             */
-  SG_SKIP_EMPTY = 1u << 1, /* skip nodes whose opacity is zero everywhere     */
+  SG_SKIP_EMPTY = 1u << 1, /* skip nodes that cannot contribute: zero opacity
+                              (emission-absorption), zero emission
+                              (emission-only), a stored maximum no larger than
+                              the ray's running maxima (maximum intensity);
+                              the image is the same either way              */
   SG_GATHER = 1u << 2      /* tuning/testing: trilinear stencils read the brick
                               pool directly instead of LDS-staged brick tiles;
                               the image is bit-identical either way          */
@@ -81,13 +98,26 @@ typedef struct {
  * its upper-left 3x3. The image plane at distance 1 spans
  * [tan_left, tan_right] x [tan_bottom, tan_top] (asymmetric frusta allowed);
  * pixel (x, y) has its centre at tangent
- *   (tan_left + (x + 0.5) / width * (tan_right - tan_left),
- *    tan_top  - (y + 0.5) / height * (tan_top - tan_bottom)),
- * row 0 at the top. */
+ *   (sx, sy) = (tan_left + (x + 0.5) / width * (tan_right - tan_left),
+ *               tan_top  - (y + 0.5) / height * (tan_top - tan_bottom)),
+ * row 0 at the top.
+ * Wrapped space (Sec 5.3: rays spread uniformly over the image the lens
+ * distortion is applied to): with lens = {k1, k2, cx, cy} not both k zero,
+ * each pixel's tangent is moved radially about (cx, cy):
+ *   (sx, sy) <- (cx, cy) + (sx - cx, sy - cy) * (1 + k1 r^2 + k2 r^4),
+ *   r^2 = (sx - cx)^2 + (sy - cy)^2.
+ * The LOD pixel angle stays (tan_top - tan_bottom) / height.
+ * ray_limit (Sec 5.6: rays end at the distance of opaque geometry read from
+ * a depth texture): NULL, or a device float [height][width] of distances
+ * along each pixel's ray from the eye (level-0 units); samples lie in front
+ * of it (+inf or NaN: no limit). Read in stream order; ignored by
+ * sg_get_lod_cut. */
 typedef struct {
   double cam_to_world[16];
   double tan_left, tan_right, tan_bottom, tan_top;
   int32_t width, height; /* >= 1 */
+  double lens[4];        /* k1, k2, cx, cy; all 0 = rectilinear           */
+  const float *ray_limit;
 } sg_view;
 
 typedef struct {
@@ -100,7 +130,15 @@ typedef struct {
   int32_t lod_bias;     /* finest level used (0 = full resolution)            */
   int32_t timepoint;    /* 0 .. timepoints-1                                  */
   uint32_t flags;       /* SG_LOD | SG_SKIP_EMPTY | SG_GATHER                 */
-  int32_t reserved;     /* must be 0                                          */
+  int32_t model;        /* sg_model                                           */
+  /* Clipping of every ray (Sec 6): cut plane j keeps the points p with
+   * nx px + ny py + nz pz + w <= 0 (planes[j] = {nx, ny, nz, w}, finite,
+   * normal not zero); with roi_on only the box roi = {lo x, y, z, hi x, y, z}
+   * (level-0 units, lo <= hi) is kept. */
+  int32_t n_planes;     /* 0..4                                              */
+  int32_t roi_on;       /* 0 or 1                                            */
+  double planes[4][4];
+  double roi[6];
 } sg_render_params;
 
 /* Optional instrumentation of one render (sg_render_views_stats). */
@@ -169,14 +207,18 @@ sg_status sg_set_transfer_function(sg_volume *vol, int32_t channel,
 /* Render n_views views in one launch sequence on hip_stream (Sec 5.1-5.3):
  * per view an LOD cut (Sec 5.2), then per pixel a ray through the cut's
  * nodes front to back, trilinear samples every step_voxels * 2^L level-0
- * units, transfer-function lookup, emission-absorption compositing with
- * early termination, background composited underneath.
+ * units inside the clipped ray interval, transfer-function lookup, the
+ * optical model's accumulation (emission-absorption compositing with early
+ * termination by default), background composited underneath
+ * (C + (1 - A) bg, A + (1 - A) bg.a).
  *   views    : host array [n_views]
  *   out_rgba : host array [n_views] of device float pointers, each
  *              [height][width][4] premultiplied RGBA, row 0 = top
  *   out_depth: NULL, or host array [n_views] of device float pointers (or
  *              NULL entries), each [height][width]: distance along the ray
  *              of the first sample whose alpha >= depth_alpha, +inf if none
+ *              (always +inf under the emission-only and maximum-intensity
+ *              models, whose alpha stays 0)
  * Asynchronous: returns after enqueueing. Requires a transfer function for
  * every channel (SG_ERR_STATE otherwise). n_views in [1, 4096]. */
 sg_status sg_render_views(sg_volume *vol, int32_t n_views, const sg_view *views,
@@ -195,7 +237,9 @@ sg_status sg_render_views_stats(sg_volume *vol, int32_t n_views,
 /* The LOD cut of one view (Sec 5.2) as computed on the device, for checking:
  * nodes receives the cut's node identifiers sorted ascending, each
  *   (level << 60) | (bx << 40) | (by << 20) | bz,
- * and empty[i] (if not NULL) the empty flag of nodes[i] at params->timepoint.
+ * and empty[i] (if not NULL) the skip flag of nodes[i] at params->timepoint
+ * for params->model (zero opacity, zero emission, or 0 for maximum
+ * intensity, whose skips depend on the ray).
  * *n_nodes is the capacity on input and the cut size on output; if the cut
  * is larger nothing is written and SG_ERR_INVALID_ARG is returned with the
  * needed size in *n_nodes. Host buffers; synchronises hip_stream. */

@@ -164,9 +164,13 @@ extern "C" sg_status sg_get_lod_cut(sg_volume* vol, const sg_view* view,
     return fail(SG_ERR_INVALID_ARG, "sg_get_lod_cut: capacity too small");
   }
   *n_nodes = (int32_t)out.size();
+  // the skip bit of the requested optical model (none for maximum intensity)
+  const uint8_t mask = params->model == SG_MODEL_EMISSION_ABSORPTION ? 1
+                       : params->model == SG_MODEL_EMISSION_ONLY   ? 2
+                                                                     : 0;
   for (size_t i = 0; i < out.size(); ++i) {
     nodes[i] = out[i].first;
-    if (empty) empty[i] = out[i].second;
+    if (empty) empty[i] = (out[i].second & mask) ? 1 : 0;
   }
   return SG_OK;
 }

@@ -1,38 +1,6 @@
-// raycast.hip -- the hot loop: per-pixel rays through the LOD cut, front to
-// back, with trilinear sampling, transfer-function lookup and
-// emission-absorption compositing with early termination (Sec 5.1, 5.2).
-//
-// Launch: one 256-thread workgroup per 16x16 pixel tile, four wave64s of
-// 8x8 pixels each; the tiles of all views form one grid (stereo pair or
-// batch in one launch, Sec 5.3). Workgroup ids are remapped so that blocks
-// of 4x4 tiles are dealt to the 8 XCDs (each with its own L2) in turn.
-//
-// Per ray:
-//  * FP64 set-up: direction from the pixel tangents, entry/exit against the
-//    volume box (Sec 5.1, x0 and x1).
-//  * A 3D DDA over the level-0 brick grid finds the cut nodes the ray
-//    crosses, in order (Sec 5.2: blocks rendered front to back, the ray
-//    continued inside each block). The cut map gives the node of each cell;
-//    consecutive cells of the same node are one segment. The node's
-//    parameter interval [t_in, t_out] is computed from its box in FP64.
-//    Empty nodes are skipped.
-//  * Inside a segment of level L the ray is sampled every
-//    D = step * 2^L level-0 units at the midpoints of the sub-intervals (the
-//    last one partial). Sample positions are evaluated in FP32 in the node's
-//    brick-local coordinates (small magnitudes), from an FP64 segment origin.
-//  * Trilinear interpolation of the node's brick (the apron makes clamping
-//    unnecessary), transfer function from LDS, a = 1 - exp(-rho s),
-//    C += (1 - A) a rgb, A += (1 - A) a; the ray stops when A >= ert.
-//
-// Two kernels share all of the per-ray arithmetic, so they give bit-identical
-// images:
-//  * staged (default): the 64 rays of a wave walk their nodes in lockstep,
-//    in the octree's front-to-back order for the view's eye (every ray meets
-//    nodes in that order, so each lane still sees its own segments in
-//    order). For the node at hand the wave stages, slab by slab along the
-//    dominant ray axis, the part of the brick its rays cross into LDS with
-//    coalesced dword loads, and the trilinear stencils read LDS.
-//  * gather: every lane reads its stencils straight from the pool.
+// raycast.hip -- host side of the ray caster: argument checks, per-view
+// constants, the LOD cut-map launch and the dispatch to the ray-casting
+// kernels (raycast_kernels.h, one translation unit per optical model).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -45,809 +13,19 @@ namespace sg {
 
 namespace {
 
-constexpr int kStageBytesDefault = 8192;  // per wave; tunable with SG_STAGE_BYTES
-
-// 1 - exp(-x) for x >= 0 with small absolute and relative error: a Taylor
-// polynomial below 1/16 (avoids the cancellation of 1 - exp(-x); truncation
-// error below x^5/120 < 1e-8), the exponential above.
-__device__ __forceinline__ float one_minus_exp_neg(float x) {
-  float p = x * (1.0f - x * (0.5f - x * (0.16666667f - x * 0.041666668f)));
-  float q = 1.0f - __expf(-x);
-  return x < 0.0625f ? p : q;
-}
-
-__device__ __forceinline__ float lerpf(float a, float b, float t) {
-  return fmaf(t, b - a, a);
-}
-
-// Slab test of e + t d against [lo, hi]; same operations as the CPU
-// reference so that segment ends agree to the bit.
-__device__ __forceinline__ bool box_interval(const double e[3], const double d[3],
-                                             const double lo[3], const double hi[3],
-                                             double& t0, double& t1) {
-  double a = -INFINITY, b = INFINITY;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    if (d[i] != 0.0) {
-      double ta = (lo[i] - e[i]) / d[i];
-      double tb = (hi[i] - e[i]) / d[i];
-      double mn = ta < tb ? ta : tb;
-      double mx = ta < tb ? tb : ta;
-      if (mn > a) a = mn;
-      if (mx < b) b = mx;
-    } else if (!(lo[i] <= e[i] && e[i] <= hi[i])) {
-      t0 = 0.0;
-      t1 = 0.0;
-      return false;
-    }
-  }
-  t0 = a;
-  t1 = b;
-  return a < b;
-}
-
-template <typename P>
-__device__ __forceinline__ float ld(P p) {
-  return (float)(*p);
-}
-
-// Trilinear value of the stencil whose (0,0,0) corner is at p0; sy / sz are
-// the row and plane strides of the array p0 points into.
-template <typename P>
-__device__ __forceinline__ float trilinear(P p0, int sy, int sz, float fx, float fy, float fz) {
-  const float c00 = lerpf(ld(p0), ld(p0 + 1), fx);
-  const float c10 = lerpf(ld(p0 + sy), ld(p0 + sy + 1), fx);
-  const float c01 = lerpf(ld(p0 + sz), ld(p0 + sz + 1), fx);
-  const float c11 = lerpf(ld(p0 + sz + sy), ld(p0 + sz + sy + 1), fx);
-  const float c0 = lerpf(c00, c10, fy);
-  const float c1 = lerpf(c01, c11, fy);
-  return lerpf(c0, c1, fz);
-}
-
-// ----------------------------------------------------------------- per ray
-struct Ray {
-  double e[3], d[3];
-  double tn, tf;
-  double tnext[3], inv[3];
-  int c[3], st[3];
-  bool alive;   // has entered the volume and is not terminated / exhausted
-  // current segment (valid when alive)
-  int node, L, b[3];
-  double t0, t1;
-  uint64_t key;
-  // sampling state of the current segment (brick-local FP32 frame)
-  float q0[3], dq[3], Df, s_last;
-  float tau, tau_last;  // ray parameter of sample k and of the last sample
-  int n, k;
-  // accumulation
-  float Cr, Cg, Cb, A, depth;
-  int nsamp;
-};
-
-__device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const ViewDev& V, int px,
-                                          int py) {
-  const double sx = V.tl + (((double)px + 0.5) / (double)V.W) * (V.tr - V.tl);
-  const double sy = V.tt - (((double)py + 0.5) / (double)V.H) * (V.tt - V.tb);
-  double w3[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    r.e[i] = V.e[i];
-    w3[i] = (V.R[3 * i + 0] * sx + V.R[3 * i + 1] * sy) + V.R[3 * i + 2] * (-1.0);
-  }
-  const double len = sqrt((w3[0] * w3[0] + w3[1] * w3[1]) + w3[2] * w3[2]);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) r.d[i] = w3[i] / len;
-  r.Cr = r.Cg = r.Cb = r.A = 0.f;
-  r.depth = INFINITY;
-  r.nsamp = 0;
-  r.n = r.k = 0;
-  const double lo[3] = {0.0, 0.0, 0.0};
-  const double hi[3] = {(double)a.dims[0], (double)a.dims[1], (double)a.dims[2]};
-  box_interval(r.e, r.d, lo, hi, r.tn, r.tf);
-  if (r.tn < 0.0) r.tn = 0.0;
-  r.alive = r.tn < r.tf;
-  if (!r.alive) return;
-  const double Bd = (double)a.B;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double p = r.e[i] + r.tn * r.d[i];
-    const int ci = (int)floor(p / Bd);
-    r.c[i] = ci < 0 ? 0 : (ci > a.grid0[i] - 1 ? a.grid0[i] - 1 : ci);
-    if (r.d[i] > 0.0) {
-      r.st[i] = 1;
-      r.inv[i] = 1.0 / r.d[i];
-      r.tnext[i] = (Bd * (double)(r.c[i] + 1) - r.e[i]) * r.inv[i];
-    } else if (r.d[i] < 0.0) {
-      r.st[i] = -1;
-      r.inv[i] = 1.0 / r.d[i];
-      r.tnext[i] = (Bd * (double)r.c[i] - r.e[i]) * r.inv[i];
-    } else {
-      r.st[i] = 0;
-      r.inv[i] = 0.0;
-      r.tnext[i] = INFINITY;
-    }
-  }
-}
-
-// Advance the ray to its next segment that needs samples: a cut node whose
-// parameter interval is non-empty and that is not skipped as empty. With
-// `first` the current DDA cell is examined before stepping.
-__device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const ViewDev& V,
-                                             bool first) {
-  const int32_t* cutmap = a.cutmap + V.cut_off;
-  const double Bd = (double)a.B;
-  bool step = !first;
-  while (true) {
-    if (step) {
-      // leave the current node: step cells until one outside the node's box
-      int clo[3], chi[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        clo[i] = r.b[i] << r.L;
-        chi[i] = min(((r.b[i] + 1) << r.L) - 1, a.grid0[i] - 1);
-      }
-      bool inside = true;
-      while (inside) {
-        // next plane crossing; the axis is chosen with constant indices only
-        // so that the ray state stays in registers
-        const bool x_min = r.tnext[0] <= r.tnext[1] && r.tnext[0] <= r.tnext[2];
-        const bool y_min = !x_min && r.tnext[1] <= r.tnext[2];
-        const double tmin = x_min ? r.tnext[0] : (y_min ? r.tnext[1] : r.tnext[2]);
-        if (!(tmin < r.tf)) {
-          r.alive = false;
-          return;
-        }
-        bool out;
-        if (x_min) {
-          r.c[0] += r.st[0];
-          out = r.c[0] < 0 || r.c[0] >= a.grid0[0];
-          r.tnext[0] = (Bd * (double)(r.c[0] + (r.st[0] > 0 ? 1 : 0)) - r.e[0]) * r.inv[0];
-        } else if (y_min) {
-          r.c[1] += r.st[1];
-          out = r.c[1] < 0 || r.c[1] >= a.grid0[1];
-          r.tnext[1] = (Bd * (double)(r.c[1] + (r.st[1] > 0 ? 1 : 0)) - r.e[1]) * r.inv[1];
-        } else {
-          r.c[2] += r.st[2];
-          out = r.c[2] < 0 || r.c[2] >= a.grid0[2];
-          r.tnext[2] = (Bd * (double)(r.c[2] + (r.st[2] > 0 ? 1 : 0)) - r.e[2]) * r.inv[2];
-        }
-        if (out) {
-          r.alive = false;
-          return;
-        }
-        inside = r.c[0] >= clo[0] && r.c[0] <= chi[0] && r.c[1] >= clo[1] &&
-                 r.c[1] <= chi[1] && r.c[2] >= clo[2] && r.c[2] <= chi[2];
-      }
-    }
-    step = true;
-    r.node = cutmap[((int64_t)r.c[2] * a.grid0[1] + r.c[1]) * a.grid0[0] + r.c[0]];
-    const NodeInfo ni = a.info[r.node];
-    r.L = ni.level;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) r.b[i] = ni.b[i];
-    if (a.skip_empty && a.empty[r.node]) continue;  // before any box arithmetic
-    double blo[3], bhi[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int64_t wdt = (int64_t)a.B << r.L;
-      const int64_t l0 = wdt * ni.b[i];
-      int64_t h0 = wdt * (ni.b[i] + 1);
-      if (h0 > a.dims[i]) h0 = a.dims[i];
-      blo[i] = (double)l0;
-      bhi[i] = (double)h0;
-    }
-    double t0, t1;
-    box_interval(r.e, r.d, blo, bhi, t0, t1);
-    if (t0 < r.tn) t0 = r.tn;
-    if (t1 > r.tf) t1 = r.tf;
-    if (!(t0 < t1)) continue;
-    r.key = visibility_key(a.key_levels, a.B, r.e, r.L, r.b);
-    r.t0 = t0;
-    r.t1 = t1;
-    // sampling frame: stored index of the brick, FP32 from an FP64 origin
-    const double Dd = a.step * (double)((int64_t)1 << r.L);
-    const double len = t1 - t0;
-    r.n = (int)ceil(len / Dd);
-    r.k = 0;
-    r.s_last = (float)(len - (double)(r.n - 1) * Dd);
-    r.Df = (float)Dd;
-    r.tau = 0.5f * r.Df;  // (k + 1/2) D is exact: D is a power of two
-    r.tau_last = fmaf((float)(r.n - 1), r.Df, 0.5f * r.s_last);
-    const double inv_s = 1.0 / (double)((int64_t)1 << r.L);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double o = (double)((int64_t)a.B * ((int64_t)r.b[i] << r.L));
-      r.q0[i] = (float)(((r.e[i] - o) + t0 * r.d[i]) * inv_s + 0.5);
-      r.dq[i] = (float)(r.d[i] * inv_s);
-    }
-    return;
-  }
-}
-
-// Ray parameter (from the segment start, level-0 units) of sample k.
-__device__ __forceinline__ float sample_tau(const Ray& r, int k) {
-  const float s = k == r.n - 1 ? r.s_last : r.Df;
-  return fmaf((float)k, r.Df, 0.5f * s);
-}
-
-// Shade and composite sample r.k; `fetch(ch, ix, iy, iz, fx, fy, fz)`
-// returns the trilinear value of channel ch at stored index (ix, iy, iz)
-// plus fraction. Returns false once the ray has terminated.
-template <int CH, bool STATS, bool CLAMP = true, typename F>
-__device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
-                                            bool want_depth, F&& fetch, int (*mb_key)[3]) {
-  const int k = r.k;
-  const bool last = k == r.n - 1;
-  const float s = last ? r.s_last : r.Df;
-  const float tau = last ? r.tau_last : r.tau;  // = sample_tau(r, k)
-  const float qx = fmaf(tau, r.dq[0], r.q0[0]);
-  const float qy = fmaf(tau, r.dq[1], r.q0[1]);
-  const float qz = fmaf(tau, r.dq[2], r.q0[2]);
-  // stencil origin. Samples inside the node box always have it in
-  // [0, B]; reads from the pool clamp it anyway to guard memory safety
-  // (LDS reads need no guard: out-of-range LDS addresses cannot fault and
-  // the staged region is proven to contain every staged stencil).
-  const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
-  const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
-  const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
-  // q >= 0, so fract(q) = q - floor(q) = q - ix (exact)
-  const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
-              fz = __builtin_amdgcn_fractf(qz);
-  float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
-#pragma unroll
-  for (int ch = 0; ch < CH; ++ch) {
-    const float val = fetch(ch, ix, iy, iz, fx, fy, fz);
-    float u = fmaf(val, a.tf_scale[ch], a.tf_bias[ch]);
-    u = fminf(fmaxf(u, 0.0f), (float)(a.tf_n - 1));
-    const int k0 = (int)u;
-    const float wt = u - (float)k0;
-    const float4 t0v = s_tf[ch * (a.tf_n + 1) + k0];
-    const float4 t1v = s_tf[ch * (a.tf_n + 1) + k0 + 1];
-    const float cr = lerpf(t0v.x, t1v.x, wt);
-    const float cg = lerpf(t0v.y, t1v.y, wt);
-    const float cb = lerpf(t0v.z, t1v.z, wt);
-    const float rh = lerpf(t0v.w, t1v.w, wt);
-    if (CH == 1) {
-      er = cr;
-      eg = cg;
-      eb = cb;
-      rho = rh;
-    } else {
-      rho += rh;
-      er = fmaf(rh, cr, er);
-      eg = fmaf(rh, cg, eg);
-      eb = fmaf(rh, cb, eb);
-    }
-    if (STATS) {
-      // distinct 4^3 blocks of this level read by the stencil; consecutive
-      // samples mostly reuse the previous blocks, so mark only on change
-      const int32_t* nL = a.ldims[r.L];
-      const int gl[3] = {a.B * r.b[0] - 1 + ix, a.B * r.b[1] - 1 + iy, a.B * r.b[2] - 1 + iz};
-      int lo3[3], hi3[3], m3[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int g0 = gl[i] < 0 ? 0 : (gl[i] > nL[i] - 1 ? nL[i] - 1 : gl[i]);
-        const int g1 = gl[i] + 1 > nL[i] - 1 ? nL[i] - 1 : gl[i] + 1;
-        lo3[i] = g0 >> 2;
-        hi3[i] = g1 >> 2;
-        m3[i] = (nL[i] + 3) >> 2;
-      }
-      const int key0 = (lo3[0] | (lo3[1] << 16)) ^ (r.L << 27);
-      const int key1 = lo3[2] | (hi3[0] << 16);
-      const int key2 = hi3[1] | (hi3[2] << 16);
-      int* mk = mb_key[ch];
-      if (!(key0 == mk[0] && key1 == mk[1] && key2 == mk[2])) {
-        mk[0] = key0;
-        mk[1] = key1;
-        mk[2] = key2;
-        const int64_t off = a.level_mb_off[ch * kMaxLevels + r.L];
-        for (int zz = lo3[2]; zz <= hi3[2]; ++zz)
-          for (int yy = lo3[1]; yy <= hi3[1]; ++yy)
-            for (int xx = lo3[0]; xx <= hi3[0]; ++xx) {
-              const int64_t bit = off + ((int64_t)zz * m3[1] + yy) * m3[0] + xx;
-              atomicOr(a.mb_bits + (bit >> 5), 1u << (bit & 31));
-            }
-      }
-    }
-  }
-  if (CH > 1) {
-    const float inv_r = rho > 0.f ? 1.0f / rho : 0.f;
-    er *= inv_r;
-    eg *= inv_r;
-    eb *= inv_r;
-  }
-  const float al = one_minus_exp_neg(rho * s);
-  const float wgt = (1.0f - r.A) * al;
-  r.Cr = fmaf(wgt, er, r.Cr);
-  r.Cg = fmaf(wgt, eg, r.Cg);
-  r.Cb = fmaf(wgt, eb, r.Cb);
-  r.A += wgt;
-  r.k = k + 1;
-  r.tau += r.Df;
-  if (STATS) ++r.nsamp;
-  if (want_depth && r.depth == INFINITY && r.A >= a.depth_alpha)
-    r.depth = (float)(r.t0 + (double)tau);
-  if (r.A >= a.ert) {
-    r.alive = false;
-    return false;
-  }
-  return true;
-}
-
-// Pool slot pointers of a node, one per channel.
-template <typename T, int CH>
-__device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T* slot[CH]) {
-#pragma unroll
-  for (int ch = 0; ch < CH; ++ch)
-    slot[ch] = reinterpret_cast<const T*>(
-        a.pool + (int64_t)a.page[(int64_t)ch * a.nodes + node] * a.slot_bytes);
-}
-
-__device__ __forceinline__ void write_pixel(const Ray& r, const RenderArgs& a, const ViewDev& V,
-                                            int px, int py) {
-  const float omA = 1.0f - r.A;
-  const int64_t pix = (int64_t)py * V.W + px;
-  float4 out;
-  out.x = fmaf(omA, a.bg[0], r.Cr);
-  out.y = fmaf(omA, a.bg[1], r.Cg);
-  out.z = fmaf(omA, a.bg[2], r.Cb);
-  out.w = fmaf(omA, a.bg[3], r.A);
-  reinterpret_cast<float4*>(V.rgba)[pix] = out;
-  if (V.depth) V.depth[pix] = r.depth;
-}
-
-// Tile of this lane. Workgroups go to the 8 XCDs round-robin (workgroup i
-// on XCD i % 8). Tiles are grouped into blocks of 4x4 tiles (64x64 pixels,
-// about one brick's footprint at the selected level) and the blocks are dealt
-// to the XCDs in turn: the 16 tiles of a block share one XCD's L2, and every
-// XCD gets an even share of the image (heavy regions are spread out).
-struct TileLane {
-  int view, px, py;
-  bool in_image;
-  bool tile_valid;
-};
-
-__device__ __forceinline__ TileLane tile_lane(const RenderArgs& a) {
-  const int bid = blockIdx.x;
-  const int x = bid & 7, j = bid >> 3;
-  const int block = (j >> 4) * 8 + x;
-  const int t = j & 15;
-  TileLane out;
-  out.view = 0;
-  out.px = out.py = 0;
-  out.in_image = false;
-  out.tile_valid = block < a.total_blocks;
-  if (!out.tile_valid) return out;
-  int lo = 0, hi = a.n_views - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.views[mid].block_begin <= block) lo = mid; else hi = mid - 1;
-  }
-  const ViewDev& V = a.views[lo];
-  const int lb = block - V.block_begin;
-  const int bx = lb % V.blocks_x, by = lb / V.blocks_x;
-  const int tx = bx * 4 + (t & 3), ty = by * 4 + (t >> 2);
-  out.tile_valid = tx < V.tiles_x && ty < V.tiles_y;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  out.view = lo;
-  out.px = tx * 16 + (w & 1) * 8 + (lane & 7);
-  out.py = ty * 16 + (w >> 1) * 8 + (lane >> 3);
-  out.in_image = out.tile_valid && out.px < V.W && out.py < V.H;
-  return out;
-}
-
-template <int CH>
-__device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
-  const int ntf = CH * (a.tf_n + 1);
-  for (int i = threadIdx.x; i < ntf; i += 256) s_tf[i] = reinterpret_cast<const float4*>(a.tf)[i];
-  __syncthreads();
-}
-
-// ------------------------------------------------------------ gather kernel
-template <typename T, int CH, bool STATS>
-__global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
-  extern __shared__ float4 s_tf[];
-  load_tf<CH>(a, s_tf);
-  const TileLane tl = tile_lane(a);
-  if (!tl.in_image) return;
-  const ViewDev& V = a.views[tl.view];
-  const bool want_depth = V.depth != nullptr;
-  int mb_key[CH][3];
-#pragma unroll
-  for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
-  Ray r;
-  ray_setup(r, a, V, tl.px, tl.py);
-  if (r.alive) next_segment(r, a, V, true);
-  const int sy = a.Sx, sz = a.S * a.Sx;
-  while (r.alive) {
-    const T* slot[CH];
-    slot_ptrs<T, CH>(a, r.node, slot);
-    if (STATS) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
-    auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-      return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
-    };
-    bool go = true;
-    while (go && r.k < r.n) go = sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key);
-    if (!go) break;
-    next_segment(r, a, V, false);
-  }
-  write_pixel(r, a, V, tl.px, tl.py);
-  if (STATS) {
-    if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
-    atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
-  }
-}
-
-// ------------------------------------------------------------ staged kernel
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wave reductions without LDS traffic: within each 16-lane row, DPP lane
-// swaps (quad_perm xor 1, quad_perm xor 2, half-row mirror, row mirror)
-// leave the row's result in every lane; the four row results are then read
-// as scalars. Every lane of the wave must be active at the call (a swap
-// from an inactive lane returns the lane's own value).
-template <int C>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, C, 0xF, 0xF, false);
-}
-template <typename Op>
-__device__ __forceinline__ int wave_reduce_i(int v, Op op) {
-  v = op(v, dpp_i<0xB1>(v));
-  v = op(v, dpp_i<0x4E>(v));
-  v = op(v, dpp_i<0x141>(v));
-  v = op(v, dpp_i<0x140>(v));
-  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
-  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
-  return op(op(a, b), op(c, d));
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-  return wave_reduce_i(v, [](int x, int y) { return min(x, y); });
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-  return wave_reduce_i(v, [](int x, int y) { return max(x, y); });
-}
-template <int C>
-__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-  const int lo = dpp_i<C>((int)(uint32_t)v), hi = dpp_i<C>((int)(uint32_t)(v >> 32));
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ uint64_t rl_u64(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-  v = umin64(v, dpp_u64<0xB1>(v));
-  v = umin64(v, dpp_u64<0x4E>(v));
-  v = umin64(v, dpp_u64<0x141>(v));
-  v = umin64(v, dpp_u64<0x140>(v));
-  return umin64(umin64(rl_u64(v, 0), rl_u64(v, 16)), umin64(rl_u64(v, 32), rl_u64(v, 48)));
-}
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float lane_f(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-
-// Component-wise minimum of two 16-bit lanes packed in a word, over the wave.
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t wave_min_u16x2(uint32_t v) {
-  return (uint32_t)wave_reduce_i((int)v, [](int x, int y) {
-    return (int)__builtin_bit_cast(uint32_t, __builtin_elementwise_min(
-        __builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, y)));
-  });
-}
-
-// Main-axis stencil layer of sample k (same arithmetic as the sample).
-__device__ __forceinline__ int sample_layer(const Ray& r, int k, float dqm, float qm0, int B) {
-  return min(max((int)fmaf(sample_tau(r, k), dqm, qm0), 0), B);
-}
-
-// Stencil corner bounds (per axis; the stencil also reads corner + 1) of
-// samples ka and kb of the lane's segment, hence of every sample between.
-__device__ __forceinline__ void stencil_bounds(const Ray& r, int ka, int kb, int B, int lo[3],
-                                               int hi[3]) {
-  const float ta = sample_tau(r, ka), tb = sample_tau(r, kb);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int ia = min(max((int)fmaf(ta, r.dq[i], r.q0[i]), 0), B);
-    const int ib = min(max((int)fmaf(tb, r.dq[i], r.q0[i]), 0), B);
-    lo[i] = min(ia, ib);
-    hi[i] = max(ia, ib);
-  }
-}
-
-__device__ __forceinline__ float pick(const float v[3], int m) {
-  return m == 0 ? v[0] : (m == 1 ? v[1] : v[2]);
-}
-__device__ __forceinline__ int pick(const int v[3], int m) {
-  return m == 0 ? v[0] : (m == 1 ? v[1] : v[2]);
-}
-
-template <typename T, int CH, bool STATS>
-__global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
-  extern __shared__ float4 smem[];
-  float4* s_tf = smem;
-  load_tf<CH>(a, s_tf);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
-                                  w * a.stage_bytes);
-  // staging moves chunks of kRowAlignBytes (pool rows are aligned to
-  // them); the capacity per channel is a whole number of chunks so every
-  // channel's region starts chunk-aligned in LDS
-  constexpr int align = kRowAlignBytes / (int)sizeof(T);  // voxels per chunk
-  const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~(align - 1);
-
-  const TileLane tl = tile_lane(a);
-  if (!tl.tile_valid) return;  // uniform over the workgroup; no barrier follows
-  const ViewDev& V = a.views[tl.view];
-  const bool want_depth = V.depth != nullptr;
-  int mb_key[CH][3];
-#pragma unroll
-  for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
-  Ray r;
-  r.alive = false;
-  r.Cr = r.Cg = r.Cb = r.A = 0.f;
-  r.depth = INFINITY;
-  r.nsamp = 0;
-  r.n = r.k = 0;
-  if (tl.in_image) {
-    ray_setup(r, a, V, tl.px, tl.py);
-    if (r.alive) next_segment(r, a, V, true);
-  }
-  const int B = a.B, S = a.S, Sx = a.Sx;
-
-  while (true) {
-    // --- the wave's next node: smallest front-to-back key among its rays
-    const uint64_t K = wave_min_u64(r.alive ? r.key : ~0ull);
-    if (K == ~0ull) break;
-    const bool mine = r.alive && r.key == K;
-    const uint64_t mask = __ballot(mine);
-    const int first = __ffsll((unsigned long long)mask) - 1;
-    const int node = uniform(__builtin_amdgcn_readlane(r.node, first));
-    const T* slot[CH];
-    slot_ptrs<T, CH>(a, node, slot);
-    if (STATS && lane == 0) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
-
-    // --- dominant axis of the node's first ray; every ray of the node must
-    // advance along it with the same sign, else everything reads the pool
-    const float d0[3] = {lane_f(r.dq[0], first), lane_f(r.dq[1], first),
-                         lane_f(r.dq[2], first)};
-    int m = 0;
-    if (fabsf(d0[1]) > fabsf(d0[0])) m = 1;
-    if (fabsf(d0[2]) > fabsf(pick(d0, m))) m = 2;
-    m = uniform(m);
-    const int sgn = uniform(pick(d0, m) > 0.f ? 1 : -1);
-    const float my_dqm = pick(r.dq, m);
-    const float my_qm0 = pick(r.q0, m);
-    const float my_sum = fabsf(r.dq[0]) + fabsf(r.dq[1]) + fabsf(r.dq[2]);
-    const bool bad = mine && !((float)sgn * my_dqm >= 0.25f * my_sum);
-    const bool axis_ok = __ballot(bad) == 0;
-
-    // --- slabs along the main axis, in the rays' direction of travel. The
-    // first slab starts at the first stencil layer any ray needs; each owns
-    // D layers and stages them plus the one the stencils reach into. Every
-    // lane takes exactly its samples whose layer lies in the slab, so the
-    // next slab starts right after it.
-    const int big = 0xFFFF;
-    const bool more0 = mine && r.alive && r.k < r.n;
-    int j;
-    {
-      const int my_im = more0 ? sample_layer(r, r.k, my_dqm, my_qm0, B) : (sgn > 0 ? big : -1);
-      j = uniform(sgn > 0 ? wave_min_i(my_im) : wave_max_i(my_im));
-    }
-    int D = 8;
-    while (true) {
-      const bool more = mine && r.alive && r.k < r.n;
-      if (__ballot(more) == 0) break;
-      if (!axis_ok || (sgn > 0 ? j > B : j < 0)) {
-        // no shared dominant direction (or, defensively, nothing left in
-        // range): read the pool for all remaining samples
-        if (more) {
-          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
-          };
-          while (r.k < r.n && sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
-          }
-        }
-        continue;
-      }
-      int jl = j, jh = j, kb = r.k - 1;
-      int o[3] = {0, 0, 0}, wd[3] = {0, 0, 0};
-      bool fits = false;
-      for (int tries = 0; tries < 8; ++tries) {
-        jl = sgn > 0 ? j : max(j - D + 1, 0);
-        jh = sgn > 0 ? min(j + D - 1, B) : j;
-        // this lane's samples in the slab: k .. kb, found exactly
-        kb = r.k - 1;
-        uint32_t plo = 0xFFFFFFFFu, phi = 0xFFFFFFFFu;  // packed min(lo), min(~hi)
-        if (more) {
-          const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
-          const float tlim = (edge - my_qm0) / my_dqm;
-          kb = (int)ceilf(tlim / r.Df - 0.5f) - 1;
-          kb = min(max(kb, r.k - 1), r.n - 1);
-          while (kb + 1 < r.n) {
-            const int im = sample_layer(r, kb + 1, my_dqm, my_qm0, B);
-            if (im < jl || im > jh) break;
-            ++kb;
-          }
-          while (kb >= r.k) {
-            const int im = sample_layer(r, kb, my_dqm, my_qm0, B);
-            if (im >= jl && im <= jh) break;
-            --kb;
-          }
-          if (kb >= r.k) {
-            int lo3[3], hi3[3];
-            stencil_bounds(r, r.k, kb, B, lo3, hi3);
-            const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;  // cross axes
-            plo = (uint32_t)pick(lo3, ua) | ((uint32_t)pick(lo3, ub) << 16);
-            phi = (uint32_t)(0xFFFF - pick(hi3, ua)) | ((uint32_t)(0xFFFF - pick(hi3, ub)) << 16);
-          }
-        }
-        const uint32_t rlo = (uint32_t)uniform((int)wave_min_u16x2(plo));
-        const uint32_t rhi = (uint32_t)uniform((int)wave_min_u16x2(phi));
-        const int la = (int)(rlo & 0xFFFF), lb = (int)(rlo >> 16);
-        const int ha = 0xFFFF - (int)(rhi & 0xFFFF), hb = 0xFFFF - (int)(rhi >> 16);
-        const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          if (i == m) {
-            o[i] = jl;
-            wd[i] = jh - jl + 2;
-          } else {
-            const int l = i == ua ? la : lb, h = i == ua ? ha : hb;
-            o[i] = l <= h ? l : 0;
-            wd[i] = l <= h ? h - l + 2 : 0;
-          }
-        }
-        // chunk-aligned rows: x origin rounded down, width rounded up
-        const int ox = (o[0] / align) * align;
-        wd[0] = ((o[0] + wd[0] - ox + align - 1) / align) * align;
-        o[0] = ox;
-        wd[0] = min(wd[0], Sx - o[0]);
-        wd[1] = min(wd[1], S - o[1]);
-        wd[2] = min(wd[2], S - o[2]);
-        const int vox = wd[0] * wd[1] * wd[2];
-        if (vox <= cap) {
-          fits = vox > 0;
-          // next slab's depth from this slab's cross-section
-          const int area = max(1, vox / max(1, wd[m]));
-          D = min(max(cap / area - 1, 1), 64);
-          break;
-        }
-        if (D == 1) break;
-        // the cross-section of a thinner slab is no larger (its samples are
-        // a subset), so this depth fits unless even one layer does not
-        D = max(1, min(D - 1, cap / max(1, vox / max(1, wd[m])) - 1));
-      }
-      if (fits) {
-        // --- stage the region of every channel: pass p moves chunks
-        // p .. p+63 of the region (row-major, cpr chunks per row) straight
-        // from the pool into LDS (global_load_lds: lane i writes chunk i
-        // after the LDS base of the pass)
-        // Chunk i of the region is row = i / cpr, plane rz = row / wd[1];
-        // in the slot it sits at base + i + row * skip_row + rz * skip_plane
-        // (the chunks a row or a plane of the slot has beyond the region's).
-        // The quotients come from (x + 1/2) * (1/d) in FP32: its relative
-        // error is below 2^-23 and (x + 1/2) / d lies at least 1/(2d) from
-        // an integer, so the floor is exact for every x < 2^22.
-        const int cpr = wd[0] / align, P = Sx / align;
-        const int rows = wd[1] * wd[2];
-        const int total = cpr * rows;
-        const float inv_cpr = 1.0f / (float)cpr, inv_wy = 1.0f / (float)wd[1];
-        const int base = ((o[2] * S + o[1]) * Sx + o[0]) / align;
-        const int skip_row = P - cpr, skip_plane = (S - wd[1]) * P;
-        for (int p0 = 0; p0 < total; p0 += 64) {
-          const int i = p0 + lane;
-          if (i < total) {
-            const int row = (int)(((float)i + 0.5f) * inv_cpr);
-            const int rz = (int)(((float)row + 0.5f) * inv_wy);
-            const int g = base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane);
-#pragma unroll
-            for (int ch = 0; ch < CH; ++ch)
-              __builtin_amdgcn_global_load_lds(
-                  reinterpret_cast<const uint8_t*>(slot[ch]) + (size_t)g * kRowAlignBytes,
-                  reinterpret_cast<uint8_t*>(stage + ch * cap) + p0 * kRowAlignBytes,
-                  kRowAlignBytes, 0, 0);
-          }
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads have landed
-        wave_sync();
-        if (STATS && lane == 0) {
-          atomicAdd((unsigned long long*)a.counters + 2, 1ull);
-          atomicAdd((unsigned long long*)a.counters + 3,
-                    (unsigned long long)(total * kRowAlignBytes * CH));
-        }
-        if (kb >= r.k) {
-          const int sy_l = wd[0], sz_l = wd[0] * wd[1];
-          const int base_off = (o[2] * wd[1] + o[1]) * wd[0] + o[0];  // region origin
-          const int wy = wd[1];
-          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            const int idx = __mul24(__mul24(iz, wy) + iy, sy_l) + ix - base_off;
-            return trilinear(stage + ch * cap + idx, sy_l, sz_l, fx, fy, fz);
-          };
-          while (r.k <= kb &&
-                 sample_once<CH, STATS, false>(r, a, s_tf, want_depth, fetch, mb_key)) {
-          }
-        }
-        wave_sync();
-      } else if (kb >= r.k) {
-        // the slab does not fit even one layer deep: read the pool for it
-        auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-          return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
-        };
-        while (r.k <= kb && sample_once<CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
-        }
-      }
-      j = sgn > 0 ? jh + 1 : jl - 1;
-    }
-    // --- rays that finished this node move on to their next segment
-    if (mine && r.alive) next_segment(r, a, V, false);
-  }
-  if (tl.in_image) {
-    write_pixel(r, a, V, tl.px, tl.py);
-    if (STATS) {
-      if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
-      atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
-    }
-  }
-}
-
-template <typename K>
-sg_status allow_lds(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  return SG_OK;
-}
-
-template <typename T, int CH>
-sg_status launch_t(const RenderArgs& a, bool stats, bool gather, hipStream_t s) {
-  const size_t tf_lds = (size_t)CH * (a.tf_n + 1) * sizeof(float4);
-  if (gather) {
-    if (stats)
-      hipLaunchKernelGGL((raycast_gather<T, CH, true>), dim3(a.grid), dim3(256), tf_lds,
-                         s, a);
-    else
-      hipLaunchKernelGGL((raycast_gather<T, CH, false>), dim3(a.grid), dim3(256), tf_lds,
-                         s, a);
-  } else {
-    const size_t lds = tf_lds + 4 * (size_t)a.stage_bytes;
-    sg_status st = stats ? allow_lds(raycast_staged<T, CH, true>, lds)
-                         : allow_lds(raycast_staged<T, CH, false>, lds);
-    if (st != SG_OK) return st;
-    if (stats)
-      hipLaunchKernelGGL((raycast_staged<T, CH, true>), dim3(a.grid), dim3(256), lds, s,
-                         a);
-    else
-      hipLaunchKernelGGL((raycast_staged<T, CH, false>), dim3(a.grid), dim3(256), lds, s,
-                         a);
-  }
-  SG_HIP(hipGetLastError());
-  return SG_OK;
-}
-
-template <typename T>
-sg_status launch_ch(const RenderArgs& a, int C, bool stats, bool gather, hipStream_t s) {
-  switch (C) {
-    case 1: return launch_t<T, 1>(a, stats, gather, s);
-    case 2: return launch_t<T, 2>(a, stats, gather, s);
-    case 3: return launch_t<T, 3>(a, stats, gather, s);
-    default: return launch_t<T, 4>(a, stats, gather, s);
-  }
-}
-
 bool finite(double x) { return std::isfinite(x); }
 
 }  // namespace
 
 sg_status launch_raycast(Volume* v, const RenderArgs& a, bool stats, hipStream_t s) {
-  if (v->bpv == 1) return launch_ch<uint8_t>(a, v->d.channels, stats, a.gather != 0, s);
-  return launch_ch<uint16_t>(a, v->d.channels, stats, a.gather != 0, s);
+  switch (a.model) {
+    case kModelEmission:
+      return launch_raycast_emission(v->bpv, v->d.channels, a, stats, s);
+    case kModelMip:
+      return launch_raycast_mip(v->bpv, v->d.channels, a, stats, s);
+    default:
+      return launch_raycast_absorption(v->bpv, v->d.channels, a, stats, s);
+  }
 }
 
 sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
@@ -861,8 +39,20 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
       !(finite(p->lod_tau_px) && p->lod_tau_px > 0.0) || !finite(p->depth_alpha) ||
       p->lod_bias < 0 || p->lod_bias >= v->L || p->timepoint < 0 ||
       p->timepoint >= v->d.timepoints ||
-      (p->flags & ~(uint32_t)(SG_LOD | SG_SKIP_EMPTY | SG_GATHER)) || p->reserved != 0)
+      (p->flags & ~(uint32_t)(SG_LOD | SG_SKIP_EMPTY | SG_GATHER)) || p->model < 0 ||
+      p->model > SG_MODEL_MAX_INTENSITY || p->n_planes < 0 || p->n_planes > 4 ||
+      (p->roi_on != 0 && p->roi_on != 1))
     return fail(SG_ERR_INVALID_ARG, "render params out of range");
+  for (int j = 0; j < p->n_planes; ++j) {
+    const double* q = p->planes[j];
+    if (!(finite(q[0]) && finite(q[1]) && finite(q[2]) && finite(q[3])) ||
+        (q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0))
+      return fail(SG_ERR_INVALID_ARG, "cut planes must be finite with a nonzero normal");
+  }
+  if (p->roi_on)
+    for (int i = 0; i < 3; ++i)
+      if (!(finite(p->roi[i]) && finite(p->roi[i + 3]) && p->roi[i] <= p->roi[i + 3]))
+        return fail(SG_ERR_INVALID_ARG, "region of interest must be finite with lo <= hi");
   for (int i = 0; i < 4; ++i)
     if (!finite(p->background[i])) return fail(SG_ERR_INVALID_ARG, "background not finite");
   std::vector<ViewDev> hv(n_views);
@@ -877,6 +67,10 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
       return fail(SG_ERR_INVALID_ARG, "view tangents must be finite with left<right, bottom<top");
     if (w.width < 1 || w.height < 1 || w.width > 32768 || w.height > 32768)
       return fail(SG_ERR_INVALID_ARG, "view size must be in [1, 32768]");
+    for (int k = 0; k < 4; ++k)
+      if (!finite(w.lens[k])) return fail(SG_ERR_INVALID_ARG, "lens coefficients not finite");
+    if (w.ray_limit && reinterpret_cast<uintptr_t>(w.ray_limit) % 4 != 0)
+      return fail(SG_ERR_INVALID_ARG, "ray_limit must be 4-byte aligned");
     const double* m = w.cam_to_world;
     double det = m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
                  m[2] * (m[4] * m[9] - m[5] * m[8]);
@@ -909,6 +103,9 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
     o.rgba = rgba ? rgba[i] : nullptr;
     o.depth = depth ? depth[i] : nullptr;
     o.nsamp = nsamp ? nsamp[i] : nullptr;
+    o.limit = w.ray_limit;
+    o.lens_on = (w.lens[0] != 0.0 || w.lens[1] != 0.0) ? 1 : 0;
+    for (int k = 0; k < 4; ++k) o.lens[k] = w.lens[k];
   }
   if (blocks > (1 << 24)) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
   const int64_t need_cut = (int64_t)n_views * cells;
@@ -976,6 +173,7 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   a.slot_bytes = v->slot_bytes;
   a.page = v->page + (int64_t)params->timepoint * C * v->nodes;
   a.empty = v->empty + (int64_t)params->timepoint * v->nodes;
+  a.range = v->range + (int64_t)params->timepoint * C * v->nodes * 2;
   a.info = v->info;
   a.tf = v->tf;
   a.cutmap = v->cutmap;
@@ -1009,6 +207,12 @@ static sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   a.step = params->step_voxels;
   a.ert = (float)params->ert_alpha;
   a.depth_alpha = (float)params->depth_alpha;
+  a.model = params->model;
+  a.n_planes = params->n_planes;
+  a.roi_on = params->roi_on;
+  for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i) a.planes[j][i] = j < params->n_planes ? params->planes[j][i] : 0.0;
+  for (int i = 0; i < 6; ++i) a.roi[i] = params->roi_on ? params->roi[i] : 0.0;
   if (stats) {
     // micro-block bitmap: one bit per 4^3 block per (channel, level)
     int64_t bits = 0;

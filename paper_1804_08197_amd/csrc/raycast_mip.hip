@@ -1,0 +1,12 @@
+// raycast_mip.hip -- ray-casting kernel instances of the maximum intensity model
+// (every voxel type, channel count, kernel flavour and statistics mode).
+#include "raycast_kernels.h"
+
+namespace sg {
+
+sg_status launch_raycast_mip(int bpv, int channels, const RenderArgs& a, bool stats,
+                              hipStream_t s) {
+  return launch_model<kModelMip>(bpv, channels, a, stats, s);
+}
+
+}  // namespace sg

@@ -19,6 +19,12 @@ constexpr int kMaxTfEntries = 1024;
 // four times the bytes per load but widen every staged row to 8 u16 voxels,
 // which costs more slabs than it saves loads on the tube workload.)
 constexpr int kRowAlignBytes = 4;
+// LDS staging bytes per wave of the ray caster (SG_STAGE_BYTES overrides).
+constexpr int kStageBytesDefault = 8192;
+// Optical models (values of sg_render_params.model).
+constexpr int kModelAbsorption = SG_MODEL_EMISSION_ABSORPTION;
+constexpr int kModelEmission = SG_MODEL_EMISSION_ONLY;
+constexpr int kModelMip = SG_MODEL_MAX_INTENSITY;
 
 // Error plumbing: every entry point funnels through these.
 sg_status fail(sg_status s, const std::string& msg);
@@ -75,7 +81,8 @@ struct Volume {
   uint8_t* pool = nullptr;    // [slots][S^3] voxels
   int32_t* page = nullptr;    // [T][C][nodes] -> slot
   uint32_t* range = nullptr;  // [T][C][nodes][2] min, max of stored voxels
-  uint8_t* empty = nullptr;   // [T][nodes] 1 if every channel is transparent
+  uint8_t* empty = nullptr;   // [T][nodes] bit 0: every channel transparent,
+                              // bit 1: every channel emits nothing
   NodeInfo* info = nullptr;   // [nodes]
   float* tf = nullptr;        // [C][tf_n + 1][4] (last entry repeated)
   int tf_n = 0;
@@ -145,6 +152,9 @@ struct ViewDev {
   float* rgba;
   float* depth;
   int32_t* nsamp;
+  const float* limit;  // per-pixel ray limit or NULL
+  double lens[4];      // k1, k2, cx, cy
+  int32_t lens_on;
 };
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
@@ -159,7 +169,8 @@ struct RenderArgs {
   const uint8_t* pool;
   int64_t slot_bytes;
   const int32_t* page;   // at timepoint: [C][nodes]
-  const uint8_t* empty;  // at timepoint: [nodes]
+  const uint8_t* empty;  // at timepoint: [nodes] skip bits (see Volume::empty)
+  const uint32_t* range; // at timepoint: [C][nodes][2] stored min, max
   const NodeInfo* info;
   const float* tf;
   const int32_t* cutmap;
@@ -186,10 +197,22 @@ struct RenderArgs {
   double step;
   float ert;
   float depth_alpha;
+  int32_t model;        // kModel*
+  int32_t n_planes;     // cut planes in use (0..4)
+  int32_t roi_on;
+  double planes[4][4];  // plane j keeps (n . p) + w <= 0: (nx, ny, nz, w)
+  double roi[6];        // region of interest lo xyz, hi xyz
 };
 
 sg_status launch_raycast(Volume* v, const RenderArgs& a, bool stats,
                          hipStream_t s);
+// Kernel instances per optical model (one translation unit each).
+sg_status launch_raycast_absorption(int bpv, int channels, const RenderArgs& a, bool stats,
+                                    hipStream_t s);
+sg_status launch_raycast_emission(int bpv, int channels, const RenderArgs& a, bool stats,
+                                  hipStream_t s);
+sg_status launch_raycast_mip(int bpv, int channels, const RenderArgs& a, bool stats,
+                             hipStream_t s);
 
 }  // namespace sg
 

@@ -170,19 +170,20 @@ __global__ __launch_bounds__(256) void range_kernel(const uint8_t* pool,
   }
 }
 
-// Empty flags (one thread per (timepoint, node)): a node is empty when, for
-// every channel, the extinction of every table entry from floor(u_min) - 1
+// Skip flags (one thread per (timepoint, node)). Bit 0 (transparent): for
+// every channel the extinction of every table entry from floor(u_min) - 1
 // to floor(u_max) + 2 is zero, u being the continuous table index of the
-// node's min / max value. The one-entry guard band on each side keeps the
-// flag exact for samples whose index is rounded in single precision.
+// node's min / max value. Bit 1 (dark): the same entries emit no colour.
+// The one-entry guard band on each side keeps the flags exact for samples
+// whose index is rounded in single precision.
 __global__ void empty_kernel(const uint32_t* range, const float* tf, int tf_n,
                              const double* lo, const double* hi, int C,
                              int64_t nodes, int64_t total, uint8_t* empty) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t t = i / nodes, node = i - t * nodes;
-    uint8_t e = 1;
-    for (int c = 0; c < C && e; ++c) {
+    bool clear = true, dark = true;
+    for (int c = 0; c < C && (clear || dark); ++c) {
       const uint32_t* r = range + 2 * ((t * C + c) * nodes + node);
       double umin = (((double)r[0] - lo[c]) / (hi[c] - lo[c])) * (double)(tf_n - 1);
       double umax = (((double)r[1] - lo[c]) / (hi[c] - lo[c])) * (double)(tf_n - 1);
@@ -191,13 +192,12 @@ __global__ void empty_kernel(const uint32_t* range, const float* tf, int tf_n,
       klo = klo < 0 ? 0 : (klo > tf_n - 1 ? tf_n - 1 : klo);
       khi = khi < 0 ? 0 : (khi > tf_n - 1 ? tf_n - 1 : khi);
       const float* tc = tf + (int64_t)c * (tf_n + 1) * 4;
-      for (int64_t k = klo; k <= khi; ++k)
-        if (tc[4 * k + 3] != 0.0f) {
-          e = 0;
-          break;
-        }
+      for (int64_t k = klo; k <= khi; ++k) {
+        if (tc[4 * k + 3] != 0.0f) clear = false;
+        if (tc[4 * k] != 0.0f || tc[4 * k + 1] != 0.0f || tc[4 * k + 2] != 0.0f) dark = false;
+      }
     }
-    empty[i] = e;
+    empty[i] = (uint8_t)((clear ? 1 : 0) | (dark ? 2 : 0));
   }
 }
 

@@ -23,7 +23,10 @@ SG_ERR_STATE = -4
 SG_ERR_UNSUPPORTED = -5
 SG_U8, SG_U16 = 1, 2
 SG_LOD, SG_SKIP_EMPTY, SG_GATHER = 1, 2, 4
-SG_ABI_VERSION = 1
+SG_MODEL_EMISSION_ABSORPTION, SG_MODEL_EMISSION_ONLY, SG_MODEL_MAX_INTENSITY = 0, 1, 2
+MODELS = {"ea": SG_MODEL_EMISSION_ABSORPTION, "eo": SG_MODEL_EMISSION_ONLY,
+          "mip": SG_MODEL_MAX_INTENSITY}
+SG_ABI_VERSION = 2
 
 
 class SgError(RuntimeError):
@@ -41,14 +44,16 @@ class sg_volume_desc(C.Structure):
 class sg_view(C.Structure):
     _fields_ = [("cam_to_world", C.c_double * 16), ("tan_left", C.c_double),
                 ("tan_right", C.c_double), ("tan_bottom", C.c_double), ("tan_top", C.c_double),
-                ("width", C.c_int32), ("height", C.c_int32)]
+                ("width", C.c_int32), ("height", C.c_int32), ("lens", C.c_double * 4),
+                ("ray_limit", C.c_void_p)]
 
 
 class sg_render_params(C.Structure):
     _fields_ = [("step_voxels", C.c_double), ("ert_alpha", C.c_double),
                 ("lod_tau_px", C.c_double), ("background", C.c_double * 4),
                 ("depth_alpha", C.c_double), ("lod_bias", C.c_int32), ("timepoint", C.c_int32),
-                ("flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("flags", C.c_uint32), ("model", C.c_int32), ("n_planes", C.c_int32),
+                ("roi_on", C.c_int32), ("planes", (C.c_double * 4) * 4), ("roi", C.c_double * 6)]
 
 
 class sg_render_stats(C.Structure):
@@ -136,6 +141,11 @@ def make_view(v) -> sg_view:
     o.tan_left, o.tan_right = float(v["tan_left"]), float(v["tan_right"])
     o.tan_bottom, o.tan_top = float(v["tan_bottom"]), float(v["tan_top"])
     o.width, o.height = int(v["width"]), int(v["height"])
+    lens = v.get("lens") or (0.0, 0.0, 0.0, 0.0)
+    for i in range(4):
+        o.lens[i] = float(lens[i])
+    lim = _ptr(v.get("ray_limit"))
+    o.ray_limit = lim.value if lim is not None else None
     return o
 
 
@@ -161,7 +171,19 @@ def make_params(p=None) -> sg_render_params:
     if p.get("gather", 0):
         flags |= SG_GATHER
     o.flags = int(p.get("flags", flags))
-    o.reserved = int(p.get("reserved", 0))
+    model = p.get("model", SG_MODEL_EMISSION_ABSORPTION)
+    o.model = MODELS[model] if isinstance(model, str) else int(model)
+    planes = list(p.get("planes") or ())
+    o.n_planes = int(p.get("n_planes", len(planes)))
+    for j, q in enumerate(planes[:4]):
+        for i in range(4):
+            o.planes[j][i] = float(q[i])
+    roi = p.get("roi")
+    o.roi_on = int(p.get("roi_on", roi is not None))
+    if roi is not None:
+        r = np.asarray(roi, dtype=np.float64).reshape(6)
+        for i in range(6):
+            o.roi[i] = float(r[i])
     return o
 
 

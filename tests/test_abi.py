@@ -80,7 +80,7 @@ int main(void) {
 
 
 def test_version_and_status_strings(sg):
-    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 1
+    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 2
     for code, name in [(0, "SG_OK"), (-1, "SG_ERR_INVALID_ARG"), (-2, "SG_ERR_OUT_OF_MEMORY"),
                        (-3, "SG_ERR_DEVICE"), (-4, "SG_ERR_STATE"), (-5, "SG_ERR_UNSUPPORTED")]:
         assert sg.sg_status_string(code) == name
