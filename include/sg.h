@@ -256,6 +256,68 @@ sg_status sg_set_kernel_timing(sg_volume *vol, int32_t enable);
 sg_status sg_get_kernel_timing(sg_volume *vol, int32_t *renders,
                                double *cutmap_ms, double *raycast_ms);
 
+/* ---------------------------------------------------------------------
+ * Launch configuration and autotuning (batched uneven views, Sec 5.3 per-eye
+ * rendering at scale). A wave renders 8x8 pixels; the knobs below change
+ * only how that work is laid out on the device, never a sample position, so
+ * every configuration renders the same image bit for bit.
+ */
+typedef struct {
+  int32_t kernel;      /* 0 = staged (brick regions copied to LDS per wave),
+                          1 = gather (stencils read the brick pool)          */
+  int32_t tile;        /* workgroup screen tile edge in pixels: 8, 16, 32
+                          (1, 4 or 4 waves per workgroup; at 32 each wave
+                          renders four 8x8 tiles in turn)                  */
+  int32_t block;       /* edge in pixels of the screen blocks dealt to the
+                          XCDs in turn: 32, 64 or 128, >= tile              */
+  int32_t stage_bytes; /* LDS staging bytes per wave (staged): 1024..32768,
+                          a multiple of 16                                 */
+  int32_t persistent;  /* 1: one resident grid whose waves take 8x8 tiles
+                          from per-XCD queues; 0: one workgroup per tile    */
+} sg_launch_config;
+/* Default: {0, 16, 64, 8192, 0}. NULL config restores the default.
+ * Errors: SG_ERR_INVALID_ARG (out of range), SG_ERR_UNSUPPORTED (the tile's
+ * LDS need exceeds 160 KiB). SG_GATHER in a render's flags overrides
+ * `kernel` for that render. */
+sg_status sg_set_launch_config(sg_volume *vol, const sg_launch_config *config);
+sg_status sg_get_launch_config(const sg_volume *vol, sg_launch_config *config);
+/* Time launch configurations on this render (coordinate descent over the
+ * five fields, two sweeps, each candidate timed over `repeats` renders after
+ * one warm-up render, with events on hip_stream) and keep the fastest as the
+ * volume's configuration. out_rgba receives the renders. best and best_ms
+ * (either may be NULL) receive the choice and its time per render.
+ * Synchronises hip_stream. SG_GATHER must be clear (the kernel is tuned). */
+sg_status sg_autotune(sg_volume *vol, int32_t n_views, const sg_view *views,
+                      const sg_render_params *params, float *const *out_rgba,
+                      int32_t repeats, sg_launch_config *best, double *best_ms,
+                      void *hip_stream);
+
+/* ---------------------------------------------------------------------
+ * Render graphs: a render prepared once as a HIP graph (cut-map kernel,
+ * queue reset when persistent, ray-casting kernel) and replayed per frame
+ * without host-side preparation. The graph owns its view table, cut map
+ * and queues; it keeps the volume's launch configuration, the params and
+ * the output pointers given at creation. Between launches the views may be
+ * re-posed (same sizes); transfer-function tables and brick contents may
+ * change (they are read at replay), but a different table size or value
+ * domain makes sg_render_graph_launch return SG_ERR_STATE. Launches of one
+ * graph must not overlap (they share its scratch); the volume must outlive
+ * the graph. */
+typedef struct sg_render_graph sg_render_graph; /* opaque */
+sg_status sg_render_graph_create(sg_volume *vol, int32_t n_views,
+                                 const sg_view *views,
+                                 const sg_render_params *params,
+                                 float *const *out_rgba, float *const *out_depth,
+                                 sg_render_graph **out);
+/* New camera poses / lens / ray limits for the next launches (view sizes
+ * must match creation). Stream-ordered on hip_stream. */
+sg_status sg_render_graph_set_views(sg_render_graph *graph, const sg_view *views,
+                                    void *hip_stream);
+/* Commit pending volume work, then replay the graph on hip_stream. */
+sg_status sg_render_graph_launch(sg_render_graph *graph, void *hip_stream);
+/* Synchronises the device, then frees the graph and its scratch. */
+sg_status sg_render_graph_destroy(sg_render_graph *graph);
+
 /* Bytes of device memory the volume holds (pool, tables, scratch). */
 sg_status sg_volume_memory(const sg_volume *vol, uint64_t *bytes);
 

@@ -84,6 +84,7 @@ void free_all(Volume* v) {
   hipFree(v->empty);
   hipFree(v->info);
   hipFree(v->tf);
+  if (v->queue) hipFree(v->queue);
   hipFree(v->cutmap);
   hipFree(v->view_dev);
   hipFree(v->mb_bits);

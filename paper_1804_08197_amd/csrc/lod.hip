@@ -96,15 +96,29 @@ CutGeom cut_geom(const Volume* v, int bias, bool lod) {
 
 }  // namespace
 
-sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, hipStream_t s) {
+sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
+                        bool lod, int32_t* cutmap, Launch* out) {
   CutGeom g = cut_geom(v, bias, lod);
   int64_t total = (int64_t)n_views * g.cells;
   int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(cutmap_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256),
-                     0, s, g, dviews, n_views, v->cutmap);
-  SG_HIP(hipGetLastError());
+  out->func = reinterpret_cast<const void*>(cutmap_kernel);
+  out->grid = dim3((unsigned)std::max<int64_t>(blocks, 1));
+  out->block = dim3(256);
+  out->lds = 0;
+  out->arg.clear();
+  out->push(g);
+  out->push(dviews);
+  out->push(n_views);
+  out->push(cutmap);
   return SG_OK;
+}
+
+sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
+                        bool lod, hipStream_t s) {
+  Launch l;
+  sg_status st = cutmap_launch(v, dviews, n_views, bias, lod, v->cutmap, &l);
+  if (st != SG_OK) return st;
+  return l.run(s);
 }
 
 }  // namespace sg

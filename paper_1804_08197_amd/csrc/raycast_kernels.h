@@ -499,22 +499,31 @@ __device__ __forceinline__ void write_pixel(Ray& r, const RenderArgs& a, const V
   if (V.depth) V.depth[pix] = r.depth;
 }
 
-// Tile of this lane. Workgroups go to the 8 XCDs round-robin (workgroup i
-// on XCD i % 8). Tiles are grouped into blocks of 4x4 tiles (64x64 pixels,
-// about one brick's footprint at the selected level) and the blocks are dealt
-// to the XCDs in turn: the 16 tiles of a block share one XCD's L2, and every
-// XCD gets an even share of the image (heavy regions are spread out).
+// Work decomposition. A wave renders a tile of 8x8 pixels. A workgroup
+// covers a square screen tile of 2^tile_log wave tiles per side with
+// 2^wg_log waves (1 wave for 8x8 pixels, 4 for 16x16 and for 32x32, where
+// each wave takes four wave tiles in turn). Workgroup tiles are grouped into
+// square blocks of 2^bt_log wave tiles per side (64x64 pixels by default,
+// about one brick's footprint at the selected level), and the blocks of all
+// views are dealt to the 8 XCDs in turn (workgroup i runs on XCD i % 8,
+// each XCD with its own L2): the tiles of a block share one L2 and every
+// XCD gets an even share of the image.
+//  * direct grid: workgroup i on XCD x = i % 8 takes workgroup tile
+//    (i / 8) % (tiles per block) of that XCD's block (i / 8) / (tiles per
+//    block);
+//  * persistent grid: every wave takes wave tiles one at a time from its
+//    XCD's queue (an atomic counter) in the same order, until the XCD's
+//    blocks are exhausted.
 struct TileLane {
   int view, px, py;
   bool in_image;
   bool tile_valid;
 };
 
-__device__ __forceinline__ TileLane tile_lane(const RenderArgs& a) {
-  const int bid = blockIdx.x;
-  const int x = bid & 7, j = bid >> 3;
-  const int block = (j >> 4) * 8 + x;
-  const int t = j & 15;
+// Lane's pixel of wave tile k (row-major) of workgroup tile t in global
+// block `block`.
+__device__ __forceinline__ TileLane tile_at(const RenderArgs& a, int block, int t, int k,
+                                            int lane) {
   TileLane out;
   out.view = 0;
   out.px = out.py = 0;
@@ -529,30 +538,58 @@ __device__ __forceinline__ TileLane tile_lane(const RenderArgs& a) {
   const ViewDev& V = a.views[lo];
   const int lb = block - V.block_begin;
   const int bx = lb % V.blocks_x, by = lb / V.blocks_x;
-  const int tx = bx * 4 + (t & 3), ty = by * 4 + (t >> 2);
+  const int per_row_log = a.bt_log - a.tile_log;  // workgroup tiles per block row (log2)
+  const int gx = t & ((1 << per_row_log) - 1), gy = t >> per_row_log;
+  const int tx = (bx << a.bt_log) + (gx << a.tile_log) + (k & ((1 << a.tile_log) - 1));
+  const int ty = (by << a.bt_log) + (gy << a.tile_log) + (k >> a.tile_log);
   out.tile_valid = tx < V.tiles_x && ty < V.tiles_y;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   out.view = lo;
-  out.px = tx * 16 + (w & 1) * 8 + (lane & 7);
-  out.py = ty * 16 + (w >> 1) * 8 + (lane >> 3);
+  out.px = tx * 8 + (lane & 7);
+  out.py = ty * 8 + (lane >> 3);
   out.in_image = out.tile_valid && out.px < V.W && out.py < V.H;
   return out;
+}
+
+// Direct grid: the it-th tile of this wave (it < 4^tile_log / 2^wg_log).
+__device__ __forceinline__ TileLane tile_lane(const RenderArgs& a, int it) {
+  const int bid = blockIdx.x;
+  const int x = bid & 7, j = bid >> 3;
+  const int tiles_log = 2 * (a.bt_log - a.tile_log);  // workgroup tiles per block (log2)
+  const int block = ((j >> tiles_log) << 3) + x;
+  const int t = j & ((1 << tiles_log) - 1);
+  const int k = (it << a.wg_log) + (int)(threadIdx.x >> 6);
+  return tile_at(a, block, t, k, threadIdx.x & 63);
+}
+
+// Persistent grid: the wave's next tile from its XCD's queue; false once the
+// XCD's blocks are exhausted (every wave reaches that point: the counter
+// only grows). Called with the whole wave active.
+__device__ __forceinline__ bool next_tile(const RenderArgs& a, TileLane& tl) {
+  const int x = blockIdx.x & 7, lane = threadIdx.x & 63;
+  uint32_t item = 0;
+  if (lane == 0) item = atomicAdd(a.queue + x, 1u);
+  item = (uint32_t)__builtin_amdgcn_readlane((int)item, 0);
+  const int per_block_log = 2 * a.bt_log;          // wave tiles per block (log2)
+  const int block = (int)((item >> per_block_log) << 3) + x;
+  if (block >= a.total_blocks) return false;
+  const int k = (int)(item & ((1u << per_block_log) - 1));
+  const int wt_log = 2 * a.tile_log;               // wave tiles per workgroup tile (log2)
+  tl = tile_at(a, block, k >> wt_log, k & ((1 << wt_log) - 1), lane);
+  return true;
 }
 
 template <int CH>
 __device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
   const int ntf = CH * (a.tf_n + 1);
-  for (int i = threadIdx.x; i < ntf; i += 256) s_tf[i] = reinterpret_cast<const float4*>(a.tf)[i];
+  for (int i = threadIdx.x; i < ntf; i += blockDim.x)
+    s_tf[i] = reinterpret_cast<const float4*>(a.tf)[i];
   __syncthreads();
 }
 
 // ------------------------------------------------------------ gather kernel
 template <typename T, int CH, bool STATS, int MODEL>
-__global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
-  extern __shared__ float4 s_tf[];
-  load_tf<CH>(a, s_tf);
-  const TileLane tl = tile_lane(a);
-  if (!tl.in_image) return;
+__device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* s_tf,
+                                             const TileLane& tl) {
   const ViewDev& V = a.views[tl.view];
   const bool want_depth = V.depth != nullptr;
   int mb_key[CH][3];
@@ -578,6 +615,28 @@ __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
   if (STATS) {
     if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
     atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
+  }
+}
+
+// LOOP: the wave renders several tiles (persistent grid, or a direct grid
+// with more wave tiles than waves per workgroup); without it exactly one.
+// The two are separate instances because the loop costs registers.
+template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
+__global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
+  extern __shared__ float4 s_tf[];
+  load_tf<CH>(a, s_tf);
+  if (!LOOP) {
+    const TileLane tl = tile_lane(a, 0);
+    if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+  } else if (a.persistent) {
+    TileLane tl;
+    while (next_tile(a, tl))
+      if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+  } else {
+    for (int it = 0; it < a.wave_tiles; ++it) {
+      const TileLane tl = tile_lane(a, it);
+      if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+    }
   }
 }
 
@@ -671,22 +730,16 @@ __device__ __forceinline__ int pick(const int v[3], int m) {
   return m == 0 ? v[0] : (m == 1 ? v[1] : v[2]);
 }
 
+// One wave tile of the staged kernel (the whole wave active).
 template <typename T, int CH, bool STATS, int MODEL>
-__global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
-  extern __shared__ float4 smem[];
-  float4* s_tf = smem;
-  load_tf<CH>(a, s_tf);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
-                                  w * a.stage_bytes);
+__device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s_tf, T* stage,
+                                            const TileLane& tl) {
+  const int lane = threadIdx.x & 63;
   // staging moves chunks of kRowAlignBytes (pool rows are aligned to
   // them); the capacity per channel is a whole number of chunks so every
   // channel's region starts chunk-aligned in LDS
   constexpr int align = kRowAlignBytes / (int)sizeof(T);  // voxels per chunk
   const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~(align - 1);
-
-  const TileLane tl = tile_lane(a);
-  if (!tl.tile_valid) return;  // uniform over the workgroup; no barrier follows
   const ViewDev& V = a.views[tl.view];
   const bool want_depth = V.depth != nullptr;
   int mb_key[CH][3];
@@ -900,58 +953,60 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   }
 }
 
-template <typename K>
-sg_status allow_lds(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  return SG_OK;
+template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
+__global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
+  extern __shared__ float4 smem[];
+  float4* s_tf = smem;
+  load_tf<CH>(a, s_tf);
+  T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + CH * (a.tf_n + 1)) +
+                                  (threadIdx.x >> 6) * a.stage_bytes);
+  // no workgroup barrier follows: the waves work independently from here
+  if (!LOOP) {
+    const TileLane tl = tile_lane(a, 0);
+    if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+  } else if (a.persistent) {
+    TileLane tl;
+    while (next_tile(a, tl))
+      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+  } else {
+    for (int it = 0; it < a.wave_tiles; ++it) {
+      const TileLane tl = tile_lane(a, it);
+      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+    }
+  }
 }
 
-template <typename T, int CH, int MODEL>
-sg_status launch_t(const RenderArgs& a, bool stats, bool gather, hipStream_t s) {
-  const size_t tf_lds = (size_t)CH * (a.tf_n + 1) * sizeof(float4);
-  if (gather) {
-    if (stats)
-      hipLaunchKernelGGL((raycast_gather<T, CH, true, MODEL>), dim3(a.grid), dim3(256), tf_lds,
-                         s, a);
-    else
-      hipLaunchKernelGGL((raycast_gather<T, CH, false, MODEL>), dim3(a.grid), dim3(256), tf_lds,
-                         s, a);
-  } else {
-    const size_t lds = tf_lds + 4 * (size_t)a.stage_bytes;
-    sg_status st = stats ? allow_lds(raycast_staged<T, CH, true, MODEL>, lds)
-                         : allow_lds(raycast_staged<T, CH, false, MODEL>, lds);
-    if (st != SG_OK) return st;
-    if (stats)
-      hipLaunchKernelGGL((raycast_staged<T, CH, true, MODEL>), dim3(a.grid), dim3(256), lds, s,
-                         a);
-    else
-      hipLaunchKernelGGL((raycast_staged<T, CH, false, MODEL>), dim3(a.grid), dim3(256), lds, s,
-                         a);
-  }
-  SG_HIP(hipGetLastError());
-  return SG_OK;
+template <typename T, int CH, int MODEL, bool LOOP>
+const void* kernel_for(bool stats, bool gather) {
+  if (gather)
+    return stats ? reinterpret_cast<const void*>(raycast_gather<T, CH, true, MODEL, LOOP>)
+                 : reinterpret_cast<const void*>(raycast_gather<T, CH, false, MODEL, LOOP>);
+  return stats ? reinterpret_cast<const void*>(raycast_staged<T, CH, true, MODEL, LOOP>)
+               : reinterpret_cast<const void*>(raycast_staged<T, CH, false, MODEL, LOOP>);
 }
 
 template <typename T, int MODEL>
-sg_status launch_ch(const RenderArgs& a, int C, bool stats, bool gather, hipStream_t s) {
+const void* kernel_ch(int C, bool stats, bool gather, bool loop) {
   switch (C) {
-    case 1: return launch_t<T, 1, MODEL>(a, stats, gather, s);
-    case 2: return launch_t<T, 2, MODEL>(a, stats, gather, s);
-    case 3: return launch_t<T, 3, MODEL>(a, stats, gather, s);
-    default: return launch_t<T, 4, MODEL>(a, stats, gather, s);
+    case 1: return loop ? kernel_for<T, 1, MODEL, true>(stats, gather)
+                        : kernel_for<T, 1, MODEL, false>(stats, gather);
+    case 2: return loop ? kernel_for<T, 2, MODEL, true>(stats, gather)
+                        : kernel_for<T, 2, MODEL, false>(stats, gather);
+    case 3: return loop ? kernel_for<T, 3, MODEL, true>(stats, gather)
+                        : kernel_for<T, 3, MODEL, false>(stats, gather);
+    default: return loop ? kernel_for<T, 4, MODEL, true>(stats, gather)
+                         : kernel_for<T, 4, MODEL, false>(stats, gather);
   }
 }
 
 }  // namespace
 
-// Every kernel instance of one optical model, by voxel type and channels.
+// The ray-casting kernel of one optical model for a voxel type and channel
+// count (instrumented or not, staged or gather, one tile per wave or a loop).
 template <int MODEL>
-sg_status launch_model(int bpv, int channels, const RenderArgs& a, bool stats,
-                       hipStream_t s) {
-  if (bpv == 1) return launch_ch<uint8_t, MODEL>(a, channels, stats, a.gather != 0, s);
-  return launch_ch<uint16_t, MODEL>(a, channels, stats, a.gather != 0, s);
+const void* model_kernel(int bpv, int channels, bool stats, bool gather, bool loop) {
+  if (bpv == 1) return kernel_ch<uint8_t, MODEL>(channels, stats, gather, loop);
+  return kernel_ch<uint16_t, MODEL>(channels, stats, gather, loop);
 }
 
 }  // namespace sg

@@ -4,9 +4,9 @@
 
 namespace sg {
 
-sg_status launch_raycast_mip(int bpv, int channels, const RenderArgs& a, bool stats,
-                              hipStream_t s) {
-  return launch_model<kModelMip>(bpv, channels, a, stats, s);
+const void* raycast_kernel_mip(int bpv, int channels, bool stats, bool gather,
+                               bool loop) {
+  return model_kernel<kModelMip>(bpv, channels, stats, gather, loop);
 }
 
 }  // namespace sg

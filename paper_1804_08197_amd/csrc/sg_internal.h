@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,38 @@ sg_status hip_fail(hipError_t e, const char* what);
     hipError_t e_ = (call);                                      \
     if (e_ != hipSuccess) return ::sg::hip_fail(e_, #call);      \
   } while (0)
+
+// A kernel launch held as data: run on a stream, or added to a graph.
+struct Launch {
+  const void* func = nullptr;
+  dim3 grid{1, 1, 1}, block{1, 1, 1};
+  size_t lds = 0;
+  std::vector<std::vector<uint8_t>> arg;  // a copy of each kernel argument
+  template <typename X>
+  void push(const X& x) {
+    arg.emplace_back(sizeof(X));
+    std::memcpy(arg.back().data(), &x, sizeof(X));
+  }
+  std::vector<void*> ptrs() {
+    std::vector<void*> p;
+    for (auto& b : arg) p.push_back(b.data());
+    return p;
+  }
+  sg_status run(hipStream_t s) {
+    std::vector<void*> p = ptrs();
+    SG_HIP(hipLaunchKernel(func, grid, block, p.data(), lds, s));
+    return SG_OK;
+  }
+};
+
+// How the ray caster is launched (sg_launch_config in internal units).
+struct LaunchConfig {
+  int32_t gather = 0;       // 1: stencils read the pool (no LDS staging)
+  int32_t tile_log = 1;     // log2 edge of a workgroup tile in 8x8 wave tiles: 0..2
+  int32_t bt_log = 3;       // log2 edge of a screen block in 8x8 wave tiles: 2..4
+  int32_t stage_bytes = kStageBytesDefault;
+  int32_t persistent = 0;   // 1: persistent grid with per-XCD tile queues
+};
 
 // Node record, one per pyramid node (level L, brick b): used by the ray
 // caster to turn a cut-map entry into a box and a level.
@@ -105,6 +138,9 @@ struct Volume {
   int64_t mb_words = 0;
   uint64_t* counters = nullptr;  // device counters (stats only)
   uint64_t bytes = 0;
+  // launch configuration of the ray caster, and the persistent grid's queues
+  LaunchConfig cfg;
+  uint32_t* queue = nullptr;  // 8 counters
   // kernel timing (instrumentation)
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -164,6 +200,15 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         const sg_render_params* p, float* const* rgba,
                         float* const* depth, int32_t* const* nsamp,
                         hipStream_t s, int* total_blocks);
+// Checked host copy of the per-view constants (screen blocks of 2^bt_log
+// wave tiles per side) and the number of blocks over all views.
+sg_status build_views(const Volume* v, int n_views, const sg_view* views,
+                      const sg_render_params* p, float* const* rgba, float* const* depth,
+                      int32_t* const* nsamp, int bt_log, std::vector<ViewDev>* hv,
+                      int64_t* total_blocks);
+// The cut-map kernel for views already on the device, writing `cutmap`.
+sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
+                        bool lod, int32_t* cutmap, Launch* out);
 
 struct RenderArgs {
   const uint8_t* pool;
@@ -190,6 +235,12 @@ struct RenderArgs {
   int32_t total_blocks;  // 4x4-tile blocks over all views
   int32_t grid;          // workgroups launched
   int32_t tf_n;
+  int32_t tile_log;     // log2 edge of a workgroup tile in 8x8 wave tiles
+  int32_t wg_log;       // log2 waves per workgroup (min(2, 2 tile_log))
+  int32_t wave_tiles;   // wave tiles per wave in a direct grid
+  int32_t bt_log;       // log2 edge of a screen block in 8x8 wave tiles
+  int32_t persistent;   // 1: waves take tiles from the per-XCD queues
+  uint32_t* queue;      // 8 counters, zero at launch (persistent grid)
   int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
@@ -204,15 +255,14 @@ struct RenderArgs {
   double roi[6];        // region of interest lo xyz, hi xyz
 };
 
-sg_status launch_raycast(Volume* v, const RenderArgs& a, bool stats,
-                         hipStream_t s);
+// The ray-casting launch (kernel, grid, LDS) for arguments `a`; a.grid is
+// set to the grid chosen.
+sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out);
 // Kernel instances per optical model (one translation unit each).
-sg_status launch_raycast_absorption(int bpv, int channels, const RenderArgs& a, bool stats,
-                                    hipStream_t s);
-sg_status launch_raycast_emission(int bpv, int channels, const RenderArgs& a, bool stats,
-                                  hipStream_t s);
-sg_status launch_raycast_mip(int bpv, int channels, const RenderArgs& a, bool stats,
-                             hipStream_t s);
+const void* raycast_kernel_absorption(int bpv, int channels, bool stats, bool gather,
+                                      bool loop);
+const void* raycast_kernel_emission(int bpv, int channels, bool stats, bool gather, bool loop);
+const void* raycast_kernel_mip(int bpv, int channels, bool stats, bool gather, bool loop);
 
 }  // namespace sg
 

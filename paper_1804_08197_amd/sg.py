@@ -62,6 +62,11 @@ class sg_render_stats(C.Structure):
                 ("staged_bytes", C.c_uint64)]
 
 
+class sg_launch_config(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("tile", C.c_int32), ("block", C.c_int32),
+                ("stage_bytes", C.c_int32), ("persistent", C.c_int32)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libsg.so is not built (run __graft_entry__.build()); there is no "
                       "fallback implementation")
@@ -87,6 +92,17 @@ _lib.sg_volume_memory.argtypes = [_P, C.POINTER(C.c_uint64)]
 _lib.sg_set_kernel_timing.argtypes = [_P, C.c_int32]
 _lib.sg_get_kernel_timing.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
+_lib.sg_set_launch_config.argtypes = [_P, C.POINTER(sg_launch_config)]
+_lib.sg_get_launch_config.argtypes = [_P, C.POINTER(sg_launch_config)]
+_lib.sg_autotune.argtypes = [_P, C.c_int32, C.POINTER(sg_view), C.POINTER(sg_render_params),
+                             C.POINTER(_P), C.c_int32, C.POINTER(sg_launch_config),
+                             C.POINTER(C.c_double), _P]
+_lib.sg_render_graph_create.argtypes = [_P, C.c_int32, C.POINTER(sg_view),
+                                        C.POINTER(sg_render_params), C.POINTER(_P),
+                                        C.POINTER(_P), C.POINTER(_P)]
+_lib.sg_render_graph_set_views.argtypes = [_P, C.POINTER(sg_view), _P]
+_lib.sg_render_graph_launch.argtypes = [_P, _P]
+_lib.sg_render_graph_destroy.argtypes = [_P]
 _lib.sg_status_string.argtypes = [C.c_int]
 _lib.sg_status_string.restype = C.c_char_p
 _lib.sg_last_error.restype = C.c_char_p
@@ -94,7 +110,9 @@ _lib.sg_abi_version.restype = C.c_int32
 for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_build_lod",
            "sg_volume_commit", "sg_set_transfer_function", "sg_render_views",
            "sg_render_views_stats", "sg_get_lod_cut", "sg_volume_memory",
-           "sg_set_kernel_timing", "sg_get_kernel_timing"):
+           "sg_set_kernel_timing", "sg_get_kernel_timing", "sg_set_launch_config",
+           "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
+           "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -311,3 +329,81 @@ def sg_get_kernel_timing(vol):
     _check(_lib.sg_get_kernel_timing(vol, C.byref(n), C.byref(a), C.byref(b)),
            "sg_get_kernel_timing")
     return int(n.value), float(a.value), float(b.value)
+
+
+# ------------------------------------------------- launch configuration
+LAUNCH_FIELDS = ("kernel", "tile", "block", "stage_bytes", "persistent")
+DEFAULT_LAUNCH = {"kernel": 0, "tile": 16, "block": 64, "stage_bytes": 8192, "persistent": 0}
+
+
+def _launch_struct(cfg) -> sg_launch_config:
+    c = dict(DEFAULT_LAUNCH, **(cfg or {}))
+    o = sg_launch_config()
+    for k in LAUNCH_FIELDS:
+        setattr(o, k, int(c[k]))
+    return o
+
+
+def _launch_dict(o: sg_launch_config) -> dict:
+    return {k: int(getattr(o, k)) for k in LAUNCH_FIELDS}
+
+
+def sg_set_launch_config(vol, cfg=None):
+    """cfg: dict with kernel / tile / block / stage_bytes / persistent, or
+    None for the default."""
+    c = _launch_struct(cfg) if cfg is not None else None
+    _check(_lib.sg_set_launch_config(vol, C.byref(c) if c is not None else None),
+           "sg_set_launch_config")
+
+
+def sg_get_launch_config(vol) -> dict:
+    o = sg_launch_config()
+    _check(_lib.sg_get_launch_config(vol, C.byref(o)), "sg_get_launch_config")
+    return _launch_dict(o)
+
+
+def sg_autotune(vol, views, params, out_rgba, repeats=3, stream=None):
+    """Tune the volume's launch configuration on this render; returns
+    (config dict, ms per render)."""
+    n = len(views)
+    varr = _views(views)
+    p = make_params(params)
+    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+    best = sg_launch_config()
+    ms = C.c_double()
+    _check(_lib.sg_autotune(vol, n, varr, C.byref(p), rgba, int(repeats), C.byref(best),
+                            C.byref(ms), _stream(stream)), "sg_autotune")
+    return _launch_dict(best), float(ms.value)
+
+
+class RenderGraph:
+    """A render prepared once as a HIP graph and replayed per frame."""
+
+    def __init__(self, vol, views, params, out_rgba, out_depth=None):
+        n = len(views)
+        self.n = n
+        varr = _views(views)
+        p = make_params(params)
+        rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+        dep = None
+        if out_depth is not None:
+            dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None)
+                                     for o in out_depth])
+        h = C.c_void_p()
+        _check(_lib.sg_render_graph_create(vol, n, varr, C.byref(p), rgba, dep, C.byref(h)),
+               "sg_render_graph_create")
+        self.handle = h
+
+    def set_views(self, views, stream=None):
+        assert len(views) == self.n
+        _check(_lib.sg_render_graph_set_views(self.handle, _views(views), _stream(stream)),
+               "sg_render_graph_set_views")
+
+    def launch(self, stream=None):
+        _check(_lib.sg_render_graph_launch(self.handle, _stream(stream)),
+               "sg_render_graph_launch")
+
+    def destroy(self):
+        if self.handle is not None:
+            _check(_lib.sg_render_graph_destroy(self.handle), "sg_render_graph_destroy")
+            self.handle = None

@@ -60,6 +60,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(sg_view, width), offsetof(sg_render_params, lod_bias),
          offsetof(sg_render_params, flags), offsetof(sg_render_params, depth_alpha),
          offsetof(sg_render_stats, microblocks));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(sg_view, lens), offsetof(sg_view, ray_limit),
+         offsetof(sg_render_params, model), offsetof(sg_render_params, planes),
+         offsetof(sg_render_params, roi), sizeof(sg_launch_config));
   return 0;
 }
 '''
@@ -77,6 +80,10 @@ int main(void) {
     assert offs == [sg.sg_view.width.offset, sg.sg_render_params.lod_bias.offset,
                     sg.sg_render_params.flags.offset, sg.sg_render_params.depth_alpha.offset,
                     sg.sg_render_stats.microblocks.offset]
+    more = [int(x) for x in lines[2].split()]
+    assert more == [sg.sg_view.lens.offset, sg.sg_view.ray_limit.offset,
+                    sg.sg_render_params.model.offset, sg.sg_render_params.planes.offset,
+                    sg.sg_render_params.roi.offset, C.sizeof(sg.sg_launch_config)]
 
 
 def test_version_and_status_strings(sg):

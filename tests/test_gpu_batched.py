@@ -1,0 +1,203 @@
+"""Batched uneven views: launch configurations, graphs and the autotuner.
+
+Every launch configuration (kernel flavour, workgroup tile, XCD block, LDS
+staging size, direct or persistent grid) must render the same image bit for
+bit, so parity with the oracle carries over from the default configuration
+(checked here on sampled pixels too). Render graphs replay equal to eager
+renders, across re-posing and transfer-function edits; the autotuner's
+choice is one of those configurations.
+"""
+import itertools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+from tests.helpers import ERT, TOL, bracket_error, gpu_volume, oracle_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU (no CPU fallback exists)"
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def uneven_views(seed=1004, n=7):
+    vs = gen.orbit_views((64, 64, 64), (1.5 * 221.7, 4 * 221.7), n, seed, (96, 700), (96, 700),
+                         tan_top=math.tan(math.radians(30)))
+    # degenerate sizes: a single pixel and a ragged sliver
+    vs.append(dict(gen.view(gen.look_at((-300.0, 90.0, 40.0), (64, 64, 64)), 1, 1, 0.2)))
+    vs.append(dict(gen.view(gen.look_at((40.0, -350.0, 120.0), (64, 64, 64)), 9, 203, 0.6)))
+    return vs
+
+
+@pytest.fixture(scope="module")
+def blobs():
+    from paper_1804_08197_amd import sg
+    vol = gen.blobs128()
+    tf = gen.tf_identity()
+    h = gpu_volume([vol], 32, 3, [tf], [(0, 255)])
+    yield h, vol, tf
+    sg.sg_volume_destroy(h)
+
+
+def render(h, views, params):
+    import torch
+
+    from paper_1804_08197_amd import sg
+    outs = [torch.full((v["height"], v["width"], 4), float("nan"), device="cuda") for v in views]
+    sg.sg_render_views(h, views, params, outs)
+    torch.cuda.synchronize()
+    return outs
+
+
+CONFIGS = [dict(kernel=k, tile=t, block=b, stage_bytes=s, persistent=p)
+           for k, t, b, s, p in itertools.product((0, 1), (8, 16, 32), (32, 64, 128),
+                                                  (4096, 16384), (0, 1))
+           if b >= t and not (k == 1 and s == 16384)]
+
+
+def test_every_launch_config_renders_the_same_image(blobs):
+    import torch
+
+    from paper_1804_08197_amd import sg
+    h, _, _ = blobs
+    views = uneven_views()
+    params = {"ert": ERT, "tau": 1.0}
+    sg.sg_set_launch_config(h, None)
+    ref = render(h, views, params)
+    ref_stats = sg.sg_render_views_stats(h, views, params,
+                                         [torch.empty_like(o) for o in ref])
+    log("%d configurations, %d views" % (len(CONFIGS), len(views)))
+    try:
+        for cfg in CONFIGS:
+            sg.sg_set_launch_config(h, cfg)
+            assert sg.sg_get_launch_config(h) == cfg
+            got = render(h, views, params)
+            for i, (a, b) in enumerate(zip(ref, got)):
+                assert torch.equal(a, b), (cfg, i)
+        # instrumented persistent render counts the same samples
+        sg.sg_set_launch_config(h, dict(kernel=0, tile=32, block=64, stage_bytes=8192,
+                                        persistent=1))
+        st = sg.sg_render_views_stats(h, views, params, [torch.empty_like(o) for o in ref])
+        assert st["total_samples"] == ref_stats["total_samples"]
+        assert st["microblocks"] == ref_stats["microblocks"]
+    finally:
+        sg.sg_set_launch_config(h, None)
+
+
+def test_persistent_grid_parity_on_sampled_pixels(blobs):
+    from paper_1804_08197_amd import sg
+    h, vol, tf = blobs
+    views = uneven_views(seed=2005, n=4)
+    params = {"ert": ERT, "tau": 1.0}
+    sg.sg_set_launch_config(h, dict(kernel=0, tile=16, block=128, stage_bytes=8192,
+                                    persistent=1))
+    try:
+        got = render(h, views, params)
+    finally:
+        sg.sg_set_launch_config(h, None)
+    sc = oracle_scene([vol], 32, 3, [tf], [(0, 255)])
+    rng = np.random.default_rng(7)
+    for i, v in enumerate(views):
+        n = min(300, v["width"] * v["height"])
+        pix = np.stack([rng.integers(0, v["width"], n), rng.integers(0, v["height"], n)], 1)
+        refs = [sc.render(v, dict(params, ert=e), pixels=pix) for e in (ERT, ERT - 1e-5,
+                                                                        ERT + 1e-5)]
+        g = got[i].cpu().numpy().astype(np.float64)[pix[:, 1], pix[:, 0]]
+        best, _ = bracket_error(g, refs)
+        assert best.max() <= TOL
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_graph_replays_equal_eager_renders(blobs, persistent):
+    import torch
+
+    from paper_1804_08197_amd import sg
+    h, _, tf = blobs
+    views = uneven_views(n=3)
+    params = {"ert": ERT, "tau": 1.0}
+    sg.sg_set_launch_config(h, dict(kernel=0, tile=16, block=64, stage_bytes=8192,
+                                    persistent=persistent))
+    try:
+        outs = [torch.zeros(v["height"], v["width"], 4, device="cuda") for v in views]
+        g = sg.RenderGraph(h, views, params, outs)
+        try:
+            ref = render(h, views, params)
+            for rep in range(3):
+                for o in outs:
+                    o.fill_(float("nan"))
+                g.launch()
+                torch.cuda.synchronize()
+                for a, b in zip(ref, outs):
+                    assert torch.equal(a, b), rep
+                # eager work on the same volume between replays
+                render(h, uneven_views(seed=77, n=2), params)
+            # re-posed views
+            moved = uneven_views(seed=99, n=3)
+            moved = [dict(m, width=v["width"], height=v["height"]) for m, v in zip(moved, views)]
+            g.set_views(moved)
+            g.launch()
+            torch.cuda.synchronize()
+            ref2 = render(h, moved, params)
+            for a, b in zip(ref2, outs):
+                assert torch.equal(a, b)
+            # new table contents (same size and domain) are picked up
+            sg.sg_set_transfer_function(h, 0, np.ascontiguousarray(tf[::-1]), 0, 255)
+            g.launch()
+            torch.cuda.synchronize()
+            ref3 = render(h, moved, params)
+            for a, b in zip(ref3, outs):
+                assert torch.equal(a, b)
+            # a different table size invalidates the graph
+            sg.sg_set_transfer_function(h, 0, gen.tf_identity(128), 0, 255)
+            with pytest.raises(sg.SgError) as ex:
+                g.launch()
+            assert ex.value.status == sg.SG_ERR_STATE
+        finally:
+            g.destroy()
+            sg.sg_set_transfer_function(h, 0, tf, 0, 255)
+    finally:
+        sg.sg_set_launch_config(h, None)
+
+
+def test_autotune_picks_a_valid_config_with_identical_output(blobs):
+    import torch
+
+    from paper_1804_08197_amd import sg
+    h, _, _ = blobs
+    views = uneven_views(n=5)
+    params = {"ert": ERT, "tau": 1.0}
+    sg.sg_set_launch_config(h, None)
+    ref = render(h, views, params)
+    outs = [torch.empty_like(o) for o in ref]
+    try:
+        cfg, ms = sg.sg_autotune(h, views, params, outs, repeats=1)
+        log("autotuned %s: %.3f ms" % (cfg, ms))
+        assert sg.sg_get_launch_config(h) == cfg
+        assert ms > 0
+        got = render(h, views, params)
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b)
+    finally:
+        sg.sg_set_launch_config(h, None)
+
+
+def test_bad_launch_configs_are_rejected(blobs):
+    from paper_1804_08197_amd import sg
+    h, _, _ = blobs
+    for bad in (dict(tile=24), dict(block=16), dict(tile=32, block=32, stage_bytes=100),
+                dict(persistent=2), dict(kernel=3), dict(tile=64, block=64)):
+        with pytest.raises(sg.SgError) as ex:
+            sg.sg_set_launch_config(h, bad)
+        assert ex.value.status == sg.SG_ERR_INVALID_ARG
+    assert sg.sg_get_launch_config(h) == sg.DEFAULT_LAUNCH
