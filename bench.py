@@ -68,6 +68,9 @@ def main():
                          "3 times (calibrates the HBM byte counters) and exit")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch configuration (no autotuning in set-up)")
+    ap.add_argument("--launch", default=None,
+                    help="explicit launch configuration kernel,tile,block,stage_bytes,persistent "
+                         "(no autotuning); profiles use the one the benchmark chose")
     ap.add_argument("--workload", default="tubes", choices=("tubes", "batched64"),
                     help="tubes: the bricked stereo frame (default, the headline); "
                          "batched64: 64 uneven views of the 128^3 blob volume in one call")
@@ -119,7 +122,10 @@ def main():
     outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
     npix = sum(v["width"] * v["height"] for v in views)
     launch = sg.sg_get_launch_config(h)
-    if not args.no_autotune:
+    if args.launch:
+        launch = dict(zip(sg.LAUNCH_FIELDS, (int(x) for x in args.launch.split(","))))
+        sg.sg_set_launch_config(h, launch)
+    elif not args.no_autotune:
         # set-up, untimed: pick the launch configuration on this frame (every
         # configuration renders the same image)
         launch, tuned_ms = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
