@@ -93,6 +93,13 @@ def lib():
         L.sgo_lod_cut.argtypes = [i3, C.c_int32, C.c_int32, C.POINTER(View), C.c_double,
                                   C.c_int32, C.c_int32, C.POINTER(C.c_uint64), C.c_int64]
         L.sgo_lod_cut.restype = C.c_int64
+        L.sgo_lod_cut_resident.argtypes = [i3, C.c_int32, C.c_int32, C.POINTER(View),
+                                           C.c_double, C.c_int32, C.c_int32,
+                                           C.POINTER(C.c_uint64), C.c_int64,
+                                           C.POINTER(C.c_uint64), C.c_int64,
+                                           C.POINTER(C.c_uint64), C.c_int64,
+                                           C.POINTER(C.c_int64)]
+        L.sgo_lod_cut_resident.restype = C.c_int64
         L.sgo_nodes_empty.argtypes = [C.POINTER(_Scene), C.POINTER(C.c_uint64), C.c_int64,
                                       C.POINTER(C.c_uint8)]
         L.sgo_nodes_empty_model.argtypes = [C.POINTER(_Scene), C.c_int32,
@@ -298,6 +305,28 @@ def lod_cut(dims0, B, levels, view: dict, tau=1.0, bias=0, lod=True) -> np.ndarr
                           int(bool(lod)), _ptr(out, C.c_uint64), n)
     assert m == n
     return out[:n]
+
+
+def lod_cut_resident(dims0, B, levels, view: dict, resident, tau=1.0, bias=0, lod=True):
+    """O18: (cut, requested) when only the node identifiers in `resident`
+    are in the cache (every top-level node must be)."""
+    v = make_view(view)
+    res = np.unique(np.asarray(resident, dtype=np.uint64))
+    res = np.ascontiguousarray(res if len(res) else np.zeros(1, np.uint64)[:0])
+    nreq = C.c_int64()
+    args = (_i3(dims0), int(B), int(levels), C.byref(v), float(tau), int(bias), int(bool(lod)),
+            _ptr(res, C.c_uint64) if len(res) else (C.c_uint64 * 1)(), len(res))
+    n = lib().sgo_lod_cut_resident(*args, None, 0, None, 0, C.byref(nreq))
+    if n == -2:
+        raise ValueError("a top-level node is not resident")
+    if n < 0:
+        raise ValueError("bad LOD arguments")
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    req = np.zeros(max(nreq.value, 1), dtype=np.uint64)
+    m = lib().sgo_lod_cut_resident(*args, _ptr(out, C.c_uint64), n, _ptr(req, C.c_uint64),
+                                   nreq.value, C.byref(nreq))
+    assert m == n
+    return out[:n], req[:nreq.value]
 
 
 class Scene:

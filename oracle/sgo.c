@@ -27,6 +27,9 @@
  *   O15 wrapped-space rays Sec 5.3 (rays spread uniformly over the wrapped image)
  *   O16 ray clipping      Sec 6 (cut plane tool, ROI tool), Sec 5.6 (rays
  *                         ending at the depth of opaque geometry)
+ *   O18 residency fallback Sec 5.2 (children missing from the cache are
+ *                         requested and the parent is rendered), Sec 4.2
+ *                         (least-recently-used chunk cache)
  *   O17 optical models    Sec 5.1 (emission-only, maximum intensity
  *                         projection, emission-absorption), Sec 5.6 (zero
  *                         alpha of the emission-only image)
@@ -492,6 +495,106 @@ int64_t sgo_lod_cut(const int32_t dims0[3], int32_t B, int32_t levels,
       }
   if (out && c.n <= cap) qsort(out, (size_t)c.n, sizeof(uint64_t), cmp_u64);
   return c.n;
+}
+
+/* O18: the cut when only some nodes are in the GPU cache (Sec 5.2: if one
+ * or more children of a block that does not suit are missing from the cache,
+ * they are added to the request queue and the block itself, one level
+ * coarser, is rendered). The traversal above with one change: a node that
+ * does not suit descends only when every existing child is resident;
+ * otherwise it is registered and its missing children are requested.
+ * `resident` is the ascending list of resident node identifiers; every
+ * top-level node must be in it (returns -2 otherwise). The requested
+ * identifiers (ascending, without repeats) go to req (first req_cap),
+ * their number to *n_req. Returns the cut size as sgo_lod_cut does. */
+typedef struct {
+  cut_ctx c;
+  const uint64_t *res;
+  int64_t n_res;
+  uint64_t *req;
+  int64_t n_req, req_cap;
+} res_ctx;
+
+static int is_resident(const res_ctx *r, uint64_t id) {
+  return bsearch(&id, r->res, (size_t)r->n_res, sizeof(uint64_t), cmp_u64) != NULL;
+}
+
+static void res_visit(res_ctx *r, int32_t L, const int32_t b[3]) {
+  cut_ctx *c = &r->c;
+  int32_t acc = c->lod_on ? sgo_node_accept(c->dims0, c->B, c->e, c->K,
+                                            c->bias, L, b)
+                          : (L == c->bias);
+  int32_t kids[8][3];
+  int nk = 0, all_res = 1;
+  if (!acc) {
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          int32_t cb[3] = {2 * b[0] + dx, 2 * b[1] + dy, 2 * b[2] + dz};
+          if (cb[0] < c->grid[L - 1][0] && cb[1] < c->grid[L - 1][1] &&
+              cb[2] < c->grid[L - 1][2]) {
+            memcpy(kids[nk++], cb, sizeof(cb));
+            if (!is_resident(r, sgo_node_id(L - 1, cb[0], cb[1], cb[2]))) all_res = 0;
+          }
+        }
+  }
+  if (acc || !all_res) {
+    if (c->n < c->cap) c->out[c->n] = sgo_node_id(L, b[0], b[1], b[2]);
+    c->n++;
+    for (int k = 0; k < nk; ++k) {
+      uint64_t id = sgo_node_id(L - 1, kids[k][0], kids[k][1], kids[k][2]);
+      if (is_resident(r, id)) continue;
+      if (r->n_req < r->req_cap) r->req[r->n_req] = id;
+      r->n_req++;
+    }
+    return;
+  }
+  for (int k = 0; k < nk; ++k) res_visit(r, L - 1, kids[k]);
+}
+
+int64_t sgo_lod_cut_resident(const int32_t dims0[3], int32_t B, int32_t levels,
+                             const sgo_view *v, double tau, int32_t bias,
+                             int32_t lod_on, const uint64_t *resident,
+                             int64_t n_resident, uint64_t *out, int64_t cap,
+                             uint64_t *req, int64_t req_cap, int64_t *n_req) {
+  if (levels < 1 || levels > SGO_MAX_LEVELS || bias < 0 || bias >= levels ||
+      !resident || !n_req)
+    return -1;
+  res_ctx r;
+  cut_ctx *c = &r.c;
+  c->dims0 = dims0;
+  c->B = B;
+  c->bias = bias;
+  c->lod_on = lod_on;
+  double e[3] = {v->cam_to_world[3], v->cam_to_world[7], v->cam_to_world[11]};
+  c->e = e;
+  c->K = sgo_lod_k(v, tau);
+  c->out = out;
+  c->n = 0;
+  c->cap = cap;
+  r.res = resident;
+  r.n_res = n_resident;
+  r.req = req;
+  r.n_req = 0;
+  r.req_cap = req_cap;
+  for (int32_t L = 0; L < levels; ++L) sgo_brick_grid(dims0, B, L, c->grid[L]);
+  int32_t T = levels - 1;
+  for (int32_t z = 0; z < c->grid[T][2]; ++z)
+    for (int32_t y = 0; y < c->grid[T][1]; ++y)
+      for (int32_t x = 0; x < c->grid[T][0]; ++x)
+        if (!is_resident(&r, sgo_node_id(T, x, y, z))) return -2;
+  for (int32_t z = 0; z < c->grid[T][2]; ++z)
+    for (int32_t y = 0; y < c->grid[T][1]; ++y)
+      for (int32_t x = 0; x < c->grid[T][0]; ++x) {
+        int32_t b[3] = {x, y, z};
+        res_visit(&r, T, b);
+      }
+  if (out && c->n <= cap) qsort(out, (size_t)c->n, sizeof(uint64_t), cmp_u64);
+  /* every node has one parent, so no request appears twice; sorting gives
+   * the canonical order */
+  if (req && r.n_req <= req_cap) qsort(req, (size_t)r.n_req, sizeof(uint64_t), cmp_u64);
+  *n_req = r.n_req;
+  return c->n;
 }
 
 /* ------------------------------------------------------------------ O9 */
