@@ -90,6 +90,9 @@ typedef struct {
   int32_t brick;      /* core edge: power of two in [2, 256]                  */
   int32_t levels;     /* pyramid levels, 1..16 (1 = no pyramid)               */
   int32_t device;     /* HIP device ordinal                                   */
+  int32_t cache_slots; /* 0: every node of every channel and timepoint has a
+                          pool slot. > 0: the pool is a cache of this many
+                          slots (out-of-core mode, see sg_cache_put)         */
 } sg_volume_desc;
 
 /* One eye / camera (Sec 5.1: one ray per pixel; Sec 5.3: one view per eye).
@@ -317,6 +320,55 @@ sg_status sg_render_graph_set_views(sg_render_graph *graph, const sg_view *views
 sg_status sg_render_graph_launch(sg_render_graph *graph, void *hip_stream);
 /* Synchronises the device, then frees the graph and its scratch. */
 sg_status sg_render_graph_destroy(sg_render_graph *graph);
+
+/* ---------------------------------------------------------------------
+ * Out-of-core mode (cache_slots > 0; Sec 4.2 GPU chunk cache, Sec 5.2
+ * request queue and coarser fallback, Sec 5.4 time series). The pool holds
+ * cache_slots bricks; which (channel, timepoint, node) are resident is the
+ * caller's loading decision, driven by the requests renders make:
+ *  - a render's LOD traversal descends from a block that does not suit into
+ *    its children only when every existing child is resident for every
+ *    channel at the render's timepoint; otherwise it renders the block one
+ *    level coarser and requests the missing children;
+ *  - every top-level node must be resident at the render's timepoint
+ *    (SG_ERR_STATE otherwise);
+ *  - each render stamps the slots of the nodes it uses with a frame number;
+ *    when sg_cache_put needs a slot and none is free it evicts the slot with
+ *    the oldest stamp (a min-heap over stamps), never a top-level node's;
+ *  - sg_upload_bricks and sg_build_lod are not available (SG_ERR_UNSUPPORTED):
+ *    bricks arrive whole, apron included, at every level;
+ *  - render graphs are not available for such volumes.
+ * All cache calls are ordered on hip_stream after earlier work (evicting a
+ * slot an enqueued render still reads is safe only in stream order). */
+/* Store n bricks of one (channel, timepoint, level): src holds n regions of
+ * (brick+2)^3 voxels (x fastest), each the core [brick*b - 1, brick*b+brick]
+ * per axis with indices clamped to the level (the one-voxel apron), from a
+ * host pointer (copied before return) or a device pointer. coords: host
+ * int32 [n][3]. Bricks already resident are overwritten in place. Errors:
+ * SG_ERR_UNSUPPORTED (not a cache volume), SG_ERR_OUT_OF_MEMORY (n larger
+ * than the slots that can be freed). */
+sg_status sg_cache_put(sg_volume *vol, int32_t channel, int32_t timepoint,
+                       int32_t level, int32_t n, const int32_t *coords,
+                       const void *src, int32_t src_on_device, void *hip_stream);
+/* Nodes requested by renders since the last call, then cleared: ids[i]
+ * packed as in sg_get_lod_cut, timepoints[i] its timepoint (every channel
+ * of it is wanted). *n is the capacity on input, the count on output
+ * (nothing is written and SG_ERR_INVALID_ARG returned, with the count, if
+ * too small). Host buffers; synchronises hip_stream. */
+sg_status sg_cache_requests(sg_volume *vol, uint64_t *ids, int32_t *timepoints,
+                            int32_t *n, void *hip_stream);
+typedef struct {
+  int64_t capacity;   /* pool slots                                         */
+  int64_t resident;   /* slots holding a brick                              */
+  int64_t uploads;    /* bricks stored by sg_cache_put                      */
+  int64_t evictions;  /* bricks dropped to make room                        */
+  int64_t frame;      /* renders so far (the stamp of the latest)           */
+} sg_cache_info;
+sg_status sg_cache_get_info(const sg_volume *vol, sg_cache_info *info);
+/* Whether node (level, b) of (channel, timepoint) is resident: *resident =
+ * 1 or 0. */
+sg_status sg_cache_resident(const sg_volume *vol, int32_t channel, int32_t timepoint,
+                            int32_t level, const int32_t b[3], int32_t *resident);
 
 /* Bytes of device memory the volume holds (pool, tables, scratch). */
 sg_status sg_volume_memory(const sg_volume *vol, uint64_t *bytes);

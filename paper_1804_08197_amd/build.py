@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "volume.hip", "lod.hip", "raycast.hip", "raycast_ea.hip",
+SOURCES = ["api.hip", "volume.hip", "lod.hip", "cache.hip", "raycast.hip", "raycast_ea.hip",
            "raycast_eo.hip", "raycast_mip.hip"]
 
 CFLAGS = [

@@ -1,0 +1,134 @@
+"""Host-side brick container and loader for out-of-core volumes.
+
+Sec 4.1 stores a volume as chunks at several resolutions, made once at
+import; Sec 4.2 keeps recently used chunks in a GPU cache and Sec 5.2 loads
+the blocks a render asks for. This module is that import step and loader
+for a cache volume (``sg_volume_create(..., cache_slots=...)``):
+
+* ``build_levels`` makes the resolution pyramid of a level-0 array: each
+  coarser voxel is the rounded mean (sum + 4) >> 3 of its 2x2x2 children,
+  with child indices clamped at the far faces (the same rule the device
+  pyramid builder applies);
+* ``brick_regions`` cuts whole bricks out of a level: the core plus a
+  one-voxel apron, indices clamped at the volume border, x fastest;
+* ``BrickSource`` holds the pyramids of every (timepoint, channel) and
+  answers the cache's request list with ``sg_cache_put`` calls.
+
+Arrays are numpy (host) or torch tensors (device); all arithmetic is
+integer, so host and device pyramids agree exactly.
+"""
+from __future__ import annotations
+
+from collections import defaultdict
+
+import numpy as np
+
+from . import sg
+
+
+def _next_level(a):
+    """One pyramid step of a [z, y, x] array (numpy or torch)."""
+    if isinstance(a, np.ndarray):
+        w = a.astype(np.uint32)
+        pad = [(0, s % 2) for s in w.shape]
+        w = np.pad(w, pad, mode="edge")
+        z, y, x = (s // 2 for s in w.shape)
+        s = w.reshape(z, 2, y, 2, x, 2).sum(axis=(1, 3, 5))
+        return ((s + 4) >> 3).astype(a.dtype)
+    import torch
+    w = a.to(torch.int32)
+    pz, py, px = (s % 2 for s in w.shape)
+    if pz or py or px:
+        w = torch.nn.functional.pad(w[None, None].float(), (0, px, 0, py, 0, pz),
+                                    mode="replicate")[0, 0].to(torch.int32)
+    z, y, x = (s // 2 for s in w.shape)
+    s = w.reshape(z, 2, y, 2, x, 2).sum(dim=(1, 3, 5))
+    return ((s + 4) >> 3).to(a.dtype)
+
+
+def build_levels(vol0, levels: int):
+    """[level-0, level-1, ...] arrays of the pyramid."""
+    out = [vol0]
+    for _ in range(1, levels):
+        out.append(_next_level(out[-1]))
+    return out
+
+
+def brick_regions(level, brick: int, coords):
+    """Regions [n, B+2, B+2, B+2] of the bricks coords [n, 3] = (bx, by, bz):
+    voxels B*b - 1 .. B*b + B per axis, clamped to the level."""
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 3)
+    B = int(brick)
+    nz, ny, nx = level.shape
+    r = np.arange(-1, B + 1)
+    ix = np.clip(coords[:, 0:1] * B + r[None, :], 0, nx - 1)
+    iy = np.clip(coords[:, 1:2] * B + r[None, :], 0, ny - 1)
+    iz = np.clip(coords[:, 2:3] * B + r[None, :], 0, nz - 1)
+    if isinstance(level, np.ndarray):
+        return np.ascontiguousarray(level[iz[:, :, None, None], iy[:, None, :, None],
+                                          ix[:, None, None, :]])
+    import torch
+    dev = level.device
+    tz, ty, tx = (torch.from_numpy(a).to(dev) for a in (iz, iy, ix))
+    return level[tz[:, :, None, None], ty[:, None, :, None], tx[:, None, None, :]].contiguous()
+
+
+def decode_ids(ids):
+    ids = np.asarray(ids, dtype=np.uint64)
+    return ((ids >> np.uint64(60)).astype(np.int64),
+            np.stack([((ids >> np.uint64(40)) & np.uint64(0xFFFFF)).astype(np.int64),
+                      ((ids >> np.uint64(20)) & np.uint64(0xFFFFF)).astype(np.int64),
+                      (ids & np.uint64(0xFFFFF)).astype(np.int64)], axis=1))
+
+
+class BrickSource:
+    """Pyramids of every (timepoint, channel) of a cache volume, and the
+    loader that serves its requests."""
+
+    def __init__(self, handle, brick: int, levels: int):
+        self.h = handle
+        self.B = int(brick)
+        self.levels = int(levels)
+        self.pyr = {}
+
+    def add(self, timepoint: int, channel: int, vol0):
+        self.pyr[(int(timepoint), int(channel))] = build_levels(vol0, self.levels)
+
+    def channels(self, timepoint):
+        return sorted(c for (t, c) in self.pyr if t == timepoint)
+
+    def put(self, timepoint, level, coords, stream=None):
+        """Store the bricks coords of one level of every channel of one
+        timepoint."""
+        coords = np.asarray(coords, dtype=np.int32).reshape(-1, 3)
+        if not len(coords):
+            return
+        for c in self.channels(timepoint):
+            reg = brick_regions(self.pyr[(timepoint, c)][level], self.B, coords)
+            sg.sg_cache_put(self.h, c, timepoint, level, coords, reg, stream=stream)
+
+    def put_top(self, timepoint, stream=None):
+        """Every top-level brick (renders need them resident)."""
+        L = self.levels - 1
+        a = self.pyr[(timepoint, self.channels(timepoint)[0])][L]
+        g = [-(-s // self.B) for s in a.shape[::-1]]
+        bz, by, bx = np.meshgrid(np.arange(g[2]), np.arange(g[1]), np.arange(g[0]),
+                                 indexing="ij")
+        self.put(timepoint, L, np.stack([bx.ravel(), by.ravel(), bz.ravel()], 1), stream)
+
+    def serve_requests(self, max_bricks=None, stream=None) -> int:
+        """Load what the renders since the last call asked for (up to
+        max_bricks nodes, coarsest first); returns the number of nodes."""
+        ids, tps = sg.sg_cache_requests(self.h, stream=stream)
+        if not len(ids):
+            return 0
+        L, b = decode_ids(ids)
+        order = np.lexsort((ids, -L))
+        if max_bricks is not None:
+            order = order[:max_bricks]
+        groups = defaultdict(list)
+        for i in order:
+            groups[(int(tps[i]), int(L[i]))].append(b[i])
+        for (t, lev), cs in groups.items():
+            self.put(t, lev, np.array(cs), stream)
+        return len(order)

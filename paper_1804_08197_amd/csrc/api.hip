@@ -85,6 +85,10 @@ void free_all(Volume* v) {
   hipFree(v->info);
   hipFree(v->tf);
   if (v->queue) hipFree(v->queue);
+  if (v->stamp) hipFree(v->stamp);
+  if (v->req_flags) hipFree(v->req_flags);
+  if (v->req_list) hipFree(v->req_list);
+  if (v->req_count) hipFree(v->req_count);
   hipFree(v->cutmap);
   hipFree(v->view_dev);
   hipFree(v->mb_bits);
@@ -111,6 +115,7 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   if (d->levels < 1 || d->levels > kMaxLevels)
     return fail(SG_ERR_INVALID_ARG, "levels must be in [1, 16]");
   if (d->device < 0) return fail(SG_ERR_INVALID_ARG, "device must be >= 0");
+  if (d->cache_slots < 0) return fail(SG_ERR_INVALID_ARG, "cache_slots must be >= 0");
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
@@ -145,11 +150,13 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   v->nodes = nodes;
   const int64_t S3 = (int64_t)v->S * v->S * v->Sx;
   v->slot_bytes = ((S3 * v->bpv + 64 + 255) / 256) * 256;
-  v->slots = (int64_t)d->timepoints * d->channels * nodes;
-  if (v->slots > 0x7FFFFFFF) {
+  v->entries = (int64_t)d->timepoints * d->channels * nodes;
+  if (v->entries > 0x7FFFFFFF) {
     delete h;
-    return fail(SG_ERR_INVALID_ARG, "too many pool slots");
+    return fail(SG_ERR_INVALID_ARG, "too many (channel, timepoint, node) entries");
   }
+  v->cache = d->cache_slots > 0;
+  v->slots = v->cache ? std::min<int64_t>(d->cache_slots, v->entries) : v->entries;
   const int64_t pool_bytes = v->slots * v->slot_bytes;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (uint64_t)pool_bytes > free_b) {
@@ -163,8 +170,8 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   };
   const int64_t tf_bytes = (int64_t)kMaxChannels * (kMaxTfEntries + 1) * 16 + 2 * kMaxChannels * 8;
   bool ok = alloc((void**)&v->pool, pool_bytes) &&
-            alloc((void**)&v->page, v->slots * 4) &&
-            alloc((void**)&v->range, v->slots * 8) &&
+            alloc((void**)&v->page, v->entries * 4) &&
+            alloc((void**)&v->range, v->entries * 8) &&
             alloc((void**)&v->empty, (int64_t)d->timepoints * nodes) &&
             alloc((void**)&v->info, nodes * (int64_t)sizeof(NodeInfo)) &&
             alloc((void**)&v->tf, tf_bytes);
@@ -174,14 +181,31 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
     (void)hipGetLastError();
     return fail(SG_ERR_OUT_OF_MEMORY, "device allocation failed");
   }
+  if (v->cache &&
+      !(alloc((void**)&v->stamp, v->slots * 4) &&
+        alloc((void**)&v->req_flags, (((int64_t)d->timepoints * nodes + 31) / 32) * 4) &&
+        alloc((void**)&v->req_list, (int64_t)kReqCap * 4) && alloc((void**)&v->req_count, 4))) {
+    free_all(v);
+    delete h;
+    (void)hipGetLastError();
+    return fail(SG_ERR_OUT_OF_MEMORY, "device allocation failed (cache tables)");
+  }
   if (hipEventCreateWithFlags(&v->stage_done, hipEventDisableTiming) != hipSuccess) {
     free_all(v);
     delete h;
     return fail(SG_ERR_DEVICE, "event creation failed");
   }
-  // page table: every node resident, slot = (t * C + c) * nodes + node
-  std::vector<int32_t> page((size_t)v->slots);
-  for (int64_t i = 0; i < v->slots; ++i) page[(size_t)i] = (int32_t)i;
+  // page table: every node resident with slot = (t * C + c) * nodes + node,
+  // or (cache) nothing resident and every slot free
+  std::vector<int32_t> page((size_t)v->entries);
+  for (int64_t i = 0; i < v->entries; ++i) page[(size_t)i] = v->cache ? -1 : (int32_t)i;
+  if (v->cache) {
+    v->page_host = page;
+    v->owner.assign((size_t)v->slots, -1);
+    v->free_slots.resize((size_t)v->slots);
+    for (int64_t i = 0; i < v->slots; ++i)
+      v->free_slots[(size_t)i] = (int32_t)(v->slots - 1 - i);
+  }
   std::vector<NodeInfo> info((size_t)nodes);
   for (int L = 0; L < v->L; ++L)
     for (int32_t z = 0; z < v->grid[L][2]; ++z)
@@ -195,10 +219,14 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
           n.b[2] = z;
         }
   hipError_t e = hipMemset(v->pool, 0, (size_t)pool_bytes);
-  if (e == hipSuccess) e = hipMemset(v->range, 0, (size_t)(v->slots * 8));
+  if (e == hipSuccess) e = hipMemset(v->range, 0, (size_t)(v->entries * 8));
   if (e == hipSuccess) e = hipMemset(v->empty, 0, (size_t)(d->timepoints * nodes));
   if (e == hipSuccess)
-    e = hipMemcpy(v->page, page.data(), (size_t)v->slots * 4, hipMemcpyHostToDevice);
+    e = hipMemcpy(v->page, page.data(), (size_t)v->entries * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && v->cache) e = hipMemset(v->stamp, 0, (size_t)v->slots * 4);
+  if (e == hipSuccess && v->cache)
+    e = hipMemset(v->req_flags, 0, (size_t)(((int64_t)d->timepoints * nodes + 31) / 32) * 4);
+  if (e == hipSuccess && v->cache) e = hipMemset(v->req_count, 0, 4);
   if (e == hipSuccess)
     e = hipMemcpy(v->info, info.data(), (size_t)nodes * sizeof(NodeInfo), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -207,7 +235,7 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
     delete h;
     return hip_fail(e, "sg_volume_create: initialisation");
   }
-  v->pending.assign((size_t)d->timepoints * d->channels, 1);
+  v->pending.assign((size_t)d->timepoints * d->channels, v->cache ? 0 : 1);
   *out = h;
   return SG_OK;
 }
@@ -239,6 +267,9 @@ sg_status sg_upload_bricks(sg_volume* vol, int32_t channel, int32_t timepoint, i
                            int32_t src_on_device, void* hip_stream) {
   if (!vol) return fail(SG_ERR_INVALID_ARG, "sg_upload_bricks: NULL volume");
   Volume* v = &vol->v;
+  if (v->cache)
+    return fail(SG_ERR_UNSUPPORTED, "sg_upload_bricks: a cache volume takes whole bricks "
+                                    "(sg_cache_put)");
   if (channel < 0 || channel >= v->d.channels || timepoint < 0 ||
       timepoint >= v->d.timepoints || level < 0 || level >= v->L || n < 0)
     return fail(SG_ERR_INVALID_ARG, "sg_upload_bricks: channel/timepoint/level/n out of range");
@@ -276,6 +307,8 @@ sg_status sg_upload_bricks(sg_volume* vol, int32_t channel, int32_t timepoint, i
 sg_status sg_build_lod(sg_volume* vol, int32_t channel, int32_t timepoint, void* hip_stream) {
   if (!vol) return fail(SG_ERR_INVALID_ARG, "sg_build_lod: NULL volume");
   Volume* v = &vol->v;
+  if (v->cache)
+    return fail(SG_ERR_UNSUPPORTED, "sg_build_lod: a cache volume holds no full level 0");
   if (channel < 0 || channel >= v->d.channels || timepoint < 0 || timepoint >= v->d.timepoints)
     return fail(SG_ERR_INVALID_ARG, "sg_build_lod: channel/timepoint out of range");
   DeviceGuard guard(v->d.device);

@@ -12,6 +12,14 @@
 // cell -> node covers the volume exactly once. The comparison is done in
 // IEEE double with no contraction (this file is built with
 // -ffp-contract=off), so it reproduces the CPU reference bit for bit.
+//
+// Cache volumes (Sec 5.2, 4.2): a node that does not suit is refined only
+// when every existing child is resident for every channel at the render's
+// timepoint; otherwise the walk stops there (the block is rendered one level
+// coarser) and the missing children are requested (a bit per (timepoint,
+// node) keeps each request once in the list until the host reads it). This
+// is a property of the node, so all cells below it stop alike and the map
+// stays a partition.
 #include <algorithm>
 #include <vector>
 
@@ -30,7 +38,46 @@ struct CutGeom {
   int32_t bias;
   int32_t lod;
   int64_t cells;  // level-0 bricks
+  // cache volumes
+  int32_t cache;
+  int32_t channels;
+  int64_t nodes;
+  int64_t req_base;          // timepoint * nodes
+  const int32_t* page;       // at timepoint: [C][nodes]
+  uint32_t* req_flags;       // [T * nodes] bits
+  uint32_t* req_list;
+  uint32_t* req_count;
 };
+
+__device__ __forceinline__ bool node_resident(const CutGeom& g, int64_t node) {
+  for (int c = 0; c < g.channels; ++c)
+    if (g.page[(int64_t)c * g.nodes + node] < 0) return false;
+  return true;
+}
+
+__device__ __forceinline__ int64_t node_index(const CutGeom& g, int L, int bx, int by, int bz) {
+  return g.node_off[L] + ((int64_t)bz * g.grid[L][1] + by) * g.grid[L][0] + bx;
+}
+
+// Cache volumes: are all existing children of (L, b) resident? Requests the
+// missing ones.
+__device__ bool children_resident(const CutGeom& g, int L, int bx, int by, int bz) {
+  bool all = true;
+  for (int k = 0; k < 8; ++k) {
+    const int cx = 2 * bx + (k & 1), cy = 2 * by + ((k >> 1) & 1), cz = 2 * bz + (k >> 2);
+    if (cx >= g.grid[L - 1][0] || cy >= g.grid[L - 1][1] || cz >= g.grid[L - 1][2]) continue;
+    const int64_t child = node_index(g, L - 1, cx, cy, cz);
+    if (node_resident(g, child)) continue;
+    all = false;
+    const int64_t e = g.req_base + child;
+    const uint32_t bit = 1u << (e & 31);
+    if ((atomicOr(g.req_flags + (e >> 5), bit) & bit) == 0u) {
+      const uint32_t i = atomicAdd(g.req_count, 1u);
+      if (i < (uint32_t)kReqCap) g.req_list[i] = (uint32_t)e;
+    }
+  }
+  return all;
+}
 
 __device__ __forceinline__ bool node_suits(const CutGeom& g, const double e[3],
                                            double K, int L, int bx, int by,
@@ -64,12 +111,13 @@ __global__ void cutmap_kernel(CutGeom g, const ViewDev* views, int n_views,
     int32_t cy = (int32_t)((cell / g.grid[0][0]) % g.grid[0][1]);
     int32_t cz = (int32_t)(cell / ((int64_t)g.grid[0][0] * g.grid[0][1]));
     double e[3] = {V.e[0], V.e[1], V.e[2]};
-    int L = g.lod ? g.top : g.bias;
-    for (; L > g.bias; --L)
-      if (node_suits(g, e, V.K, L, cx >> L, cy >> L, cz >> L)) break;
-    const int32_t bx = cx >> L, by = cy >> L, bz = cz >> L;
-    cutmap[V.cut_off + cell] =
-        (int32_t)(g.node_off[L] + ((int64_t)bz * g.grid[L][1] + by) * g.grid[L][0] + bx);
+    int L = (g.lod || g.cache) ? g.top : g.bias;
+    for (; L > g.bias; --L) {
+      if (g.lod && node_suits(g, e, V.K, L, cx >> L, cy >> L, cz >> L)) break;
+      if (g.cache && !children_resident(g, L, cx >> L, cy >> L, cz >> L)) break;
+    }
+    const int64_t node = node_index(g, L, cx >> L, cy >> L, cz >> L);
+    cutmap[V.cut_off + cell] = (int32_t)node;
   }
 }
 
@@ -79,8 +127,18 @@ __global__ void mark_kernel(const int32_t* cutmap, int64_t cells, uint8_t* flags
     flags[cutmap[i]] = 1;
 }
 
-CutGeom cut_geom(const Volume* v, int bias, bool lod) {
+CutGeom cut_geom(const Volume* v, int bias, bool lod, int timepoint) {
   CutGeom g{};
+  if (v->cache) {
+    g.cache = 1;
+    g.channels = v->d.channels;
+    g.nodes = v->nodes;
+    g.req_base = (int64_t)timepoint * v->nodes;
+    g.page = v->page + (int64_t)timepoint * v->d.channels * v->nodes;
+    g.req_flags = v->req_flags;
+    g.req_list = v->req_list;
+    g.req_count = v->req_count;
+  }
   for (int a = 0; a < 3; ++a) g.dims[a] = v->d.dims[a];
   for (int L = 0; L < v->L; ++L) {
     for (int a = 0; a < 3; ++a) g.grid[L][a] = v->grid[L][a];
@@ -97,8 +155,8 @@ CutGeom cut_geom(const Volume* v, int bias, bool lod) {
 }  // namespace
 
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, int32_t* cutmap, Launch* out) {
-  CutGeom g = cut_geom(v, bias, lod);
+                        bool lod, int timepoint, int32_t* cutmap, Launch* out) {
+  CutGeom g = cut_geom(v, bias, lod, timepoint);
   int64_t total = (int64_t)n_views * g.cells;
   int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   out->func = reinterpret_cast<const void*>(cutmap_kernel);
@@ -114,9 +172,9 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
 }
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, hipStream_t s) {
+                        bool lod, int timepoint, hipStream_t s) {
   Launch l;
-  sg_status st = cutmap_launch(v, dviews, n_views, bias, lod, v->cutmap, &l);
+  sg_status st = cutmap_launch(v, dviews, n_views, bias, lod, timepoint, v->cutmap, &l);
   if (st != SG_OK) return st;
   return l.run(s);
 }
@@ -139,8 +197,11 @@ extern "C" sg_status sg_get_lod_cut(sg_volume* vol, const sg_view* view,
   st = prepare_views(v, 1, view, params, nullptr, nullptr, nullptr, s, &view_blocks);
   if (st != SG_OK) return st;
   const bool lod = (params->flags & SG_LOD) != 0;
+  if (!top_level_resident(v, params->timepoint))
+    return fail(SG_ERR_STATE, "sg_get_lod_cut: a top-level node is not in the cache");
+  ++v->frame;
   st = launch_cutmap(v, reinterpret_cast<const ViewDev*>(v->view_dev), 1, params->lod_bias,
-                     lod, s);
+                     lod, params->timepoint, s);
   if (st != SG_OK) return st;
   const int64_t cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
   uint8_t* dflags = nullptr;

@@ -125,6 +125,8 @@ void fill_args(const Volume* v, const sg_render_params* params, int n_views,
   a.bt_log = cfg.bt_log;
   a.persistent = cfg.persistent;
   a.queue = v->queue;
+  a.stamp = v->cache ? v->stamp : nullptr;
+  a.frame = v->frame;
   a.B = v->B;
   a.S = v->S;
   a.Sx = v->Sx;
@@ -333,8 +335,12 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   if (cfg.persistent && (st = ensure_queue(v)) != SG_OK) return st;
   const ViewDev* dv = reinterpret_cast<const ViewDev*>(v->view_dev);
   const bool timed = v->timing && !stats;
+  if (!top_level_resident(v, params->timepoint))
+    return fail(SG_ERR_STATE, "a top-level node is not in the cache at this timepoint");
+  ++v->frame;
   if (timed && (st = timing_mark(v, s)) != SG_OK) return st;
-  st = launch_cutmap(v, dv, n_views, params->lod_bias, (params->flags & SG_LOD) != 0, s);
+  st = launch_cutmap(v, dv, n_views, params->lod_bias, (params->flags & SG_LOD) != 0,
+                     params->timepoint, s);
   if (st != SG_OK) return st;
   if (cfg.persistent) {
     Launch q = queue_reset_launch(v->queue);
@@ -595,6 +601,8 @@ extern "C" sg_status sg_render_graph_create(sg_volume* vol, int32_t n_views,
   if (!vol || !views || !params || !out_rgba || !out)
     return fail(SG_ERR_INVALID_ARG, "sg_render_graph_create: NULL argument");
   Volume* v = &vol->v;
+  if (v->cache)
+    return fail(SG_ERR_UNSUPPORTED, "sg_render_graph_create: not available for cache volumes");
   sg_status st = check_volume_ready(v);
   if (st != SG_OK) return st;
   const LaunchConfig cfg = effective_config(v, params);
@@ -636,7 +644,8 @@ extern "C" sg_status sg_render_graph_create(sg_volume* vol, int32_t n_views,
     return bail(fail(SG_ERR_DEVICE, "sg_render_graph_create: view upload failed"));
   Launch cut, ray, reset = queue_reset_launch(g->queue);
   if ((st = cutmap_launch(v, g->dviews, n_views, params->lod_bias,
-                          (params->flags & SG_LOD) != 0, g->cutmap, &cut)) != SG_OK)
+                          (params->flags & SG_LOD) != 0, params->timepoint, g->cutmap,
+                          &cut)) != SG_OK)
     return bail(st);
   RenderArgs a;
   fill_args(v, params, n_views, g->dviews, g->cutmap, blocks, cfg, &a);

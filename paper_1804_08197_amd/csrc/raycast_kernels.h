@@ -466,13 +466,17 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   return true;
 }
 
-// Pool slot pointers of a node, one per channel.
+// Pool slot pointers of a node, one per channel. Cache volumes stamp the
+// slots with the frame number (last use, for eviction) when `stamp_it`.
 template <typename T, int CH>
-__device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T* slot[CH]) {
+__device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T* slot[CH],
+                                          bool stamp_it) {
 #pragma unroll
-  for (int ch = 0; ch < CH; ++ch)
-    slot[ch] = reinterpret_cast<const T*>(
-        a.pool + (int64_t)a.page[(int64_t)ch * a.nodes + node] * a.slot_bytes);
+  for (int ch = 0; ch < CH; ++ch) {
+    const int32_t sl = a.page[(int64_t)ch * a.nodes + node];
+    slot[ch] = reinterpret_cast<const T*>(a.pool + (int64_t)sl * a.slot_bytes);
+    if (stamp_it && a.stamp) a.stamp[sl] = a.frame;
+  }
 }
 
 template <int MODEL, int CH>
@@ -601,7 +605,7 @@ __device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* 
   const int sy = a.Sx, sz = a.S * a.Sx;
   while (r.alive) {
     const T* slot[CH];
-    slot_ptrs<T, CH>(a, r.node, slot);
+    slot_ptrs<T, CH>(a, r.node, slot, true);
     if (STATS) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
     auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
       return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
@@ -766,7 +770,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     const int first = __ffsll((unsigned long long)mask) - 1;
     const int node = uniform(__builtin_amdgcn_readlane(r.node, first));
     const T* slot[CH];
-    slot_ptrs<T, CH>(a, node, slot);
+    slot_ptrs<T, CH>(a, node, slot, lane == 0);
     if (STATS && lane == 0) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
 
     // --- dominant axis of the node's first ray; every ray of the node must

@@ -109,10 +109,11 @@ struct Volume {
   int32_t grid[kMaxLevels][3]{};
   int64_t node_off[kMaxLevels + 1]{};
   int64_t nodes = 0;          // nodes per (channel, timepoint)
+  int64_t entries = 0;        // T * C * nodes (page table entries)
   int64_t slot_bytes = 0;     // bytes per pool slot (padded)
-  int64_t slots = 0;          // pool slots
+  int64_t slots = 0;          // pool slots (= entries unless a cache)
   uint8_t* pool = nullptr;    // [slots][S^3] voxels
-  int32_t* page = nullptr;    // [T][C][nodes] -> slot
+  int32_t* page = nullptr;    // [T][C][nodes] -> slot, -1 if not resident
   uint32_t* range = nullptr;  // [T][C][nodes][2] min, max of stored voxels
   uint8_t* empty = nullptr;   // [T][nodes] bit 0: every channel transparent,
                               // bit 1: every channel emits nothing
@@ -138,6 +139,17 @@ struct Volume {
   int64_t mb_words = 0;
   uint64_t* counters = nullptr;  // device counters (stats only)
   uint64_t bytes = 0;
+  // out-of-core mode (cache_slots > 0)
+  bool cache = false;
+  std::vector<int32_t> page_host;   // mirror of page
+  std::vector<int64_t> owner;       // slot -> entry, -1 if free
+  std::vector<int32_t> free_slots;
+  uint32_t* stamp = nullptr;        // [slots] frame of last use
+  uint32_t* req_flags = nullptr;    // [T * nodes] bits: requested since last read
+  uint32_t* req_list = nullptr;     // [kReqCap] requested t * nodes + node
+  uint32_t* req_count = nullptr;
+  uint32_t frame = 0;
+  int64_t uploads = 0, evictions = 0;
   // launch configuration of the ray caster, and the persistent grid's queues
   LaunchConfig cfg;
   uint32_t* queue = nullptr;  // 8 counters
@@ -146,6 +158,9 @@ struct Volume {
   std::vector<hipEvent_t> ev_free;
   std::vector<hipEvent_t> ev_rec;  // triples: before cut map, before / after ray cast
 };
+
+// Capacity of the request list of a cache volume.
+constexpr int kReqCap = 1 << 20;
 
 // Record an event from the volume's pool on `s` (timing mode only).
 sg_status timing_mark(Volume* v, hipStream_t s);
@@ -172,6 +187,8 @@ sg_status launch_downsample(Volume* v, int c, int t, int level_dst,
 sg_status launch_apron(Volume* v, int c, int t, hipStream_t s);
 sg_status launch_range(Volume* v, int c, int t, hipStream_t s);
 sg_status launch_empty(Volume* v, hipStream_t s);
+// Cache volumes: every top-level node resident at timepoint t?
+bool top_level_resident(const Volume* v, int t);
 sg_status commit(Volume* v, hipStream_t s);
 
 // Per-view constants consumed by the LOD and ray-casting kernels.
@@ -194,7 +211,7 @@ struct ViewDev {
 };
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
-                        int bias, bool lod, hipStream_t s);
+                        int bias, bool lod, int timepoint, hipStream_t s);
 // rgba may be NULL (cut queries); the render path checks it itself.
 sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         const sg_render_params* p, float* const* rgba,
@@ -208,7 +225,7 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       int64_t* total_blocks);
 // The cut-map kernel for views already on the device, writing `cutmap`.
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, int32_t* cutmap, Launch* out);
+                        bool lod, int timepoint, int32_t* cutmap, Launch* out);
 
 struct RenderArgs {
   const uint8_t* pool;
@@ -241,6 +258,8 @@ struct RenderArgs {
   int32_t bt_log;       // log2 edge of a screen block in 8x8 wave tiles
   int32_t persistent;   // 1: waves take tiles from the per-XCD queues
   uint32_t* queue;      // 8 counters, zero at launch (persistent grid)
+  uint32_t* stamp;      // cache volumes: [slots] frame of last use, else NULL
+  uint32_t frame;
   int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)

@@ -38,7 +38,7 @@ class SgError(RuntimeError):
 class sg_volume_desc(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("channels", C.c_int32), ("timepoints", C.c_int32),
                 ("dtype", C.c_int32), ("brick", C.c_int32), ("levels", C.c_int32),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("cache_slots", C.c_int32)]
 
 
 class sg_view(C.Structure):
@@ -60,6 +60,11 @@ class sg_render_stats(C.Structure):
     _fields_ = [("samples", C.POINTER(C.c_void_p)), ("total_samples", C.c_uint64),
                 ("microblocks", C.c_uint64), ("node_visits", C.c_uint64), ("slabs", C.c_uint64),
                 ("staged_bytes", C.c_uint64)]
+
+
+class sg_cache_info(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("resident", C.c_int64), ("uploads", C.c_int64),
+                ("evictions", C.c_int64), ("frame", C.c_int64)]
 
 
 class sg_launch_config(C.Structure):
@@ -103,6 +108,13 @@ _lib.sg_render_graph_create.argtypes = [_P, C.c_int32, C.POINTER(sg_view),
 _lib.sg_render_graph_set_views.argtypes = [_P, C.POINTER(sg_view), _P]
 _lib.sg_render_graph_launch.argtypes = [_P, _P]
 _lib.sg_render_graph_destroy.argtypes = [_P]
+_lib.sg_cache_put.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                              C.POINTER(C.c_int32), _P, C.c_int32, _P]
+_lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), _P]
+_lib.sg_cache_get_info.argtypes = [_P, C.POINTER(sg_cache_info)]
+_lib.sg_cache_resident.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32)]
 _lib.sg_status_string.argtypes = [C.c_int]
 _lib.sg_status_string.restype = C.c_char_p
 _lib.sg_last_error.restype = C.c_char_p
@@ -112,7 +124,8 @@ for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_buil
            "sg_render_views_stats", "sg_get_lod_cut", "sg_volume_memory",
            "sg_set_kernel_timing", "sg_get_kernel_timing", "sg_set_launch_config",
            "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
-           "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy"):
+           "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy",
+           "sg_cache_put", "sg_cache_requests", "sg_cache_get_info", "sg_cache_resident"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -219,12 +232,13 @@ def sg_last_error() -> str:
 
 
 def sg_volume_create(dims, channels=1, timepoints=1, dtype=SG_U16, brick=64, levels=1,
-                     device=0):
+                     device=0, cache_slots=0):
     d = sg_volume_desc()
     for i in range(3):
         d.dims[i] = int(dims[i])
     d.channels, d.timepoints, d.dtype = int(channels), int(timepoints), int(dtype)
     d.brick, d.levels, d.device = int(brick), int(levels), int(device)
+    d.cache_slots = int(cache_slots)
     h = C.c_void_p()
     _check(_lib.sg_volume_create(C.byref(d), C.byref(h)), "sg_volume_create")
     return h
@@ -407,3 +421,48 @@ class RenderGraph:
         if self.handle is not None:
             _check(_lib.sg_render_graph_destroy(self.handle), "sg_render_graph_destroy")
             self.handle = None
+
+
+# ------------------------------------------------------------ brick cache
+def sg_cache_put(vol, channel, timepoint, level, coords, regions, stream=None):
+    """Store whole bricks (regions [n, B+2, B+2, B+2], core plus apron, x
+    fastest; numpy or a device tensor) of one (channel, timepoint, level)."""
+    coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
+    on_dev = not isinstance(regions, np.ndarray) and getattr(regions, "is_cuda", False)
+    if isinstance(regions, np.ndarray):
+        regions = np.ascontiguousarray(regions)
+    else:
+        regions = regions.contiguous()
+    _check(_lib.sg_cache_put(vol, int(channel), int(timepoint), int(level), len(coords),
+                             coords.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(regions),
+                             int(bool(on_dev)), _stream(stream)), "sg_cache_put")
+
+
+def sg_cache_requests(vol, stream=None):
+    """Requested nodes since the last call: (ids uint64, timepoints int32)."""
+    n = C.c_int32(0)
+    st = _lib.sg_cache_requests(vol, None, None, C.byref(n), _stream(stream))
+    if st == SG_OK:
+        return np.zeros(0, np.uint64), np.zeros(0, np.int32)
+    if st != SG_ERR_INVALID_ARG:
+        _check(st, "sg_cache_requests")
+    ids = np.zeros(n.value, np.uint64)
+    tps = np.zeros(n.value, np.int32)
+    _check(_lib.sg_cache_requests(vol, ids.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                  tps.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n),
+                                  _stream(stream)), "sg_cache_requests")
+    return ids[:n.value], tps[:n.value]
+
+
+def sg_cache_get_info(vol) -> dict:
+    o = sg_cache_info()
+    _check(_lib.sg_cache_get_info(vol, C.byref(o)), "sg_cache_get_info")
+    return {k: int(getattr(o, k)) for k, _ in sg_cache_info._fields_}
+
+
+def sg_cache_resident(vol, channel, timepoint, level, b) -> bool:
+    bb = (C.c_int32 * 3)(*[int(x) for x in b])
+    r = C.c_int32()
+    _check(_lib.sg_cache_resident(vol, int(channel), int(timepoint), int(level), bb,
+                                  C.byref(r)), "sg_cache_resident")
+    return bool(r.value)
