@@ -1,0 +1,92 @@
+/*
+ * sg_upsampler.h -- C ABI of the learned upsampler (gfx950, MFMA).
+ *
+ * Fewer rays per frame (Sec 5.3 renders in a space that needs fewer rays and
+ * resamples): the volume is ray cast at half the resolution one pyramid
+ * level coarser, and a small convolutional network predicts the
+ * full-resolution frame from that render's premultiplied RGBA and depth.
+ * The network (BF16 weights and activations, FP32 accumulation on MFMA):
+ *   x0  [N][H][W][8]   r, g, b, a, depth code 1/(1 + t/depth_scale) (0 where
+ *                      the ray never reached the depth threshold), 0, 0, 0
+ *   h1 = relu(conv3x3(x0)), h2 = relu(conv3x3(h1)), h3 = relu(conv3x3(h2)),
+ *   o  = conv3x3(h3)                 (32 channels each; zero padding)
+ *   full-resolution pixel (2y + sy, 2x + sx), s = 2 sy + sx:
+ *     rgba = bilinear x2 of x0's rgba (half-pixel centres, clamped edges)
+ *            + o[y][x][5s .. 5s+3],
+ *     err  = o[y][x][5s+4]^2, a prediction of that pixel's mean squared RGB
+ *            error; its frame mean predicts the frame's PSNR, which decides
+ *            whether the caller falls back to a full-resolution render.
+ * Weights are packed layer by layer as w[9][c_in][32] (tap = 3 (dy+1) +
+ * (dx+1)) followed by b[32], with c_in = 8, 32, 32, 32.
+ *
+ * Conventions as in sg.h: every call returns an sg_status; device pointers
+ * are read or written in hip_stream order; the upsampler owns its weights,
+ * optimiser state and scratch; it is not thread-safe.
+ */
+#ifndef SG_UPSAMPLER_H
+#define SG_UPSAMPLER_H
+#include <stdint.h>
+
+#include "sg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_upsampler sg_upsampler; /* opaque */
+
+/* Number of floats in the packed weights (all four layers). */
+int64_t sg_up_param_count(void);
+
+/* Create an upsampler on a device with scratch for batches of up to
+ * max_pixels low-resolution pixels (N * H * W) and zero weights.
+ * Errors: SG_ERR_INVALID_ARG, SG_ERR_OUT_OF_MEMORY, SG_ERR_DEVICE. */
+sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler **out);
+sg_status sg_up_destroy(sg_upsampler *up);
+
+/* Copy packed weights in (host floats, sg_up_param_count of them; also
+ * resets the optimiser state) or out. Synchronous. */
+sg_status sg_up_set_weights(sg_upsampler *up, const float *params, int64_t n);
+sg_status sg_up_get_weights(sg_upsampler *up, float *params, int64_t n);
+
+/* Inference on n low-resolution images of h x w:
+ *   rgba  device float [n][h][w][4] (a render's premultiplied output)
+ *   depth device float [n][h][w]    (its first-hit depth, +inf = none)
+ *   out_rgba device float [n][2h][2w][4]
+ *   out_err  NULL or device float [n][2h][2w] (predicted squared error)
+ *   mse_pred NULL or host double [n]: mean predicted squared error per
+ *            image (synchronises hip_stream when given)
+ * n * h * w <= max_pixels. */
+sg_status sg_up_forward(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
+                        const float *rgba, const float *depth, double depth_scale,
+                        float *out_rgba, float *out_err, double *mse_pred,
+                        void *hip_stream);
+
+/* Gradients of the training loss (mean squared RGBA error against target,
+ * plus err_weight times the mean squared error of the error head against
+ * each pixel's actual RMS RGB error, held constant) for one batch:
+ *   target device float [n][2h][2w][4]
+ *   grads  NULL or host float [sg_up_param_count()] (packed like the
+ *          weights; synchronises)
+ *   loss   NULL or host double (synchronises) */
+sg_status sg_up_gradients(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
+                          const float *rgba, const float *depth, double depth_scale,
+                          const float *target, double err_weight, float *grads,
+                          double *loss, void *hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr on the gradients of the batch (as sg_up_gradients). */
+sg_status sg_up_train_step(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
+                           const float *rgba, const float *depth, double depth_scale,
+                           const float *target, double err_weight, double lr,
+                           double *loss, void *hip_stream);
+
+/* Test hook: copy the first `bytes` of an activation of the last forward
+ * or gradient call to host memory (synchronises the device): which = 0 x0
+ * (bf16 [P][8]), 1..3 h1..h3 (bf16 [P][32]), 4 o (float [P][32]). */
+sg_status sg_up_read_buffer(sg_upsampler *up, int32_t which, void *host, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_UPSAMPLER_H */

@@ -121,26 +121,31 @@ def pixel_unshuffle(g, channels=C_OUT):
     return out
 
 
-def forward(params, x0):
+def forward(params, x0, act_round=None):
     """params: list of (w, b) per layer. Returns (rgba [N,2H,2W,4], z
-    [N,2H,2W], cache for backpropagation)."""
+    [N,2H,2W], cache for backpropagation). act_round, if given, is applied
+    to every hidden activation (the precision they are stored in)."""
     h = [np.asarray(x0, np.float64)]
     pre = []
     for i, (w, b) in enumerate(params):
         a = conv3x3(h[-1], w, b)
         pre.append(a)
-        h.append(relu(a) if i < len(params) - 1 else a)
+        if i < len(params) - 1:
+            r = relu(a)
+            h.append(act_round(r) if act_round is not None else r)
+        else:
+            h.append(a)
     sh = pixel_shuffle(h[-1])
     base = bilinear_up2(h[0][..., :4])
     rgba = base + sh[..., :4]
     return rgba, sh[..., 4], (h, pre)
 
 
-def loss_and_grads(params, x0, target, err_weight=1.0):
+def loss_and_grads(params, x0, target, err_weight=1.0, act_round=None):
     """Loss = mean over full-resolution pixels and RGBA of the squared error
     + err_weight * mean over pixels of (z - e)^2, e = sqrt(mean over RGB of
     the squared error) held constant. Returns (loss, grads [(dw, db)])."""
-    rgba, z, (h, pre) = forward(params, x0)
+    rgba, z, (h, pre) = forward(params, x0, act_round)
     target = np.asarray(target, np.float64)
     P = rgba.shape[0] * rgba.shape[1] * rgba.shape[2]
     diff = rgba - target

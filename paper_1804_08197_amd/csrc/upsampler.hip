@@ -1,0 +1,689 @@
+// upsampler.hip -- the learned upsampler: inference and training kernels.
+//
+// Fewer rays per frame (Sec 5.3): the volume is ray cast at half resolution
+// one pyramid level coarser and a 4-layer 3x3 convolutional network predicts
+// the full-resolution frame (the network is described in
+// sg_upsampler.h). Activations are NHWC bfloat16 with 8 (input) or 32
+// channels, so one pixel's channels are one contiguous 16- or 64-byte run.
+//
+// Convolution = implicit GEMM on the matrix cores: a wave computes 64
+// consecutive pixels x 32 output channels with v_mfma_f32_16x16x32_bf16
+// (four 16-pixel row blocks x two 16-channel column blocks, FP32
+// accumulators). The GEMM's K runs over (tap, input channel): with 32
+// input channels one K-step of 32 is one tap; with 8 input channels one
+// K-step covers four taps (K = 72 padded to 96). Operand layouts of the
+// instruction (lane l): A[row l % 16][k 8 (l / 16) .. + 7], B[k 8 (l / 16)
+// .. + 7][column l % 16], result rows 4 (l / 16) .. + 3 of column l % 16.
+// So a lane's A operand is 8 consecutive channels of one pixel at one tap
+// (one 16-byte load) and its B operand 8 consecutive K of one output
+// channel, stored that way ([K / 8][32][8]) when the weights are packed.
+//
+// Backward: the input gradient of a 3x3 convolution is a 3x3 convolution of
+// the output gradient with the taps mirrored and the channel roles swapped,
+// so it runs on the same kernel with weights packed that way and the ReLU
+// derivative applied as a mask. Weight gradients sum x (tap-shifted) times
+// the output gradient over every pixel: FP32 partial sums per workgroup,
+// added in a fixed order (deterministic). Adam keeps FP32 master weights.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sg_upsampler.h"
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLayers = 4;
+constexpr int kCin[kLayers] = {8, 32, 32, 32};
+constexpr int kCh = 32;       // output channels of every layer
+constexpr int kUsed = 20;     // used output channels of the last layer
+
+// packed weights: per layer w[9][cin][32] then b[32]
+constexpr int64_t layer_size(int l) { return (int64_t)9 * kCin[l] * kCh + kCh; }
+constexpr int64_t kParams = layer_size(0) + layer_size(1) + layer_size(2) + layer_size(3);
+int64_t layer_off(int l) {
+  int64_t o = 0;
+  for (int i = 0; i < l; ++i) o += layer_size(i);
+  return o;
+}
+// K of a layer's GEMM (9 * cin rounded up to a multiple of 32)
+constexpr int kdim(int cin) { return ((9 * cin + 31) / 32) * 32; }
+
+__device__ __forceinline__ float bf(bf16 x) { return (float)x; }
+
+// --------------------------------------------------------------- kernels
+// x0 from a render: r, g, b, a, depth code, 0, 0, 0
+__global__ void prep_kernel(const float4* rgba, const float* depth, int64_t P, float inv_scale,
+                            bf16* x0) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const float4 c = rgba[p];
+    const float d = depth[p];
+    const float code = isfinite(d) ? 1.0f / (1.0f + d * inv_scale) : 0.0f;
+    bf16x8 v;
+    v[0] = (bf16)c.x;
+    v[1] = (bf16)c.y;
+    v[2] = (bf16)c.z;
+    v[3] = (bf16)c.w;
+    v[4] = (bf16)code;
+    v[5] = v[6] = v[7] = (bf16)0.0f;
+    reinterpret_cast<bf16x8*>(x0)[p] = v;
+  }
+}
+
+// Epilogues of the convolution kernel.
+enum { kReluBf16 = 0, kBiasF32 = 1, kMaskBf16 = 2 };
+
+// y[p][co] = sum_{tap, ci} x[p + off(tap)][ci] * w[tap][ci][co] (+ epilogue),
+// zero padding, for N images of H x W. wt: packed [K / 8][32][8] bf16.
+template <int CIN, int EPI>
+__global__ __launch_bounds__(256) void conv_kernel(const bf16* __restrict__ x, int N, int H, int W,
+                                                   const bf16x8* __restrict__ wt,
+                                                   const float* __restrict__ bias,
+                                                   void* __restrict__ out,
+                                                   const bf16* __restrict__ mask) {
+  const int lane = threadIdx.x & 63;
+  const int64_t P = (int64_t)N * H * W;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+  if (p0 >= P) return;  // whole wave
+  const int row = lane & 15, grp = lane >> 4;
+  // the lane's pixel in each of the four row blocks
+  int py[4], px[4], pn[4];
+  bool pv[4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int64_t p = p0 + mb * 16 + row;
+    pv[mb] = p < P;
+    const int64_t q = pv[mb] ? p : 0;
+    pn[mb] = (int)(q / ((int64_t)H * W));
+    const int r = (int)(q - (int64_t)pn[mb] * H * W);
+    py[mb] = r / W;
+    px[mb] = r - py[mb] * W;
+  }
+  floatx4 acc[4][2];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  constexpr int KSTEPS = kdim(CIN) / 32;
+  const bf16x8 zero8 = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f,
+                        (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+#pragma unroll 1
+  for (int s = 0; s < KSTEPS; ++s) {
+    const int k8 = s * 4 + grp;  // this lane's group of 8 K values
+    const int tap = CIN == 32 ? s : k8;
+    const int c0 = CIN == 32 ? grp * 8 : 0;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    bf16x8 a[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int yy = py[mb] + dy, xx = px[mb] + dx;
+      const bool in = pv[mb] && tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      a[mb] = in ? *reinterpret_cast<const bf16x8*>(
+                       x + (((int64_t)pn[mb] * H + yy) * W + xx) * CIN + c0)
+                 : zero8;
+    }
+    const bf16x8 b0 = wt[(int64_t)k8 * kCh + row];
+    const bf16x8 b1 = wt[(int64_t)k8 * kCh + 16 + row];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b0, acc[mb][0], 0, 0, 0);
+      acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b1, acc[mb][1], 0, 0, 0);
+    }
+  }
+  // result (row 4 grp + i, column row) of each block
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t p = p0 + mb * 16 + grp * 4 + i;
+        if (p >= P) continue;
+        const int co = nb * 16 + row;
+        float vv = acc[mb][nb][i];
+        if (EPI == kReluBf16) {
+          vv = fmaxf(vv + bias[co], 0.0f);
+          reinterpret_cast<bf16*>(out)[p * kCh + co] = (bf16)vv;
+        } else if (EPI == kBiasF32) {
+          reinterpret_cast<float*>(out)[p * kCh + co] = vv + bias[co];
+        } else {
+          const bool on = bf(mask[p * kCh + co]) > 0.0f;
+          reinterpret_cast<bf16*>(out)[p * kCh + co] = (bf16)(on ? vv : 0.0f);
+        }
+      }
+}
+
+// Bilinear x2 (half-pixel centres, clamped) of x0's rgba at full-resolution
+// pixel (2y + sy, 2x + sx).
+__device__ __forceinline__ float4 base_rgba(const bf16* x0, int n, int H, int W, int y, int x,
+                                            int sy, int sx) {
+  const int ya = sy ? y : y - 1, xa = sx ? x : x - 1;
+  const float fy = sy ? 0.25f : 0.75f, fx = sx ? 0.25f : 0.75f;
+  const int y0 = min(max(ya, 0), H - 1), y1 = min(max(ya + 1, 0), H - 1);
+  const int x0i = min(max(xa, 0), W - 1), x1 = min(max(xa + 1, 0), W - 1);
+  auto at = [&](int yy, int xx, int c) {
+    return bf(x0[(((int64_t)n * H + yy) * W + xx) * 8 + c]);
+  };
+  float o[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float a = at(y0, x0i, c), b = at(y0, x1, c), cc = at(y1, x0i, c), d = at(y1, x1, c);
+    const float top = a + (b - a) * fx, bot = cc + (d - cc) * fx;
+    o[c] = top + (bot - top) * fy;
+  }
+  return make_float4(o[0], o[1], o[2], o[3]);
+}
+
+// Inference epilogue: full-resolution rgba and predicted squared error; the
+// per-image sum of the prediction accumulates in mse_sum[n] (doubles).
+__global__ __launch_bounds__(256) void shuffle_kernel(const float* o, const bf16* x0, int N, int H,
+                                                      int W, float4* out, float* err,
+                                                      double* mse_sum) {
+  const int64_t P = (int64_t)N * H * W;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float zsum = 0.f;
+  int n = 0;
+  if (p < P) {
+    n = (int)(p / ((int64_t)H * W));
+    const int r = (int)(p - (int64_t)n * H * W), y = r / W, x = r - y * W;
+    const float* op = o + p * kCh;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int sy = s >> 1, sx = s & 1;
+      const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
+      const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
+      out[q] = make_float4(b.x + op[5 * s], b.y + op[5 * s + 1], b.z + op[5 * s + 2],
+                           b.w + op[5 * s + 3]);
+      const float z = op[5 * s + 4];
+      if (err) err[q] = z * z;
+      zsum += z * z;
+    }
+  }
+  if (!mse_sum) return;
+  // block sums for the block's first image and the next one; other images
+  // (tiny images) add per thread
+  const int64_t HW = (int64_t)H * W;
+  const int nf = (int)(((int64_t)blockIdx.x * blockDim.x) / HW);
+  __shared__ double r0[256], r1[256];
+  const bool in = p < P;
+  r0[threadIdx.x] = in && n == nf ? (double)zsum : 0.0;
+  r1[threadIdx.x] = in && n == nf + 1 ? (double)zsum : 0.0;
+  if (in && n > nf + 1) atomicAdd(mse_sum + n, (double)zsum);
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (nf < N) atomicAdd(mse_sum + nf, r0[0]);
+    if (nf + 1 < N) atomicAdd(mse_sum + nf + 1, r1[0]);
+  }
+}
+
+// Training loss and its gradient with respect to o (bf16, 32 channels,
+// zeros beyond the 20 used): per low-resolution pixel, its four
+// full-resolution pixels. loss_sum[0] += the pixel's share.
+__global__ __launch_bounds__(256) void loss_kernel(const float* o, const bf16* x0,
+                                                   const float4* target, int N, int H, int W,
+                                                   float err_weight, bf16* g, double* loss_sum) {
+  const int64_t P = (int64_t)N * H * W;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const double Pf = 4.0 * (double)P;  // full-resolution pixels
+  double part = 0.0;
+  if (p < P) {
+    const int n = (int)(p / ((int64_t)H * W));
+    const int r = (int)(p - (int64_t)n * H * W), y = r / W, x = r - y * W;
+    const float* op = o + p * kCh;
+    float gv[kCh];
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) gv[c] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int sy = s >> 1, sx = s & 1;
+      const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
+      const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
+      const float4 t = target[q];
+      const float d0 = b.x + op[5 * s] - t.x, d1 = b.y + op[5 * s + 1] - t.y,
+                  d2 = b.z + op[5 * s + 2] - t.z, d3 = b.w + op[5 * s + 3] - t.w;
+      const float e = sqrtf((d0 * d0 + d1 * d1 + d2 * d2) / 3.0f);
+      const float z = op[5 * s + 4];
+      // loss = sum d^2 / (4 Pf) + err_weight sum (z - e)^2 / Pf (e held constant)
+      part += ((double)d0 * d0 + (double)d1 * d1 + (double)d2 * d2 + (double)d3 * d3) /
+                  (4.0 * Pf) +
+              (double)err_weight * ((double)(z - e) * (z - e)) / Pf;
+      const float k = (float)(2.0 / (4.0 * Pf));
+      gv[5 * s] = k * d0;
+      gv[5 * s + 1] = k * d1;
+      gv[5 * s + 2] = k * d2;
+      gv[5 * s + 3] = k * d3;
+      gv[5 * s + 4] = (float)(2.0 / Pf) * err_weight * (z - e);
+    }
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) g[p * kCh + c] = (bf16)gv[c];
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss_sum) atomicAdd(loss_sum, red[0]);
+}
+
+// Weight-gradient partial sums of one workgroup over its pixel chunk:
+// part[blk][t][ci][co] = sum_p x[p + off(t)][ci] g[p][co], and the bias
+// part[blk][9 CIN 32 + co] = sum_p g[p][co]. 32-pixel tiles are staged in
+// LDS (x gathered at the 9 taps, zero outside the image).
+template <int CIN>
+__global__ __launch_bounds__(256) void wgrad_kernel(const bf16* x, const bf16* g, int N, int H,
+                                                    int W, int64_t chunk, float* part) {
+  constexpr int PAIRS = CIN * kCh;           // (ci, co)
+  constexpr int PER = (PAIRS + 255) / 256;   // pairs per thread
+  __shared__ float sx[32][9][CIN];
+  __shared__ float sg[32][kCh];
+  const int64_t P = (int64_t)N * H * W;
+  const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(P, begin + chunk);
+  float acc[PER][9];
+  float bacc = 0.f;
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[k][t] = 0.f;
+  for (int64_t t0 = begin; t0 < end; t0 += 32) {
+    const int cnt = (int)min<int64_t>(32, end - t0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * 9 * CIN; i += 256) {
+      const int pi = i / (9 * CIN), rem = i - pi * 9 * CIN, t = rem / CIN, ci = rem - t * CIN;
+      float v = 0.f;
+      if (pi < cnt) {
+        const int64_t p = t0 + pi;
+        const int n = (int)(p / ((int64_t)H * W));
+        const int r = (int)(p - (int64_t)n * H * W), y = r / W + t / 3 - 1,
+                  xx = r % W + t % 3 - 1;
+        if (y >= 0 && y < H && xx >= 0 && xx < W)
+          v = bf(x[(((int64_t)n * H + y) * W + xx) * CIN + ci]);
+      }
+      sx[pi][t][ci] = v;
+    }
+    for (int i = threadIdx.x; i < 32 * kCh; i += 256) {
+      const int pi = i / kCh, co = i - pi * kCh;
+      sg[pi][co] = pi < cnt ? bf(g[(t0 + pi) * kCh + co]) : 0.f;
+    }
+    __syncthreads();
+    for (int pi = 0; pi < cnt; ++pi) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int pair = threadIdx.x + 256 * k;
+        if (pair >= PAIRS) continue;
+        const int ci = pair / kCh, co = pair - ci * kCh;
+        const float gv = sg[pi][co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[k][t] = fmaf(sx[pi][t][ci], gv, acc[k][t]);
+      }
+      if (threadIdx.x < kCh) bacc += sg[pi][threadIdx.x];
+    }
+  }
+  float* out = part + (int64_t)blockIdx.x * (9 * PAIRS + kCh);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int pair = threadIdx.x + 256 * k;
+    if (pair >= PAIRS) continue;
+    const int ci = pair / kCh, co = pair - ci * kCh;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) out[((int64_t)t * CIN + ci) * kCh + co] = acc[k][t];
+  }
+  if (threadIdx.x < kCh) out[9 * PAIRS + threadIdx.x] = bacc;
+}
+
+// grads[i] = sum over blocks (in order) of part[blk][i]
+__global__ void reduce_kernel(const float* part, int blocks, int64_t n, float* grads) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * n + i];
+    grads[i] = s;
+  }
+}
+
+// Adam on the FP32 master weights.
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                            float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+  }
+}
+
+// Pack one layer's FP32 weights w[9][cin][32] into the GEMM layouts:
+// forward fw[k / 8][co][k % 8], k = tap cin + ci (zero beyond 9 cin);
+// backward (cin == 32 only) bw[k / 8][ci][k % 8], k = tap' 32 + co, with
+// element w[8 - tap'][ci][co] (mirrored taps, swapped channel roles).
+__global__ void pack_kernel(const float* w, int cin, bf16* fw, bf16* bw) {
+  const int K = ((9 * cin + 31) / 32) * 32;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < K * kCh; i += gridDim.x * blockDim.x) {
+    const int k = i / kCh, c = i - k * kCh;  // (k, output column)
+    const int tap = k / cin, ci = k - tap * cin;
+    const float f = k < 9 * cin ? w[((int64_t)tap * cin + ci) * kCh + c] : 0.f;
+    fw[((int64_t)(k / 8) * kCh + c) * 8 + (k % 8)] = (bf16)f;
+    if (bw && cin == kCh) {
+      // column c is the input channel ci' of the backward conv, k = tap' 32 + co
+      const int tp = k / kCh, co = k - tp * kCh;
+      const float b = w[((int64_t)(8 - tp) * kCh + c) * kCh + co];
+      bw[((int64_t)(k / 8) * kCh + c) * 8 + (k % 8)] = (bf16)b;
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace sg
+
+using namespace sg;
+
+struct sg_upsampler {
+  int device = 0;
+  int64_t max_pixels = 0;
+  float* params = nullptr;  // FP32 master weights (packed)
+  float* grads = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  int64_t step = 0;
+  bf16* fw[kLayers] = {};   // forward GEMM weights
+  bf16* bw[kLayers] = {};   // backward-data GEMM weights (layers 1..3)
+  bf16* x0 = nullptr;
+  bf16* h[3] = {};          // hidden activations
+  float* o = nullptr;
+  bf16* ga = nullptr;       // gradient buffers
+  bf16* gb = nullptr;
+  float* part = nullptr;    // weight-gradient partial sums
+  int part_blocks = 0;
+  double* acc = nullptr;    // device doubles: loss, per-image sums
+  int64_t acc_n = 0;
+  bool packed = false;
+};
+
+namespace {
+
+void up_free(sg_upsampler* u) {
+  void* ptrs[] = {u->params, u->grads, u->m, u->v, u->x0, u->o, u->ga, u->gb, u->part, u->acc};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  for (int l = 0; l < kLayers; ++l) {
+    if (u->fw[l]) hipFree(u->fw[l]);
+    if (u->bw[l]) hipFree(u->bw[l]);
+  }
+  for (int i = 0; i < 3; ++i)
+    if (u->h[i]) hipFree(u->h[i]);
+  delete u;
+}
+
+int blocks_of(int64_t n, int per = 256) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 1 << 20));
+}
+
+sg_status pack_weights(sg_upsampler* u, hipStream_t s) {
+  for (int l = 0; l < kLayers; ++l) {
+    const int K = kdim(kCin[l]);
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_of((int64_t)K * kCh)), dim3(256), 0, s,
+                       u->params + layer_off(l), kCin[l], u->fw[l], u->bw[l]);
+  }
+  SG_HIP(hipGetLastError());
+  u->packed = true;
+  return SG_OK;
+}
+
+template <int CIN, int EPI>
+sg_status conv(const bf16* x, int N, int H, int W, const bf16* wt, const float* bias, void* out,
+               const bf16* mask, hipStream_t s) {
+  const int64_t waves = ((int64_t)N * H * W + 63) / 64;
+  hipLaunchKernelGGL((conv_kernel<CIN, EPI>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                     x, N, H, W, reinterpret_cast<const bf16x8*>(wt), bias, out, mask);
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+sg_status check_batch(sg_upsampler* u, int32_t n, int32_t h, int32_t w, const float* rgba,
+                      const float* depth) {
+  if (!u || !rgba || !depth || n < 1 || h < 1 || w < 1)
+    return fail(SG_ERR_INVALID_ARG, "upsampler: NULL input or empty batch");
+  if ((int64_t)n * h * w > u->max_pixels)
+    return fail(SG_ERR_INVALID_ARG, "upsampler: batch larger than max_pixels");
+  return SG_OK;
+}
+
+// x0 and the forward pass (activations kept for the backward pass)
+sg_status forward(sg_upsampler* u, int n, int h, int w, const float* rgba, const float* depth,
+                  double depth_scale, hipStream_t s) {
+  sg_status st;
+  if (!u->packed && (st = pack_weights(u, s)) != SG_OK) return st;
+  const int64_t P = (int64_t)n * h * w;
+  hipLaunchKernelGGL(prep_kernel, dim3(blocks_of(P)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(rgba), depth, P, (float)(1.0 / depth_scale),
+                     u->x0);
+  SG_HIP(hipGetLastError());
+  const float* b = u->params;
+  if ((st = conv<8, kReluBf16>(u->x0, n, h, w, u->fw[0], b + layer_off(0) + 9 * 8 * kCh, u->h[0],
+                               nullptr, s)) != SG_OK)
+    return st;
+  for (int l = 1; l < 3; ++l)
+    if ((st = conv<32, kReluBf16>(u->h[l - 1], n, h, w, u->fw[l],
+                                  b + layer_off(l) + 9 * 32 * kCh, u->h[l], nullptr, s)) != SG_OK)
+      return st;
+  return conv<32, kBiasF32>(u->h[2], n, h, w, u->fw[3], b + layer_off(3) + 9 * 32 * kCh, u->o,
+                            nullptr, s);
+}
+
+template <int CIN>
+sg_status wgrad(sg_upsampler* u, const bf16* x, const bf16* g, int n, int h, int w, int layer,
+                hipStream_t s) {
+  const int64_t P = (int64_t)n * h * w;
+  const int blocks = (int)std::min<int64_t>(u->part_blocks, (P + 63) / 64);
+  const int64_t chunk = (((P + blocks - 1) / blocks + 63) / 64) * 64;
+  const int used = (int)((P + chunk - 1) / chunk);
+  hipLaunchKernelGGL(wgrad_kernel<CIN>, dim3(used), dim3(256), 0, s, x, g, n, h, w, chunk,
+                     u->part);
+  const int64_t nn = layer_size(layer);
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_of(nn)), dim3(256), 0, s, u->part, used, nn,
+                     u->grads + layer_off(layer));
+  SG_HIP(hipGetLastError());
+  return SG_OK;
+}
+
+sg_status gradients(sg_upsampler* u, int n, int h, int w, const float* rgba, const float* depth,
+                    double depth_scale, const float* target, double err_weight, hipStream_t s) {
+  sg_status st = forward(u, n, h, w, rgba, depth, depth_scale, s);
+  if (st != SG_OK) return st;
+  const int64_t P = (int64_t)n * h * w;
+  SG_HIP(hipMemsetAsync(u->acc, 0, sizeof(double), s));
+  hipLaunchKernelGGL(loss_kernel, dim3(blocks_of(P)), dim3(256), 0, s, u->o, u->x0,
+                     reinterpret_cast<const float4*>(target), n, h, w, (float)err_weight, u->ga,
+                     u->acc);
+  SG_HIP(hipGetLastError());
+  // layer 4 (input h3), then back through the ReLUs
+  bf16* g = u->ga;
+  bf16* gn = u->gb;
+  for (int l = 3; l >= 1; --l) {
+    if ((st = wgrad<32>(u, u->h[l - 1], g, n, h, w, l, s)) != SG_OK) return st;
+    if ((st = conv<32, kMaskBf16>(g, n, h, w, u->bw[l], nullptr, gn, u->h[l - 1], s)) != SG_OK)
+      return st;
+    std::swap(g, gn);
+  }
+  return wgrad<8>(u, u->x0, g, n, h, w, 0, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sg_up_param_count(void) { return kParams; }
+
+sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler** out) {
+  if (!out || max_pixels < 1 || max_pixels > ((int64_t)1 << 30))
+    return fail(SG_ERR_INVALID_ARG, "sg_up_create: bad arguments");
+  *out = nullptr;
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "sg_up_create: cannot select device");
+  sg_upsampler* u = new sg_upsampler;
+  u->device = device;
+  u->max_pixels = max_pixels;
+  u->part_blocks = 512;
+  u->acc_n = std::max<int64_t>(2, max_pixels + 1);
+  bool ok = true;
+  auto al = [&](void** p, int64_t bytes) {
+    ok = ok && hipMalloc(p, (size_t)std::max<int64_t>(bytes, 16)) == hipSuccess;
+  };
+  al((void**)&u->params, kParams * 4);
+  al((void**)&u->grads, kParams * 4);
+  al((void**)&u->m, kParams * 4);
+  al((void**)&u->v, kParams * 4);
+  for (int l = 0; l < kLayers; ++l) {
+    al((void**)&u->fw[l], (int64_t)kdim(kCin[l]) * kCh * 2);
+    if (kCin[l] == kCh) al((void**)&u->bw[l], (int64_t)kdim(kCh) * kCh * 2);
+  }
+  al((void**)&u->x0, max_pixels * 8 * 2);
+  for (int i = 0; i < 3; ++i) al((void**)&u->h[i], max_pixels * kCh * 2);
+  al((void**)&u->o, max_pixels * kCh * 4);
+  al((void**)&u->ga, max_pixels * kCh * 2);
+  al((void**)&u->gb, max_pixels * kCh * 2);
+  al((void**)&u->part, (int64_t)u->part_blocks * (9 * 32 * kCh + kCh) * 4);
+  al((void**)&u->acc, u->acc_n * 8);
+  if (!ok) {
+    up_free(u);
+    (void)hipGetLastError();
+    return fail(SG_ERR_OUT_OF_MEMORY, "sg_up_create: device allocation failed");
+  }
+  if (hipMemset(u->params, 0, kParams * 4) != hipSuccess ||
+      hipMemset(u->m, 0, kParams * 4) != hipSuccess ||
+      hipMemset(u->v, 0, kParams * 4) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    up_free(u);
+    return fail(SG_ERR_DEVICE, "sg_up_create: initialisation failed");
+  }
+  *out = u;
+  return SG_OK;
+}
+
+sg_status sg_up_destroy(sg_upsampler* up) {
+  if (!up) return fail(SG_ERR_INVALID_ARG, "sg_up_destroy: NULL");
+  DeviceGuard guard(up->device);
+  (void)hipDeviceSynchronize();
+  up_free(up);
+  return SG_OK;
+}
+
+sg_status sg_up_set_weights(sg_upsampler* up, const float* params, int64_t n) {
+  if (!up || !params || n != kParams) return fail(SG_ERR_INVALID_ARG, "sg_up_set_weights");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return fail(SG_ERR_INVALID_ARG, "weights must be finite");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  SG_HIP(hipMemcpy(up->params, params, (size_t)n * 4, hipMemcpyHostToDevice));
+  SG_HIP(hipMemset(up->m, 0, kParams * 4));
+  SG_HIP(hipMemset(up->v, 0, kParams * 4));
+  up->step = 0;
+  up->packed = false;
+  return SG_OK;
+}
+
+sg_status sg_up_get_weights(sg_upsampler* up, float* params, int64_t n) {
+  if (!up || !params || n != kParams) return fail(SG_ERR_INVALID_ARG, "sg_up_get_weights");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  SG_HIP(hipDeviceSynchronize());
+  SG_HIP(hipMemcpy(params, up->params, (size_t)n * 4, hipMemcpyDeviceToHost));
+  return SG_OK;
+}
+
+sg_status sg_up_forward(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
+                        const float* depth, double depth_scale, float* out_rgba, float* out_err,
+                        double* mse_pred, void* hip_stream) {
+  sg_status st = check_batch(up, n, h, w, rgba, depth);
+  if (st != SG_OK) return st;
+  if (!out_rgba || !(std::isfinite(depth_scale) && depth_scale > 0.0))
+    return fail(SG_ERR_INVALID_ARG, "sg_up_forward: NULL output or bad depth_scale");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
+  if (mse_pred) SG_HIP(hipMemsetAsync(up->acc + 1, 0, sizeof(double) * n, s));
+  const int64_t P = (int64_t)n * h * w;
+  hipLaunchKernelGGL(shuffle_kernel, dim3(blocks_of(P)), dim3(256), 0, s, up->o, up->x0, n, h, w,
+                     reinterpret_cast<float4*>(out_rgba), out_err, mse_pred ? up->acc + 1 : nullptr);
+  SG_HIP(hipGetLastError());
+  if (mse_pred) {
+    SG_HIP(hipMemcpyAsync(mse_pred, up->acc + 1, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) mse_pred[i] /= 4.0 * (double)h * w;
+  }
+  return SG_OK;
+}
+
+sg_status sg_up_gradients(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
+                          const float* depth, double depth_scale, const float* target,
+                          double err_weight, float* grads, double* loss, void* hip_stream) {
+  sg_status st = check_batch(up, n, h, w, rgba, depth);
+  if (st != SG_OK) return st;
+  if (!target || !(std::isfinite(depth_scale) && depth_scale > 0.0) || !std::isfinite(err_weight))
+    return fail(SG_ERR_INVALID_ARG, "sg_up_gradients: NULL target or bad scalars");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = gradients(up, n, h, w, rgba, depth, depth_scale, target, err_weight, s)) != SG_OK)
+    return st;
+  if (grads) SG_HIP(hipMemcpyAsync(grads, up->grads, kParams * 4, hipMemcpyDeviceToHost, s));
+  if (loss) SG_HIP(hipMemcpyAsync(loss, up->acc, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (grads || loss) SG_HIP(hipStreamSynchronize(s));
+  return SG_OK;
+}
+
+sg_status sg_up_train_step(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
+                           const float* depth, double depth_scale, const float* target,
+                           double err_weight, double lr, double* loss, void* hip_stream) {
+  if (!(std::isfinite(lr) && lr > 0.0)) return fail(SG_ERR_INVALID_ARG, "sg_up_train_step: lr");
+  sg_status st = sg_up_gradients(up, n, h, w, rgba, depth, depth_scale, target, err_weight,
+                                 nullptr, loss, hip_stream);
+  if (st != SG_OK) return st;
+  DeviceGuard guard(up->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  up->step += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)up->step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)up->step)));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_of(kParams)), dim3(256), 0, s, up->params,
+                     up->grads, up->m, up->v, kParams, (float)lr, c1, c2);
+  SG_HIP(hipGetLastError());
+  return pack_weights(up, s);
+}
+
+sg_status sg_up_read_buffer(sg_upsampler* up, int32_t which, void* host, int64_t bytes) {
+  if (!up || !host || which < 0 || which > 4 || bytes < 0)
+    return fail(SG_ERR_INVALID_ARG, "sg_up_read_buffer: bad arguments");
+  const void* src[5] = {up->x0, up->h[0], up->h[1], up->h[2], up->o};
+  const int64_t cap = which == 0 ? up->max_pixels * 8 * 2
+                      : which == 4 ? up->max_pixels * kCh * 4
+                                   : up->max_pixels * kCh * 2;
+  if (bytes > cap) return fail(SG_ERR_INVALID_ARG, "sg_up_read_buffer: more than the buffer");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  SG_HIP(hipDeviceSynchronize());
+  SG_HIP(hipMemcpy(host, src[which], (size_t)bytes, hipMemcpyDeviceToHost));
+  return SG_OK;
+}
+
+}  // extern "C"

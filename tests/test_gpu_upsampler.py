@@ -1,0 +1,206 @@
+"""GPU parity of the learned upsampler's MFMA kernels against the FP64
+reference (oracle/upsampler.py).
+
+Each convolution layer is checked on the GPU's own input of that layer
+(bf16-stored activations): hidden layers within one bfloat16 step, the last
+(FP32) layer and the upsampled output to FP32 accumulation error. Gradients
+of the training loss must point the same way as the reference's (bf16
+gradients on the GPU), Adam's first step is checked in closed form, and a
+small problem must train.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import upsampler as U
+
+pytestmark = pytest.mark.gpu
+
+N, H, W = 2, 19, 23  # ragged against the 64-pixel waves
+SCALE = 50.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU (no CPU fallback exists)"
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_params(rng, scale=0.25):
+    out = []
+    for ci, co in U.LAYERS:
+        w = U.to_bf16(rng.normal(size=(9, ci, co)) * scale / np.sqrt(9 * min(ci, 5 if ci == 8
+                                                                               else ci)))
+        b = rng.normal(size=co).astype(np.float32).astype(np.float64) * 0.05
+        out.append((w, b))
+    return out
+
+
+def inputs(rng):
+    import torch
+    rgba = rng.uniform(0, 1, size=(N, H, W, 4)).astype(np.float32)
+    rgba[..., :3] *= rgba[..., 3:4]
+    depth = rng.uniform(0, 300, size=(N, H, W)).astype(np.float32)
+    depth[rng.uniform(size=depth.shape) < 0.2] = np.inf
+    return rgba, depth, torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+
+
+def x0_reference(rgba, depth):
+    """The input tensor as the prep kernel builds it (FP32 arithmetic, then
+    bfloat16)."""
+    inv = np.float32(1.0 / SCALE)
+    code = np.where(np.isfinite(depth), np.float32(1) / (np.float32(1) + depth * inv),
+                    np.float32(0)).astype(np.float32)
+    x0 = np.zeros((N, H, W, 8))
+    x0[..., :4] = U.to_bf16(rgba)
+    x0[..., 4] = U.to_bf16(code)
+    return x0
+
+
+def test_forward_layers_match_reference():
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(11)
+    params = bf16_params(rng)
+    rgba, depth, trgba, tdepth = inputs(rng)
+    u = up.Upsampler(N * H * W)
+    try:
+        u.set_weights(up.pack(params))
+        out = torch.full((N, 2 * H, 2 * W, 4), float("nan"), device="cuda")
+        err = torch.full((N, 2 * H, 2 * W), float("nan"), device="cuda")
+        mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True)
+        P = N * H * W
+        x0 = u.read_buffer(0, (N, H, W, 8), "bf16")
+        assert np.array_equal(x0, x0_reference(rgba, depth))
+        prev = x0
+        for layer in range(3):
+            got = u.read_buffer(1 + layer, (N, H, W, 32), "bf16")
+            w, b = params[layer]
+            ref = U.to_bf16(U.relu(U.conv3x3(prev, w, b)))
+            ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7
+            bad = np.abs(got - ref) > ulp
+            assert bad.mean() < 2e-3 and np.abs(got - ref).max() <= 2 * ulp.max(), layer
+            log("layer %d: %.4f%% of values one bf16 step off" % (layer + 1, 100 * bad.mean()))
+            prev = got
+        o = u.read_buffer(4, (N, H, W, 32), "f32")
+        w, b = params[3]
+        oref = U.conv3x3(prev, w, b)
+        assert np.abs(o - oref).max() <= 1e-5 * max(1.0, np.abs(oref).max())
+        # upsampled output from the GPU's o and x0
+        sh = U.pixel_shuffle(o)
+        ref_rgba = U.bilinear_up2(x0[..., :4]) + sh[..., :4]
+        assert np.abs(out.cpu().numpy() - ref_rgba).max() <= 1e-5
+        assert np.allclose(err.cpu().numpy(), sh[..., 4] ** 2, rtol=1e-5, atol=1e-7)
+        assert np.allclose(mse, (sh[..., 4] ** 2).reshape(N, -1).mean(axis=1), rtol=1e-5)
+        assert P == 874
+    finally:
+        u.close()
+
+
+def test_gradients_match_reference():
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(12)
+    params = bf16_params(rng)
+    rgba, depth, trgba, tdepth = inputs(rng)
+    target = rng.uniform(0, 1, size=(N, 2 * H, 2 * W, 4)).astype(np.float32)
+    u = up.Upsampler(N * H * W)
+    try:
+        u.set_weights(up.pack(params))
+        loss, g = u.gradients(trgba, tdepth, SCALE, torch.from_numpy(target).cuda(), 0.5)
+        x0 = x0_reference(rgba, depth)
+        ref_loss, ref_grads = U.loss_and_grads(params, x0, target, 0.5, act_round=U.to_bf16)
+        assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+        got = up.unpack(g)
+        for layer in range(4):
+            for k in range(2):
+                a = np.asarray(got[layer][k], np.float64).ravel()
+                r = ref_grads[layer][k].ravel()
+                cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
+                rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+                log("layer %d %s: cos %.6f rel %.2e" % (layer + 1, "wb"[k], cos, rel))
+                assert cos > 0.999 and rel < 0.05, (layer, k)
+    finally:
+        u.close()
+
+
+def test_first_adam_step_closed_form():
+    """From zero optimiser state Adam's first bias-corrected step is
+    -lr g / (|g| + eps) for every weight."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(13)
+    params = bf16_params(rng)
+    _, _, trgba, tdepth = inputs(rng)
+    target = torch.from_numpy(rng.uniform(0, 1, size=(N, 2 * H, 2 * W, 4)).astype(np.float32))
+    target = target.cuda()
+    u = up.Upsampler(N * H * W)
+    try:
+        w0 = up.pack(params)
+        u.set_weights(w0)
+        _, g = u.gradients(trgba, tdepth, SCALE, target, 1.0)
+        lr = 1e-3
+        u.train_step(trgba, tdepth, SCALE, target, lr, 1.0)
+        w1 = u.get_weights()
+        expect = w0.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+        live = (np.abs(g) > 1e-12) | (g == 0)  # squares of tinier gradients underflow
+        assert np.abs(w1 - expect)[live].max() <= 1e-6
+        assert live.mean() > 0.99
+    finally:
+        u.close()
+
+
+def test_training_fits_a_small_problem():
+    """Targets made by a fixed random network of the same shape: training
+    from another random start must cut the loss by a large factor."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(14)
+    teacher = bf16_params(rng, 0.5)
+    _, _, trgba, tdepth = inputs(rng)
+    t = up.Upsampler(N * H * W)
+    u = up.Upsampler(N * H * W)
+    try:
+        t.set_weights(up.pack(teacher))
+        target = torch.empty(N, 2 * H, 2 * W, 4, device="cuda")
+        t.forward(trgba, tdepth, SCALE, target)
+        u.set_weights(up.pack(bf16_params(rng, 0.25)))
+        first = None
+        for i in range(300):
+            loss = u.train_step(trgba, tdepth, SCALE, target, 3e-3, 0.0, want_loss=True)
+            first = loss if first is None else first
+        log("loss %.3e -> %.3e" % (first, loss))
+        assert loss < 0.1 * first
+    finally:
+        t.close()
+        u.close()
+
+
+def test_bad_arguments():
+    import torch
+
+    from paper_1804_08197_amd import sg
+    from paper_1804_08197_amd import upsampler as up
+    u = up.Upsampler(100)
+    try:
+        x = torch.zeros(1, 10, 11, 4, device="cuda")
+        d = torch.zeros(1, 10, 11, device="cuda")
+        o = torch.zeros(1, 20, 22, 4, device="cuda")
+        with pytest.raises(sg.SgError):
+            u.forward(x, d, SCALE, o)  # 110 pixels > 100
+        with pytest.raises(sg.SgError):
+            u.set_weights(np.zeros(5, np.float32))
+        with pytest.raises(sg.SgError):
+            u.forward(x[:, :5], d[:, :5], -1.0, o)
+    finally:
+        u.close()
