@@ -71,9 +71,14 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="explicit launch configuration kernel,tile,block,stage_bytes,persistent "
                          "(no autotuning); profiles use the one the benchmark chose")
-    ap.add_argument("--workload", default="tubes", choices=("tubes", "batched64"),
+    ap.add_argument("--workload", default="tubes", choices=("tubes", "batched64", "upsampler"),
                     help="tubes: the bricked stereo frame (default, the headline); "
-                         "batched64: 64 uneven views of the 128^3 blob volume in one call")
+                         "batched64: 64 uneven views of the 128^3 blob volume in one call; "
+                         "upsampler: learned-upsampler path vs plain path on the blob scene")
+    ap.add_argument("--train-pairs", type=int, default=20000,
+                    help="upsampler: training pairs (random pose and window each)")
+    ap.add_argument("--eval-frames", type=int, default=1000,
+                    help="upsampler: held-out stereo frames evaluated")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
@@ -88,6 +93,9 @@ def main():
     torch.cuda.init()
     if args.workload == "batched64":
         bench_batched(args)
+        return
+    if args.workload == "upsampler":
+        bench_upsampler(args)
         return
 
     import gen
@@ -268,6 +276,151 @@ def bench_batched(args):
            "views_per_s": len(views) / (best_ms * 1e-3), "samples_per_batch": samples,
            "default_launch_ms": default_ms, "autotuned_launch": cfg, "autotuned_ms": eager_ms,
            "graph_replay_ms": graph_ms, "raycast_kernel_ms": ray_ms / n_k, "roofline": alu}
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def bench_upsampler(args):
+    """The blob scene (128^3 u8, two levels) in stereo at 1440x1600 per eye:
+    the plain full-resolution path against the learned-upsampler path
+    (half-resolution level-1 render with depth, network, fallback to the
+    plain render when the predicted PSNR is below the threshold). Trains the
+    network first on pairs the ray caster renders (seed 1005), calibrates
+    the threshold on 200 frames (seed 3005), evaluates on held-out frames
+    (seed 2005)."""
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg, upload_volume
+    from paper_1804_08197_amd import upsample as U
+    from paper_1804_08197_amd import upsampler as up
+    W, H = 1440, 1600
+    diag = 128 * math.sqrt(3.0)
+    tan_t = math.tan(math.radians(30))
+    vol = gen.blobs128()
+    h = sg.sg_volume_create((128, 128, 128), dtype=sg.SG_U8, brick=64, levels=2)
+    upload_volume(h, torch.from_numpy(vol).cuda(), 64)
+    sg.sg_set_transfer_function(h, 0, gen.tf_identity(), 0, 255)
+    base = {"step": 0.5, "ert": 0.99, "skip_empty": 1}
+    radius = (1.5 * diag, 4.0 * diag)
+
+    # ---- training (set-up, timed separately)
+    t0 = time.time()
+    poses = gen.orbit_views((64.0, 64.0, 64.0), radius, args.train_pairs, 1005, W, H, tan_t)
+    model = up.Upsampler(max(16 * 128 * 128, 2 * (H // 2) * (W // 2)))
+    rng = np.random.default_rng(1005)
+    model.set_weights(U.init_params(rng))
+    tr = U.Trainer(h, model, diag, base, crop=256, batch=16)
+    steps = max(1, 2 * args.train_pairs // 16)
+    losses = []
+    for i in range(steps):
+        lr = 2e-3 * (0.5 * (1 + math.cos(math.pi * i / steps))) + 1e-5
+        loss = tr.step(rng, poses, lr, 1.0, want_loss=(i % 100 == 0 or i == steps - 1))
+        if loss is not None:
+            losses.append(loss)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log("trained %d steps (%d pairs per epoch, batch 16) in %.1fs, loss %.3e -> %.3e" % (
+        steps, args.train_pairs, train_s, losses[0], losses[-1]))
+
+    path = U.UpsampledPath(h, model, diag, base, W, H, 2)
+    plain = torch.empty(2, H, W, 4, device="cuda")
+    p_full = dict(base, lod=0, bias=0)
+
+    def frame_psnr(views):
+        sg.sg_render_views(h, views, p_full, list(plain))
+        pred = path.predicted_psnr(views)
+        mse = float(((path.out[..., :3] - plain[..., :3]) ** 2).mean())
+        return pred, (math.inf if mse == 0 else 10 * math.log10(1.0 / mse))
+
+    # ---- calibration of the fallback threshold
+    cal = gen.orbit_views((64.0, 64.0, 64.0), radius, 200, 3005, W, H, tan_t, stereo_ipd=8.192)
+    pairs = [frame_psnr(v) for v in cal]
+    # the prediction's worst overestimate on the calibration frames, plus a
+    # 0.5 dB margin, on top of 40 dB: a frame predicted above the threshold
+    # is expected to reach 40 dB
+    over = max(0.0, max(p - a for p, a in pairs))
+    thr = 40.0 + over + 0.5
+    path.threshold_db = thr
+    log("fallback threshold (predicted PSNR): %.2f dB" % thr)
+
+    # ---- evaluation on held-out frames
+    ev = gen.orbit_views((64.0, 64.0, 64.0), radius, args.eval_frames, 2005, W, H, tan_t,
+                         stereo_ipd=8.192)
+    res = [frame_psnr(v) for v in ev]
+    actual = np.array([a for _, a in res])
+    predicted = np.array([p for p, _ in res])
+    accepted = predicted >= thr
+    delivered = np.where(accepted, actual, np.inf)
+    # bilinear baseline (network output zero): the half-resolution render upsampled
+    zero = up.Upsampler(2 * (H // 2) * (W // 2))
+    zero.set_weights(np.zeros(up.param_count(), np.float32))
+    bl = []
+    for v in ev[:200]:
+        sg.sg_render_views(h, v, p_full, list(plain))
+        sg.sg_render_views(h, [U.half_view(x) for x in v], path.p_half, list(path.rgba_lo),
+                           list(path.depth_lo))
+        zero.forward(path.rgba_lo, path.depth_lo, diag, path.out)
+        mse = float(((path.out[..., :3] - plain[..., :3]) ** 2).mean())
+        bl.append(10 * math.log10(1.0 / mse) if mse > 0 else math.inf)
+    zero.close()
+
+    # ---- timing: plain path and upsampler path over the held-out frames
+    sub = ev[:min(len(ev), 200)]
+
+    def run_plain():
+        for v in sub:
+            sg.sg_render_views(h, v, p_full, list(plain))
+
+    def run_up():
+        for v in sub:
+            path.render(v)
+
+    for fn in (run_plain, run_up):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    run_plain()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3 / len(sub)
+    t = time.perf_counter()
+    run_up()
+    torch.cuda.synchronize()
+    up_ms = (time.perf_counter() - t) * 1e3 / len(sub)
+    # network alone (no render, no host read-back)
+    ev_net = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev_net[0].record()
+    for _ in range(50):
+        model.forward(path.rgba_lo, path.depth_lo, diag, path.out)
+    ev_net[1].record()
+    torch.cuda.synchronize()
+    net_ms = ev_net[0].elapsed_time(ev_net[1]) / 50
+    flops = 2 * 2 * (H // 2) * (W // 2) * 9 * 32 * (8 + 32 + 32 + 32)  # MACs x 2, both eyes
+    out = {"metric": "stereo frames/s, plain vs learned-upsampler path at PSNR>=40 dB",
+           "value": 1e3 / up_ms, "unit": "stereo frames/s", "n_gpus": 1,
+           "steps": len(sub), "warmup": 1, "ms_per_step": up_ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network, f32 ray caster",
+           "data": "synthetic",
+           "config": {"workload": "blobs128_u8_stereo_1440x1600_upsampler",
+                      "input": "720x800 per eye on level 1 with depth", "train_pairs":
+                      args.train_pairs, "train_steps": steps, "eval_frames": len(ev)},
+           "plain_ms": plain_ms, "plain_fps": 1e3 / plain_ms, "upsampler_path_ms": up_ms,
+           "speedup_vs_plain": plain_ms / up_ms, "network_ms": net_ms,
+           "network_tflops": flops / (net_ms * 1e-3) / 1e12,
+           "network_roofline": {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12,
+                                "peak": 2500.0, "unit": "TFLOP/s",
+                                "frac": flops / (net_ms * 1e-3) / 1e12 / 2500.0,
+                                "traffic": None},
+           "psnr_upsampled_mean": float(np.mean(actual)),
+           "psnr_upsampled_min": float(np.min(actual)),
+           "psnr_bilinear_mean": float(np.mean(bl)),
+           "frac_upsampled_ge_40db": float(np.mean(actual >= 40.0)),
+           "fallback_threshold_db": thr, "prediction_overestimate_db": over,
+           "fallback_rate": float(1.0 - accepted.mean()),
+           "delivered_min_psnr": float(np.min(delivered)),
+           "delivered_frac_ge_40db": float(np.mean(delivered >= 40.0)),
+           "train_seconds": train_s, "train_loss_first_last": [losses[0], losses[-1]]}
+    model.close()
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
 
