@@ -308,6 +308,16 @@ def cell_tracks(channel, timepoint, dims=CELLS_DIMS, n_cells=200, seed=1003,
     return pos, sig, am, bg_c, bg_a
 
 
+def cells_stereo():
+    """The time series' stereo pair: 1440x1600 per eye, vertical half-FOV 50
+    degrees, horizontal 0.9 tan 50; longest edge 1024 voxels = 1 m, so the
+    64 mm IPD is 65.536 voxels; head 1.25 m from the centre."""
+    c = np.array([512.0, 512.0, 256.0])
+    head = c + 1280.0 * unit((0.3, -1.0, 0.45))
+    t = math.tan(math.radians(50.0))
+    return stereo(head, c, 65.536, 1440, 1600, t, 0.9 * t)
+
+
 CELL_TINTS = ((1.0, 0.2, 0.2), (0.2, 1.0, 0.2), (0.3, 0.3, 1.0))
 CELL_DOMAIN = (0.0, 50000.0)
 TUBE_DOMAIN = (0.0, 65535.0)

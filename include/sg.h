@@ -350,6 +350,19 @@ sg_status sg_render_graph_destroy(sg_render_graph *graph);
 sg_status sg_cache_put(sg_volume *vol, int32_t channel, int32_t timepoint,
                        int32_t level, int32_t n, const int32_t *coords,
                        const void *src, int32_t src_on_device, void *hip_stream);
+/* As sg_cache_put, with brick i's region ((brick+2)^3 voxels, x fastest) at
+ * srcs[i]: for a CPU-memory tier that keeps every chunk on its own (Sec 4.2:
+ * a host cache beside the GPU cache). Each run of regions that lie back to
+ * back in memory (srcs[i+1] = srcs[i] + region bytes) is copied by one DMA
+ * into the library's staging buffer (the memory kind of every pointer is
+ * looked up: page-locked host memory moves at the bus rate, pageable host
+ * memory through the runtime's bounce buffers, device memory directly), then
+ * all n are stored as by sg_cache_put. srcs: host array of n pointers, none
+ * NULL; coords as in sg_cache_put. The regions are consumed before return.
+ * Errors as sg_cache_put. */
+sg_status sg_cache_put_scattered(sg_volume *vol, int32_t channel, int32_t timepoint,
+                                 int32_t level, int32_t n, const int32_t *coords,
+                                 const void *const *srcs, void *hip_stream);
 /* Nodes requested by renders since the last call, then cleared: ids[i]
  * packed as in sg_get_lod_cut, timepoints[i] its timepoint (every channel
  * of it is wanted). *n is the capacity on input, the count on output

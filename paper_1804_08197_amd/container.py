@@ -36,14 +36,16 @@ def _next_level(a):
         s = w.reshape(z, 2, y, 2, x, 2).sum(axis=(1, 3, 5))
         return ((s + 4) >> 3).astype(a.dtype)
     import torch
-    w = a.to(torch.int32)
+    u16 = a.dtype == torch.uint16  # few device kernels take uint16: go through int16 bits
+    w = (a.view(torch.int16).to(torch.int32) & 0xFFFF) if u16 else a.to(torch.int32)
     pz, py, px = (s % 2 for s in w.shape)
     if pz or py or px:
         w = torch.nn.functional.pad(w[None, None].float(), (0, px, 0, py, 0, pz),
                                     mode="replicate")[0, 0].to(torch.int32)
     z, y, x = (s // 2 for s in w.shape)
     s = w.reshape(z, 2, y, 2, x, 2).sum(dim=(1, 3, 5))
-    return ((s + 4) >> 3).to(a.dtype)
+    m = (s + 4) >> 3
+    return m.to(torch.int16).view(torch.uint16) if u16 else m.to(a.dtype)
 
 
 def build_levels(vol0, levels: int):
@@ -70,7 +72,10 @@ def brick_regions(level, brick: int, coords):
     import torch
     dev = level.device
     tz, ty, tx = (torch.from_numpy(a).to(dev) for a in (iz, iy, ix))
-    return level[tz[:, :, None, None], ty[:, None, :, None], tx[:, None, None, :]].contiguous()
+    # gathers do not take uint16 on the device: index the same bits as int16
+    src = level.view(torch.int16) if level.dtype == torch.uint16 else level
+    out = src[tz[:, :, None, None], ty[:, None, :, None], tx[:, None, None, :]].contiguous()
+    return out.view(torch.uint16) if level.dtype == torch.uint16 else out
 
 
 def decode_ids(ids):
@@ -132,3 +137,120 @@ class BrickSource:
         for (t, lev), cs in groups.items():
             self.put(t, lev, np.array(cs), stream)
         return len(order)
+
+
+def level_grids(dims, brick: int, levels: int):
+    """Brick grid (x, y, z) of every level: level dims halve with rounding
+    up; a level is cut into ceil(n / brick) bricks per axis."""
+    d = [int(x) for x in dims]
+    out = []
+    for _ in range(levels):
+        out.append(tuple(-(-x // brick) for x in d))
+        d = [-(-x // 2) for x in d]
+    return out
+
+
+def grid_coords(grid):
+    """Every brick (bx, by, bz) of a grid, x fastest."""
+    bz, by, bx = np.meshgrid(np.arange(grid[2]), np.arange(grid[1]), np.arange(grid[0]),
+                             indexing="ij")
+    return np.stack([bx.ravel(), by.ravel(), bz.ravel()], 1)
+
+
+class HostBrickStore:
+    """The CPU-memory tier beside the GPU cache (Sec 4.2): whole bricks (core
+    plus apron) of every registered (timepoint, channel) pyramid, kept in
+    page-locked host chunks (1 GiB by default), and the loader that answers a cache
+    volume's requests from them with one DMA per brick
+    (``sg_cache_put_scattered``), as a chunk cache hands chunks to the GPU.
+
+    ``add`` takes a level-0 volume on the device (torch [z, y, x]) or the
+    host (numpy), builds its pyramid, cuts every brick and copies it into
+    the chunks; ``served_bytes`` counts what the loader has sent."""
+
+    def __init__(self, handle, dims, brick: int, levels: int, itemsize: int = 2,
+                 chunk_bytes: int = 1 << 30):
+        self.h = handle
+        self.chunk_bytes = int(chunk_bytes)
+        self.B = int(brick)
+        self.levels = int(levels)
+        self.grids = level_grids(dims, self.B, self.levels)
+        self.itemsize = int(itemsize)
+        self.region_bytes = (self.B + 2) ** 3 * self.itemsize
+        self.per_chunk = self.chunk_bytes // self.region_bytes
+        if self.per_chunk < 1:
+            raise ValueError("a brick region is larger than a host chunk")
+        self.chunks = []
+        self.next = self.per_chunk  # regions used in the newest chunk
+        self.addr = {}  # (timepoint, channel, level) -> host addresses, brick order x fastest
+        self.served_bytes = 0
+        self.served_nodes = 0
+
+    def host_bytes(self) -> int:
+        return len(self.chunks) * self.chunk_bytes
+
+    def _slots(self, k):
+        """(chunk tensor, first region index, count <= k) of the next free run."""
+        import torch
+        if self.next == self.per_chunk:
+            self.chunks.append(torch.empty(self.chunk_bytes, dtype=torch.uint8, pin_memory=True))
+            self.next = 0
+        m = min(k, self.per_chunk - self.next)
+        first = self.next
+        self.next += m
+        return self.chunks[-1], first, m
+
+    def channels(self, timepoint):
+        return sorted({c for (t, c, _) in self.addr if t == timepoint})
+
+    def add(self, timepoint: int, channel: int, vol0, batch: int = 256):
+        import torch
+        dt = {1: torch.uint8, 2: torch.uint16}[self.itemsize]
+        S = self.B + 2
+        for lev, arr in enumerate(build_levels(vol0, self.levels)):
+            coords = grid_coords(self.grids[lev])
+            addrs = np.zeros(len(coords), np.uint64)
+            i = 0
+            while i < len(coords):
+                chunk, first, m = self._slots(min(batch, len(coords) - i))
+                reg = brick_regions(arr, self.B, coords[i:i + m])
+                if isinstance(reg, np.ndarray):
+                    reg = torch.from_numpy(reg)
+                off = first * self.region_bytes
+                dst = chunk[off:off + m * self.region_bytes].view(dt).view(m, S, S, S)
+                dst.copy_(reg)
+                addrs[i:i + m] = chunk.data_ptr() + off + \
+                    np.arange(m, dtype=np.uint64) * np.uint64(self.region_bytes)
+                i += m
+            self.addr[(int(timepoint), int(channel), lev)] = addrs
+
+    def _put(self, timepoint, level, coords, stream=None):
+        g = self.grids[level]
+        lin = (coords[:, 2] * g[1] + coords[:, 1]) * g[0] + coords[:, 0]
+        order = np.argsort(lin, kind="stable")  # storage order: neighbours travel together
+        coords, lin = coords[order], lin[order]
+        chans = self.channels(timepoint)
+        for c in chans:
+            sg.sg_cache_put_scattered(self.h, c, timepoint, level, coords,
+                                      self.addr[(timepoint, c, level)][lin], stream=stream)
+        self.served_bytes += len(coords) * len(chans) * self.region_bytes
+        self.served_nodes += len(coords)
+
+    def put_top(self, timepoint, stream=None):
+        """Every top-level brick of every channel (renders need them)."""
+        L = self.levels - 1
+        self._put(int(timepoint), L, grid_coords(self.grids[L]), stream)
+
+    def serve_requests(self, stream=None) -> int:
+        """Load every node the renders since the last call asked for (all
+        channels of its timepoint); returns the number of nodes."""
+        ids, tps = sg.sg_cache_requests(self.h, stream=stream)
+        if not len(ids):
+            return 0
+        L, b = decode_ids(ids)
+        groups = defaultdict(list)
+        for i in np.lexsort((ids, -L)):
+            groups[(int(tps[i]), int(L[i]))].append(b[i])
+        for (t, lev), cs in groups.items():
+            self._put(t, lev, np.asarray(cs, dtype=np.int64), stream)
+        return len(ids)

@@ -128,9 +128,14 @@ bool top_level_resident(const Volume* v, int t) {
 
 using namespace sg;
 
-extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timepoint,
-                                  int32_t level, int32_t n, const int32_t* coords,
-                                  const void* src, int32_t src_on_device, void* hip_stream) {
+namespace {
+
+// Both put entry points: the regions come from one buffer (src, host or
+// device) or from one pointer per brick (srcs, any memory; each copied by
+// its own DMA into the staging buffer).
+sg_status put_impl(sg_volume* vol, int32_t channel, int32_t timepoint, int32_t level, int32_t n,
+                   const int32_t* coords, const void* src, const void* const* srcs,
+                   int32_t src_on_device, void* hip_stream) {
   if (!vol) return fail(SG_ERR_INVALID_ARG, "sg_cache_put: NULL volume");
   Volume* v = &vol->v;
   if (!v->cache) return fail(SG_ERR_UNSUPPORTED, "sg_cache_put: not a cache volume");
@@ -138,7 +143,11 @@ extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timep
       timepoint >= v->d.timepoints || level < 0 || level >= v->L || n < 0)
     return fail(SG_ERR_INVALID_ARG, "sg_cache_put: channel/timepoint/level/n out of range");
   if (n == 0) return SG_OK;
-  if (!coords || !src) return fail(SG_ERR_INVALID_ARG, "sg_cache_put: NULL coords or src");
+  if (!coords || (!src && !srcs))
+    return fail(SG_ERR_INVALID_ARG, "sg_cache_put: NULL coords or source");
+  if (srcs)
+    for (int32_t i = 0; i < n; ++i)
+      if (!srcs[i]) return fail(SG_ERR_INVALID_ARG, "sg_cache_put_scattered: NULL region pointer");
   std::vector<int64_t> ent((size_t)n);
   for (int32_t i = 0; i < n; ++i) {
     for (int a = 0; a < 3; ++a)
@@ -216,8 +225,9 @@ extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timep
   const int64_t data_bytes = S3 * v->bpv * n;
   const int64_t meta = 4 * ((int64_t)2 * n + 2 * (int64_t)pidx.size());
   const int64_t meta_pad = ((meta + 255) / 256) * 256;
+  const bool staged = srcs || !src_on_device;
   uint8_t* tmp = nullptr;
-  SG_HIP(hipMallocAsync((void**)&tmp, (size_t)(meta_pad + (src_on_device ? 0 : data_bytes)), s));
+  SG_HIP(hipMallocAsync((void**)&tmp, (size_t)(meta_pad + (staged ? data_bytes : 0)), s));
   std::vector<int32_t> host_meta;
   host_meta.insert(host_meta.end(), slot.begin(), slot.end());
   for (int64_t e : ent) host_meta.push_back((int32_t)e);
@@ -225,7 +235,18 @@ extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timep
   host_meta.insert(host_meta.end(), pval.begin(), pval.end());
   SG_HIP(hipMemcpyAsync(tmp, host_meta.data(), host_meta.size() * 4, hipMemcpyHostToDevice, s));
   const void* dsrc = src;
-  if (!src_on_device) {
+  if (srcs) {
+    // one copy per run of regions that lie back to back in the source
+    const size_t region = (size_t)(S3 * v->bpv);
+    for (int32_t i = 0; i < n;) {
+      int32_t j = i + 1;
+      while (j < n && (const uint8_t*)srcs[j] == (const uint8_t*)srcs[j - 1] + region) ++j;
+      SG_HIP(hipMemcpyAsync(tmp + meta_pad + region * (size_t)i, srcs[i],
+                            region * (size_t)(j - i), hipMemcpyDefault, s));
+      i = j;
+    }
+    dsrc = tmp + meta_pad;
+  } else if (!src_on_device) {
     SG_HIP(hipMemcpyAsync(tmp + meta_pad, src, (size_t)data_bytes, hipMemcpyHostToDevice, s));
     dsrc = tmp + meta_pad;
   }
@@ -258,6 +279,22 @@ extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timep
   SG_HIP(hipFreeAsync(tmp, s));
   v->empty_dirty = true;
   return SG_OK;
+}
+
+}  // namespace
+
+extern "C" sg_status sg_cache_put(sg_volume* vol, int32_t channel, int32_t timepoint,
+                                  int32_t level, int32_t n, const int32_t* coords,
+                                  const void* src, int32_t src_on_device, void* hip_stream) {
+  return put_impl(vol, channel, timepoint, level, n, coords, src, nullptr, src_on_device,
+                  hip_stream);
+}
+
+extern "C" sg_status sg_cache_put_scattered(sg_volume* vol, int32_t channel, int32_t timepoint,
+                                            int32_t level, int32_t n, const int32_t* coords,
+                                            const void* const* srcs, void* hip_stream) {
+  if (!srcs && n > 0) return fail(SG_ERR_INVALID_ARG, "sg_cache_put_scattered: NULL srcs");
+  return put_impl(vol, channel, timepoint, level, n, coords, nullptr, srcs, 0, hip_stream);
 }
 
 extern "C" sg_status sg_cache_requests(sg_volume* vol, uint64_t* ids, int32_t* timepoints,

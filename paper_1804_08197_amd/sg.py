@@ -110,6 +110,8 @@ _lib.sg_render_graph_launch.argtypes = [_P, _P]
 _lib.sg_render_graph_destroy.argtypes = [_P]
 _lib.sg_cache_put.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                               C.POINTER(C.c_int32), _P, C.c_int32, _P]
+_lib.sg_cache_put_scattered.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_void_p), _P]
 _lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), _P]
 _lib.sg_cache_get_info.argtypes = [_P, C.POINTER(sg_cache_info)]
@@ -125,7 +127,8 @@ for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_buil
            "sg_set_kernel_timing", "sg_get_kernel_timing", "sg_set_launch_config",
            "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
            "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy",
-           "sg_cache_put", "sg_cache_requests", "sg_cache_get_info", "sg_cache_resident"):
+           "sg_cache_put", "sg_cache_put_scattered", "sg_cache_requests", "sg_cache_get_info",
+           "sg_cache_resident"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -436,6 +439,20 @@ def sg_cache_put(vol, channel, timepoint, level, coords, regions, stream=None):
     _check(_lib.sg_cache_put(vol, int(channel), int(timepoint), int(level), len(coords),
                              coords.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(regions),
                              int(bool(on_dev)), _stream(stream)), "sg_cache_put")
+
+
+def sg_cache_put_scattered(vol, channel, timepoint, level, coords, addrs, stream=None):
+    """Store whole bricks of one (channel, timepoint, level) whose regions
+    ([B+2]^3 voxels each) sit at the addresses addrs[i] (integers: host or
+    device pointers), one DMA per brick."""
+    coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
+    addrs = np.ascontiguousarray(addrs, dtype=np.uint64).reshape(-1)
+    if len(addrs) != len(coords):
+        raise ValueError("one address per brick")
+    _check(_lib.sg_cache_put_scattered(vol, int(channel), int(timepoint), int(level),
+                                       len(coords), coords.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       addrs.ctypes.data_as(C.POINTER(C.c_void_p)),
+                                       _stream(stream)), "sg_cache_put_scattered")
 
 
 def sg_cache_requests(vol, stream=None):

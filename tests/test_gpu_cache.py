@@ -233,6 +233,85 @@ def test_time_series_streams_through_a_smaller_cache():
         sg.sg_volume_destroy(h)
 
 
+def test_scattered_puts_from_the_host_tier_pageable_and_device_memory():
+    """sg_cache_put_scattered: bricks served from page-locked host chunks
+    (HostBrickStore) converge to the all-resident image of every timepoint;
+    bricks scattered in pageable host memory (channel 0) and device memory
+    (channel 1) store exactly what the all-resident volume holds."""
+    import torch
+
+    from paper_1804_08197_amd import sg
+    from paper_1804_08197_amd.container import (HostBrickStore, brick_regions, build_levels,
+                                                grid_coords, level_grids)
+    T, C = 2, 2
+    vols = [[gen.random_volume(DIMS_ZYX, 700 + 10 * t + c, dtype=np.uint16) for c in range(C)]
+            for t in range(T)]
+    tf = (gen.tf_hot() * np.array([1, 1, 1, 0.3])).astype(np.float32)
+    vs = views()
+    p0 = {"ert": ERT, "tau": 1.0}
+    dims0 = DIMS_ZYX[::-1]
+    refs = []
+    for t in range(T):
+        full = make_full(vols[t], tf)
+        refs.append(render(full, vs, p0))
+        sg.sg_volume_destroy(full)
+
+    h = sg.sg_volume_create(dims0, channels=C, timepoints=T, dtype=sg.SG_U16, brick=B,
+                            levels=LEVELS, cache_slots=4000)
+    try:
+        for c in range(C):
+            sg.sg_set_transfer_function(h, c, tf, 0, 65535)
+        store = HostBrickStore(h, dims0, B, LEVELS, 2, chunk_bytes=1 << 22)
+        for t in range(T):
+            for c in range(C):
+                store.add(t, c, vols[t][c] if c == 0 else torch.from_numpy(vols[t][c]).cuda())
+        for t in range(T):
+            store.put_top(t)
+        for t in range(T):
+            p = dict(p0, timepoint=t)
+            rounds = 0
+            while True:
+                img = render(h, vs, p)
+                if store.serve_requests() == 0:
+                    break
+                rounds += 1
+                assert rounds <= LEVELS
+            for a, b in zip(img, refs[t]):
+                assert np.array_equal(a, b), t
+        log("host tier: %d nodes, %.1f MB served" % (store.served_nodes, store.served_bytes / 1e6))
+    finally:
+        sg.sg_volume_destroy(h)
+
+    grids = level_grids(dims0, B, LEVELS)
+    h = sg.sg_volume_create(dims0, channels=C, dtype=sg.SG_U16, brick=B, levels=LEVELS,
+                            cache_slots=4000)
+    try:
+        for c in range(C):
+            sg.sg_set_transfer_function(h, c, tf, 0, 65535)
+        keep = []
+        for c in range(C):
+            for L, arr in enumerate(build_levels(vols[0][c], LEVELS)):
+                coords = grid_coords(grids[L])
+                regs = brick_regions(arr, B, coords)
+                # one separate buffer per brick, in reverse order of address
+                bufs = [np.ascontiguousarray(r) for r in regs[::-1]][::-1]
+                if c == 1:
+                    bufs = [torch.from_numpy(r).cuda() for r in bufs]
+                    addrs = [b.data_ptr() for b in bufs]
+                else:
+                    addrs = [b.ctypes.data for b in bufs]
+                sg.sg_cache_put_scattered(h, c, 0, L, coords, addrs)
+                keep.append(bufs)
+        img = render(h, vs, p0)
+        for a, b in zip(img, refs[0]):
+            assert np.array_equal(a, b)
+        with pytest.raises(sg.SgError) as ex:
+            sg.sg_cache_put_scattered(h, 0, 0, 0, [[0, 0, 0]], [0])
+        assert ex.value.status == sg.SG_ERR_INVALID_ARG
+    finally:
+        sg.sg_volume_destroy(h)
+
+
 def test_cache_volume_errors(data):
     from paper_1804_08197_amd import sg
     vol, tf = data

@@ -109,13 +109,6 @@ def test_tubes_2048_stereo_parity(gpu):
         sg.sg_volume_destroy(h)
 
 
-def cell_views():
-    c = np.array([512.0, 512.0, 256.0])
-    head = c + 1280.0 * gen.unit((0.3, -1.0, 0.45))
-    t = math.tan(math.radians(50.0))
-    return gen.stereo(head, c, 65.536, 1440, 1600, t, 0.9 * t)
-
-
 def test_cells_multichannel_timepoints_parity(gpu):
     import oracle
     from gen.large import CellVolume, upload_generated
@@ -136,7 +129,7 @@ def test_cells_multichannel_timepoints_parity(gpu):
         tfs = [gen.tf_tint(tint) for tint in gen.CELL_TINTS]
         for c in range(3):
             sg.sg_set_transfer_function(h, c, tfs[c], *gen.CELL_DOMAIN)
-        views = cell_views()
+        views = gen.cells_stereo()
         for ti in range(len(tps)):
             params = {"ert": ERT, "tau": 1.0, "timepoint": ti}
             rgba, ns, st = render_with_counts(h, views, params)
