@@ -86,6 +86,9 @@ def main():
                     help="upsampler: training pairs (random pose and window each)")
     ap.add_argument("--eval-frames", type=int, default=1000,
                     help="upsampler: held-out stereo frames evaluated")
+    ap.add_argument("--scene", default="blobs", choices=("blobs", "tubes"),
+                    help="upsampler: the 128^3 blob scene (default) or the 2048^3 tube "
+                         "volume with the screen-space LOD")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
@@ -290,37 +293,72 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_upsampler(args):
-    """The blob scene (128^3 u8, two levels) in stereo at 1440x1600 per eye:
-    the plain full-resolution path against the learned-upsampler path
-    (half-resolution level-1 render with depth, network, fallback to the
-    plain render when the predicted PSNR is below the threshold). Trains the
-    network first on pairs the ray caster renders (seed 1005), calibrates
-    the threshold on 200 frames (seed 3005), evaluates on held-out frames
-    (seed 2005)."""
+def upsampler_scene(args):
+    """The volume and poses of the upsampler workload. blobs (the default):
+    the 128^3 u8 blob volume with two levels, no LOD (target on level 0,
+    input on level 1), 60 degree vertical FOV, eyes at 1.5-4 diagonals, IPD
+    8.192. tubes: the 2048^3 u16 tube volume with its 6 levels and the
+    screen-space LOD at 1 pixel (target = the plain bricked stereo frame;
+    the half-resolution input lands one level coarser by itself), the HMD
+    frustum (half-FOV 50 degrees), heads at 0.9-1.5 m (1843-3072 voxels),
+    IPD 131.072."""
     import torch
 
     import gen
     from paper_1804_08197_amd import sg, upload_volume
+    if args.scene == "blobs":
+        vol = gen.blobs128()
+        h = sg.sg_volume_create((128, 128, 128), dtype=sg.SG_U8, brick=64, levels=2)
+        upload_volume(h, torch.from_numpy(vol).cuda(), 64)
+        sg.sg_set_transfer_function(h, 0, gen.tf_identity(), 0, 255)
+        diag = 128 * math.sqrt(3.0)
+        return {"h": h, "diag": diag, "center": (64.0, 64.0, 64.0),
+                "radius": (1.5 * diag, 4.0 * diag), "tan": math.tan(math.radians(30)),
+                "ipd": 8.192, "lod": False,
+                "workload": "blobs128_u8_stereo_1440x1600_upsampler",
+                "input": "720x800 per eye on level 1 with depth"}
+    from gen.large import TubeVolume, upload_generated
+    dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
+    tv = TubeVolume().to_device()
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
+    sg.sg_build_lod(h, 0, 0)
+    sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
+    sg.sg_volume_commit(h)
+    torch.cuda.synchronize()
+    return {"h": h, "diag": 2048 * math.sqrt(3.0), "center": (1024.0, 1024.0, 1024.0),
+            "radius": (1843.2, 3072.0), "tan": math.tan(math.radians(50)), "ipd": 131.072,
+            "lod": True, "workload": "tubes2048_u16_stereo_1440x1600_upsampler",
+            "input": "720x800 per eye, screen-space LOD (one level coarser), with depth"}
+
+
+def bench_upsampler(args):
+    """A scene in stereo at 1440x1600 per eye: the plain full-resolution path
+    against the learned-upsampler path (half-resolution render one level
+    coarser with depth, network, fallback to the plain render when the
+    predicted PSNR is below the threshold). Trains the network first on
+    pairs the ray caster renders (seed 1005), calibrates the threshold on
+    200 frames (seed 3005), evaluates on held-out frames (seed 2005)."""
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg
     from paper_1804_08197_amd import upsample as U
     from paper_1804_08197_amd import upsampler as up
     W, H = 1440, 1600
-    diag = 128 * math.sqrt(3.0)
-    tan_t = math.tan(math.radians(30))
-    vol = gen.blobs128()
-    h = sg.sg_volume_create((128, 128, 128), dtype=sg.SG_U8, brick=64, levels=2)
-    upload_volume(h, torch.from_numpy(vol).cuda(), 64)
-    sg.sg_set_transfer_function(h, 0, gen.tf_identity(), 0, 255)
-    base = {"step": 0.5, "ert": 0.99, "skip_empty": 1}
-    radius = (1.5 * diag, 4.0 * diag)
+    t0 = time.time()
+    sc = upsampler_scene(args)
+    log("scene %s ready in %.1fs" % (args.scene, time.time() - t0))
+    h, diag, center, radius, tan_t = sc["h"], sc["diag"], sc["center"], sc["radius"], sc["tan"]
+    base = {"step": 0.5, "ert": 0.99, "skip_empty": 1, "tau": 1.0}
 
     # ---- training (set-up, timed separately)
     t0 = time.time()
-    poses = gen.orbit_views((64.0, 64.0, 64.0), radius, args.train_pairs, 1005, W, H, tan_t)
+    poses = gen.orbit_views(center, radius, args.train_pairs, 1005, W, H, tan_t)
     model = up.Upsampler(max(16 * 128 * 128, 2 * (H // 2) * (W // 2)))
     rng = np.random.default_rng(1005)
     model.set_weights(U.init_params(rng))
-    tr = U.Trainer(h, model, diag, base, crop=256, batch=16)
+    tr = U.Trainer(h, model, diag, base, crop=256, batch=16, lod=sc["lod"])
     steps = max(1, 2 * args.train_pairs // 16)
     losses = []
     for i in range(steps):
@@ -333,9 +371,9 @@ def bench_upsampler(args):
     log("trained %d steps (%d pairs per epoch, batch 16) in %.1fs, loss %.3e -> %.3e" % (
         steps, args.train_pairs, train_s, losses[0], losses[-1]))
 
-    path = U.UpsampledPath(h, model, diag, base, W, H, 2)
+    path = U.UpsampledPath(h, model, diag, base, W, H, 2, lod=sc["lod"])
     plain = torch.empty(2, H, W, 4, device="cuda")
-    p_full = dict(base, lod=0, bias=0)
+    p_full = path.p_full
 
     def frame_psnr(views):
         sg.sg_render_views(h, views, p_full, list(plain))
@@ -344,7 +382,7 @@ def bench_upsampler(args):
         return pred, (math.inf if mse == 0 else 10 * math.log10(1.0 / mse))
 
     # ---- calibration of the fallback threshold
-    cal = gen.orbit_views((64.0, 64.0, 64.0), radius, 200, 3005, W, H, tan_t, stereo_ipd=8.192)
+    cal = gen.orbit_views(center, radius, 200, 3005, W, H, tan_t, stereo_ipd=sc["ipd"])
     pairs = [frame_psnr(v) for v in cal]
     # the prediction's worst overestimate on the calibration frames, plus a
     # 0.5 dB margin, on top of 40 dB: a frame predicted above the threshold
@@ -355,8 +393,8 @@ def bench_upsampler(args):
     log("fallback threshold (predicted PSNR): %.2f dB" % thr)
 
     # ---- evaluation on held-out frames
-    ev = gen.orbit_views((64.0, 64.0, 64.0), radius, args.eval_frames, 2005, W, H, tan_t,
-                         stereo_ipd=8.192)
+    ev = gen.orbit_views(center, radius, args.eval_frames, 2005, W, H, tan_t,
+                         stereo_ipd=sc["ipd"])
     res = [frame_psnr(v) for v in ev]
     actual = np.array([a for _, a in res])
     predicted = np.array([p for p, _ in res])
@@ -382,11 +420,20 @@ def bench_upsampler(args):
         for v in sub:
             sg.sg_render_views(h, v, p_full, list(plain))
 
-    def run_up():
+    def run_up_host():
+        fell = 0
         for v in sub:
-            path.render(v)
+            fell += path.render(v)[1]
+        return fell
 
-    for fn in (run_plain, run_up):
+    flags = torch.zeros(len(sub), dtype=torch.int32, device="cuda")
+
+    def run_up():
+        # the product path: the fallback decision stays on the device
+        for i, v in enumerate(sub):
+            path.render_device(v, flags[i:i + 1])
+
+    for fn in (run_plain, run_up_host, run_up):
         fn()
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -394,9 +441,16 @@ def bench_upsampler(args):
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t) * 1e3 / len(sub)
     t = time.perf_counter()
+    fell_host = run_up_host()
+    torch.cuda.synchronize()
+    up_host_ms = (time.perf_counter() - t) * 1e3 / len(sub)
+    flags.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
     run_up()
     torch.cuda.synchronize()
     up_ms = (time.perf_counter() - t) * 1e3 / len(sub)
+    fell = int(flags.sum().item())
     # network alone (no render, no host read-back)
     ev_net = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev_net[0].record()
@@ -411,16 +465,18 @@ def bench_upsampler(args):
            "steps": len(sub), "warmup": 1, "ms_per_step": up_ms, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network, f32 ray caster",
            "data": "synthetic",
-           "config": {"workload": "blobs128_u8_stereo_1440x1600_upsampler",
-                      "input": "720x800 per eye on level 1 with depth", "train_pairs":
-                      args.train_pairs, "train_steps": steps, "eval_frames": len(ev)},
+           "config": {"workload": sc["workload"], "input": sc["input"],
+                      "train_pairs": args.train_pairs, "train_steps": steps,
+                      "eval_frames": len(ev)},
            "plain_ms": plain_ms, "plain_fps": 1e3 / plain_ms, "upsampler_path_ms": up_ms,
-           "speedup_vs_plain": plain_ms / up_ms, "network_ms": net_ms,
+           "speedup_vs_plain": plain_ms / up_ms, "timed_fallbacks": fell,
+           "upsampler_path_host_decision_ms": up_host_ms,
+           "timed_fallbacks_host_decision": int(fell_host),
+           "network_ms": net_ms,
            "network_tflops": flops / (net_ms * 1e-3) / 1e12,
-           "network_roofline": {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12,
-                                "peak": 2500.0, "unit": "TFLOP/s",
-                                "frac": flops / (net_ms * 1e-3) / 1e12 / 2500.0,
-                                "traffic": None},
+           "roofline": {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12,
+                        "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": flops / (net_ms * 1e-3) / 1e12 / 2500.0, "traffic": None},
            "psnr_upsampled_mean": float(np.mean(actual)),
            "psnr_upsampled_min": float(np.min(actual)),
            "psnr_bilinear_mean": float(np.mean(bl)),

@@ -228,6 +228,19 @@ sg_status sg_render_views(sg_volume *vol, int32_t n_views, const sg_view *views,
                           const sg_render_params *params, float *const *out_rgba,
                           float *const *out_depth, void *hip_stream);
 
+/* sg_render_views whose execution is decided on the device: enable is a
+ * device int32 read by the render's kernels when they run (stream order);
+ * nonzero renders exactly as sg_render_views, zero makes every kernel return
+ * at once, so the outputs keep their contents (and a cache volume records no
+ * requests or uses). For decisions taken by earlier device work without a
+ * host round trip, such as the upsampler's fallback to the full-resolution
+ * render (sg_up_forward_flag). enable must not be NULL
+ * (SG_ERR_INVALID_ARG). */
+sg_status sg_render_views_if(sg_volume *vol, int32_t n_views, const sg_view *views,
+                             const sg_render_params *params, float *const *out_rgba,
+                             float *const *out_depth, const int32_t *enable,
+                             void *hip_stream);
+
 /* Same render with instrumentation (per-pixel sample counts, total samples,
  * distinct micro-blocks read). Synchronises hip_stream before returning so
  * that the host counters are valid. Slower; for tests and measurement. */

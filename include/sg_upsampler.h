@@ -62,6 +62,17 @@ sg_status sg_up_forward(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
                         float *out_rgba, float *out_err, double *mse_pred,
                         void *hip_stream);
 
+/* Inference as sg_up_forward, and the fallback decision taken on the device
+ * without a host round trip: *fallback (device int32) = 1 when the frame's
+ * predicted PSNR, 10 log10(1 / m) with m the mean over the n images of
+ * their mean predicted squared error, is below threshold_db, else 0. Pass
+ * the flag to sg_render_views_if to render the frame at full resolution
+ * only when the prediction fails. Asynchronous. */
+sg_status sg_up_forward_flag(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
+                             const float *rgba, const float *depth, double depth_scale,
+                             float *out_rgba, float *out_err, double threshold_db,
+                             int32_t *fallback, void *hip_stream);
+
 /* Gradients of the training loss (mean squared RGBA error against target,
  * plus err_weight times the mean squared error of the error head against
  * each pixel's actual RMS RGB error, held constant) for one batch:
@@ -81,9 +92,19 @@ sg_status sg_up_train_step(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
                            const float *target, double err_weight, double lr,
                            double *loss, void *hip_stream);
 
-/* Test hook: copy the first `bytes` of an activation of the last forward
- * or gradient call to host memory (synchronises the device): which = 0 x0
- * (bf16 [P][8]), 1..3 h1..h3 (bf16 [P][32]), 4 o (float [P][32]). */
+/* How sg_up_forward runs the network: fused != 0 (the default) in one
+ * kernel per 16 x 16 tile of low-resolution pixels with every activation in
+ * LDS; fused == 0 layer by layer through device buffers (the path training
+ * uses; it leaves the activations sg_up_read_buffer returns). Both give the
+ * same output bit for bit (same products, same accumulation order); the
+ * predicted mean squared errors may differ in the last bits (per-image sums
+ * taken in another order). */
+sg_status sg_up_set_fused(sg_upsampler *up, int32_t fused);
+
+/* Test hook: copy the first `bytes` of an activation of the last gradient
+ * call, or of the last forward call made layer by layer, to host memory
+ * (synchronises the device): which = 0 x0 (bf16 [P][8]), 1..3 h1..h3 (bf16
+ * [P][32]), 4 o (float [P][32]). */
 sg_status sg_up_read_buffer(sg_upsampler *up, int32_t which, void *host, int64_t bytes);
 
 #ifdef __cplusplus

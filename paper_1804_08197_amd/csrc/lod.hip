@@ -47,6 +47,7 @@ struct CutGeom {
   uint32_t* req_flags;       // [T * nodes] bits
   uint32_t* req_list;
   uint32_t* req_count;
+  const int32_t* enable;     // NULL, or a device flag: 0 = do nothing
 };
 
 __device__ __forceinline__ bool node_resident(const CutGeom& g, int64_t node) {
@@ -102,6 +103,7 @@ __device__ __forceinline__ bool node_suits(const CutGeom& g, const double e[3],
 
 __global__ void cutmap_kernel(CutGeom g, const ViewDev* views, int n_views,
                               int32_t* cutmap) {
+  if (g.enable && *g.enable == 0) return;
   const int64_t total = (int64_t)n_views * g.cells;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -155,8 +157,10 @@ CutGeom cut_geom(const Volume* v, int bias, bool lod, int timepoint) {
 }  // namespace
 
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, int timepoint, int32_t* cutmap, Launch* out) {
+                        bool lod, int timepoint, int32_t* cutmap, Launch* out,
+                        const int32_t* enable) {
   CutGeom g = cut_geom(v, bias, lod, timepoint);
+  g.enable = enable;
   int64_t total = (int64_t)n_views * g.cells;
   int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   out->func = reinterpret_cast<const void*>(cutmap_kernel);
@@ -172,9 +176,10 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
 }
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, int timepoint, hipStream_t s) {
+                        bool lod, int timepoint, hipStream_t s, const int32_t* enable) {
   Launch l;
-  sg_status st = cutmap_launch(v, dviews, n_views, bias, lod, timepoint, v->cutmap, &l);
+  sg_status st =
+      cutmap_launch(v, dviews, n_views, bias, lod, timepoint, v->cutmap, &l, enable);
   if (st != SG_OK) return st;
   return l.run(s);
 }

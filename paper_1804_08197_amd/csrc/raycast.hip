@@ -315,7 +315,8 @@ sg_status check_volume_ready(Volume* v) {
 
 sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
                  const sg_render_params* params, float* const* out_rgba,
-                 float* const* out_depth, sg_render_stats* stats, void* hip_stream) {
+                 float* const* out_depth, sg_render_stats* stats, void* hip_stream,
+                 const int32_t* enable = nullptr) {
   if (!vol) return fail(SG_ERR_INVALID_ARG, "volume is NULL");
   Volume* v = &vol->v;
   if (!params || !out_rgba) return fail(SG_ERR_INVALID_ARG, "params / out_rgba is NULL");
@@ -340,7 +341,7 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   ++v->frame;
   if (timed && (st = timing_mark(v, s)) != SG_OK) return st;
   st = launch_cutmap(v, dv, n_views, params->lod_bias, (params->flags & SG_LOD) != 0,
-                     params->timepoint, s);
+                     params->timepoint, s, enable);
   if (st != SG_OK) return st;
   if (cfg.persistent) {
     Launch q = queue_reset_launch(v->queue);
@@ -350,6 +351,7 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
 
   RenderArgs a;
   fill_args(v, params, n_views, dv, v->cutmap, blocks, cfg, &a);
+  a.enable = enable;
   const int C = v->d.channels;
   if (stats) {
     // micro-block bitmap: one bit per 4^3 block per (channel, level)
@@ -435,6 +437,14 @@ extern "C" sg_status sg_render_views(sg_volume* vol, int32_t n_views, const sg_v
                                      const sg_render_params* params, float* const* out_rgba,
                                      float* const* out_depth, void* hip_stream) {
   return render(vol, n_views, views, params, out_rgba, out_depth, nullptr, hip_stream);
+}
+
+extern "C" sg_status sg_render_views_if(sg_volume* vol, int32_t n_views, const sg_view* views,
+                                        const sg_render_params* params, float* const* out_rgba,
+                                        float* const* out_depth, const int32_t* enable,
+                                        void* hip_stream) {
+  if (!enable) return fail(SG_ERR_INVALID_ARG, "sg_render_views_if: NULL enable flag");
+  return render(vol, n_views, views, params, out_rgba, out_depth, nullptr, hip_stream, enable);
 }
 
 extern "C" sg_status sg_render_views_stats(sg_volume* vol, int32_t n_views,

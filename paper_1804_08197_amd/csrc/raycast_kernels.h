@@ -627,6 +627,7 @@ __device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* 
 // The two are separate instances because the loop costs registers.
 template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
 __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
+  if (a.enable && *a.enable == 0) return;  // whole grid: before any barrier
   extern __shared__ float4 s_tf[];
   load_tf<CH>(a, s_tf);
   if (!LOOP) {
@@ -959,6 +960,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
 
 template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
 __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
+  if (a.enable && *a.enable == 0) return;  // whole grid: before any barrier
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
   load_tf<CH>(a, s_tf);

@@ -211,7 +211,8 @@ struct ViewDev {
 };
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
-                        int bias, bool lod, int timepoint, hipStream_t s);
+                        int bias, bool lod, int timepoint, hipStream_t s,
+                        const int32_t* enable = nullptr);
 // rgba may be NULL (cut queries); the render path checks it itself.
 sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         const sg_render_params* p, float* const* rgba,
@@ -224,8 +225,10 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       int32_t* const* nsamp, int bt_log, std::vector<ViewDev>* hv,
                       int64_t* total_blocks);
 // The cut-map kernel for views already on the device, writing `cutmap`.
+// enable: NULL, or a device flag read by the kernel (0: it does nothing).
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
-                        bool lod, int timepoint, int32_t* cutmap, Launch* out);
+                        bool lod, int timepoint, int32_t* cutmap, Launch* out,
+                        const int32_t* enable = nullptr);
 
 struct RenderArgs {
   const uint8_t* pool;
@@ -272,6 +275,7 @@ struct RenderArgs {
   int32_t roi_on;
   double planes[4][4];  // plane j keeps (n . p) + w <= 0: (nx, ny, nz, w)
   double roi[6];        // region of interest lo xyz, hi xyz
+  const int32_t* enable;  // NULL, or a device flag: 0 = every workgroup returns at once
 };
 
 // The ray-casting launch (kernel, grid, LDS) for arguments `a`; a.grid is

@@ -6,17 +6,15 @@
 // sg_upsampler.h). Activations are NHWC bfloat16 with 8 (input) or 32
 // channels, so one pixel's channels are one contiguous 16- or 64-byte run.
 //
-// Convolution = implicit GEMM on the matrix cores: a wave computes 64
-// consecutive pixels x 32 output channels with v_mfma_f32_16x16x32_bf16
-// (four 16-pixel row blocks x two 16-channel column blocks, FP32
-// accumulators). The GEMM's K runs over (tap, input channel): with 32
-// input channels one K-step of 32 is one tap; with 8 input channels one
-// K-step covers four taps (K = 72 padded to 96). Operand layouts of the
-// instruction (lane l): A[row l % 16][k 8 (l / 16) .. + 7], B[k 8 (l / 16)
-// .. + 7][column l % 16], result rows 4 (l / 16) .. + 3 of column l % 16.
-// So a lane's A operand is 8 consecutive channels of one pixel at one tap
-// (one 16-byte load) and its B operand 8 consecutive K of one output
-// channel, stored that way ([K / 8][32][8]) when the weights are packed.
+// Convolution = implicit GEMM on the matrix cores, taken transposed: 32
+// output channels x 32 pixels per v_mfma_f32_32x32x16_bf16, FP32
+// accumulators, the weights as the A operand and the pixels as B. The
+// GEMM's K runs over (tap, input channel) in steps of 16: with 32 input
+// channels a tap is two K-steps; with 8 input channels a K-step covers two
+// taps (K = 72 padded to 80). A lane's A operand is 8 consecutive K of one
+// output channel (the weights are packed that way, [K / 8][32][8]) and its
+// B operand 8 consecutive channels of one pixel at one tap (one 16-byte
+// load); its results are 16 channels (four runs of four) of one pixel.
 //
 // Backward: the input gradient of a 3x3 convolution is a 3x3 convolution of
 // the output gradient with the taps mirrored and the channel roles swapped,
@@ -60,6 +58,27 @@ constexpr int kdim(int cin) { return ((9 * cin + 31) / 32) * 32; }
 
 __device__ __forceinline__ float bf(bf16 x) { return (float)x; }
 
+// The products run on v_mfma_f32_32x32x16_bf16 (on gfx950 it sustains
+// about 1.6x the rate of the 16x16x32 form). Operand layouts (lane l,
+// half = l / 32): A[row l % 32][k 8 half .. + 7], B[k 8 half .. + 7][column
+// l % 32]; result register r holds row 8 (r / 4) + 4 half + r % 4 of column
+// l % 32. A K-step is 16 K; K runs over (tap, input channel), padded to a
+// multiple of 16 (72 -> 80 for 8 input channels).
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int ksteps(int cin) { return (9 * cin + 15) / 16; }
+__device__ __forceinline__ int acc_channel(int r, int half) {
+  return 8 * (r >> 2) + 4 * half + (r & 3);
+}
+// four floats as four bfloat16 (round to nearest even), packed
+__device__ __forceinline__ uint2 pack4(const float (&r)[4]) {
+  uint2 pk;
+  pk.x = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)r[0]) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)r[1]) << 16);
+  pk.y = (uint32_t)__builtin_bit_cast(uint16_t, (bf16)r[2]) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (bf16)r[3]) << 16);
+  return pk;
+}
+
 // --------------------------------------------------------------- kernels
 // x0 from a render: r, g, b, a, depth code, 0, 0, 0
 __global__ void prep_kernel(const float4* rgba, const float* depth, int64_t P, float inv_scale,
@@ -83,25 +102,28 @@ __global__ void prep_kernel(const float4* rgba, const float* depth, int64_t P, f
 // Epilogues of the convolution kernel.
 enum { kReluBf16 = 0, kBiasF32 = 1, kMaskBf16 = 2 };
 
-// y[p][co] = sum_{tap, ci} x[p + off(tap)][ci] * w[tap][ci][co] (+ epilogue),
-// zero padding, for N images of H x W. wt: packed [K / 8][32][8] bf16.
+// y[p][co] = bias[co] + sum_{tap, ci} x[p + off(tap)][ci] * w[tap][ci][co]
+// (the bias is the accumulator's starting value; the sum runs in K order),
+// then the epilogue; zero padding, for N images of H x W. wt: packed
+// [K / 8][32][8] bf16. A wave computes 64 pixels (two blocks of 32) x 32
+// channels as the transposed product: A = weights (32 channels x 16 K),
+// B = pixels (16 K x 32 pixels).
 template <int CIN, int EPI>
 __global__ __launch_bounds__(256) void conv_kernel(const bf16* __restrict__ x, int N, int H, int W,
                                                    const bf16x8* __restrict__ wt,
                                                    const float* __restrict__ bias,
                                                    void* __restrict__ out,
                                                    const bf16* __restrict__ mask) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
   const int64_t P = (int64_t)N * H * W;
   const int64_t p0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
   if (p0 >= P) return;  // whole wave
-  const int row = lane & 15, grp = lane >> 4;
-  // the lane's pixel in each of the four row blocks
-  int py[4], px[4], pn[4];
-  bool pv[4];
+  // the lane's pixel in each of the two blocks
+  int py[2], px[2], pn[2];
+  bool pv[2];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const int64_t p = p0 + mb * 16 + row;
+  for (int mb = 0; mb < 2; ++mb) {
+    const int64_t p = p0 + mb * 32 + col;
     pv[mb] = p < P;
     const int64_t q = pv[mb] ? p : 0;
     pn[mb] = (int)(q / ((int64_t)H * W));
@@ -109,57 +131,65 @@ __global__ __launch_bounds__(256) void conv_kernel(const bf16* __restrict__ x, i
     py[mb] = r / W;
     px[mb] = r - py[mb] * W;
   }
-  floatx4 acc[4][2];
+  // the bias is the accumulators' starting value (no bias: 0); register r
+  // holds channel acc_channel(r, half)
+  floatx16 acc[2];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  constexpr int KSTEPS = kdim(CIN) / 32;
+  for (int r = 0; r < 16; ++r) {
+    const float b = EPI == kMaskBf16 ? 0.f : bias[acc_channel(r, half)];
+    acc[0][r] = b;
+    acc[1][r] = b;
+  }
+  constexpr int KSTEPS = ksteps(CIN);
   const bf16x8 zero8 = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f,
                         (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
 #pragma unroll 1
   for (int s = 0; s < KSTEPS; ++s) {
-    const int k8 = s * 4 + grp;  // this lane's group of 8 K values
-    const int tap = CIN == 32 ? s : k8;
-    const int c0 = CIN == 32 ? grp * 8 : 0;
+    const int k8 = 2 * s + half;  // this lane's group of 8 K values
+    const int tap = CIN == 32 ? k8 >> 2 : k8;
+    const int c0 = CIN == 32 ? (k8 & 3) * 8 : 0;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    bf16x8 a[4];
+    bf16x8 a[2];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < 2; ++mb) {
       const int yy = py[mb] + dy, xx = px[mb] + dx;
       const bool in = pv[mb] && tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
       a[mb] = in ? *reinterpret_cast<const bf16x8*>(
                        x + (((int64_t)pn[mb] * H + yy) * W + xx) * CIN + c0)
                  : zero8;
     }
-    const bf16x8 b0 = wt[(int64_t)k8 * kCh + row];
-    const bf16x8 b1 = wt[(int64_t)k8 * kCh + 16 + row];
+    const bf16x8 w = wt[(int64_t)k8 * kCh + col];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b0, acc[mb][0], 0, 0, 0);
-      acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b1, acc[mb][1], 0, 0, 0);
+    for (int mb = 0; mb < 2; ++mb)
+      acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, a[mb], acc[mb], 0, 0, 0);
+  }
+  // lane: pixel p0 + 32 mb + col; channels acc_channel(4 g + i, half) =
+  // 8 g + 4 half + i, four consecutive per g
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    const int64_t p = p0 + mb * 32 + col;
+    if (p >= P) continue;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int c = 8 * g + 4 * half;
+      const float v0 = acc[mb][4 * g], v1 = acc[mb][4 * g + 1], v2 = acc[mb][4 * g + 2],
+                  v3 = acc[mb][4 * g + 3];
+      if (EPI == kBiasF32) {
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + p * kCh + c) =
+            make_float4(v0, v1, v2, v3);
+      } else {
+        float r[4] = {v0, v1, v2, v3};
+        if (EPI == kReluBf16) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) r[i] = fmaxf(r[i], 0.0f);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) r[i] = bf(mask[p * kCh + c + i]) > 0.0f ? r[i] : 0.0f;
+        }
+        *reinterpret_cast<uint2*>(reinterpret_cast<bf16*>(out) + p * kCh + c) = pack4(r);
+      }
     }
   }
-  // result (row 4 grp + i, column row) of each block
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t p = p0 + mb * 16 + grp * 4 + i;
-        if (p >= P) continue;
-        const int co = nb * 16 + row;
-        float vv = acc[mb][nb][i];
-        if (EPI == kReluBf16) {
-          vv = fmaxf(vv + bias[co], 0.0f);
-          reinterpret_cast<bf16*>(out)[p * kCh + co] = (bf16)vv;
-        } else if (EPI == kBiasF32) {
-          reinterpret_cast<float*>(out)[p * kCh + co] = vv + bias[co];
-        } else {
-          const bool on = bf(mask[p * kCh + co]) > 0.0f;
-          reinterpret_cast<bf16*>(out)[p * kCh + co] = (bf16)(on ? vv : 0.0f);
-        }
-      }
 }
 
 // Bilinear x2 (half-pixel centres, clamped) of x0's rgba at full-resolution
@@ -230,6 +260,286 @@ __global__ __launch_bounds__(256) void shuffle_kernel(const float* o, const bf16
     if (nf < N) atomicAdd(mse_sum + nf, r0[0]);
     if (nf + 1 < N) atomicAdd(mse_sum + nf + 1, r1[0]);
   }
+}
+
+// ------------------------------------------------ fused inference kernel
+// One workgroup per 16 x 16 tile of low-resolution pixels runs the whole
+// network: x0 on the tile plus a 4-pixel halo, h1 on a 3-pixel halo, h2 on
+// 2, h3 on 1, o on the tile, every activation in LDS (two buffers used in
+// turn: V holds x0, then h2, then o; U holds h1, then h3). Each layer is the
+// implicit GEMM of conv_kernel with the same operand layouts, K order,
+// epilogue arithmetic and zero padding (activations outside the image are
+// stored as 0), so the result equals the layer-by-layer path bit for bit.
+// A wave owns up to eight 16-pixel row blocks of a layer's region and keeps
+// their accumulators across the K loop, so each weight fragment is loaded
+// once per K-step and reused by all of them.
+// A hidden pixel's 32 bf16 channels occupy 80 bytes (64 + 16 of padding):
+// the 16 pixels of a 16-byte-per-lane read then start on 16 different
+// groups of four 4-byte banks (a 64-byte stride would put them on 4).
+constexpr int kTile = 16;
+constexpr int kE0 = kTile + 8;                               // x0 region edge
+constexpr int kPix = kCh + 8;                                // bf16 per hidden pixel (padded)
+constexpr int kBufU = (kE0 - 2) * (kE0 - 2) * kPix;          // bf16 elements (h1, h3)
+constexpr int kBufV = (kE0 - 4) * (kE0 - 4) * kPix;          // bf16 elements (x0, h2, o)
+constexpr int kE1 = kTile + 2;                               // x0 rgba ring edge
+constexpr size_t kFusedLds = (size_t)(kBufU + kBufV) * 2 + kE1 * kE1 * 16 + 256 * 8;
+static_assert(kE0 * kE0 * 8 <= kBufV, "x0 region fits buffer V");
+static_assert(kTile * kTile * kUsed * 2 <= kBufV, "o (FP32, used channels) fits buffer V");
+static_assert(kFusedLds <= 80 * 1024, "two workgroups per CU");
+
+// One layer on a region: input region edge EIN in `sin` (CIN channels per
+// pixel), output region edge EIN - 2 into `sout` (bf16 x 32 after bias and
+// ReLU, or FP32 x kUsed after bias when LAST). (oy0, ox0): image position
+// of the output region's first pixel. The product is taken transposed
+// (weights as the A operand, pixels as B): the same 32 products per output
+// value in the same K order, and each lane ends up holding 4 consecutive
+// channels of one pixel, stored with one 8- or 16-byte LDS write.
+// A layer's weight fragments for this lane, every K-step (the A operand).
+template <int CIN>
+__device__ __forceinline__ void load_weights(const bf16x8* __restrict__ wt,
+                                             bf16x8 (&wf)[ksteps(CIN)]) {
+  const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
+#pragma unroll
+  for (int s = 0; s < ksteps(CIN); ++s) wf[s] = wt[(int64_t)(2 * s + half) * kCh + col];
+}
+
+// NJ 32-pixel blocks of a layer's output region for this wave (blocks
+// wave, wave + 4, ...): input region edge EIN in `sin` (CIN channels per
+// pixel), output region edge EIN - 2 into `sout` (bf16 x 32 after ReLU, or
+// FP32 x kUsed when LAST). (oy0, ox0): image position of the output
+// region's first pixel. wf: this layer's weights; the next layer's (wn from
+// wnext, unless LAST) are loaded right after the products, so their latency
+// overlaps the epilogue and the barrier.
+template <int CIN, int EIN, int NJ, bool LAST>
+__device__ __forceinline__ void fused_blocks(const bf16* __restrict__ sin,
+                                             void* __restrict__ sout,
+                                             const bf16x8 (&wf)[ksteps(CIN)],
+                                             const bf16x8* __restrict__ wnext,
+                                             bf16x8 (&wn)[ksteps(32)],
+                                             const float* __restrict__ bias, int oy0, int ox0,
+                                             int H, int W) {
+  constexpr int EO = EIN - 2, MO = EO * EO;
+  constexpr int PB = CIN == 32 ? kPix * 2 : 16;  // bytes per input pixel
+  constexpr int KSTEPS = ksteps(CIN);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const bf16x8 zero8 = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f,
+                        (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+  // the bias is the accumulators' starting value (as in conv_kernel)
+  floatx16 acc[NJ];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float b = bias[acc_channel(r, half)];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j][r] = b;
+  }
+  // byte address of the top-left input pixel of the lane's 3 x 3 window
+  // (with 32 channels, plus the lane's 8-channel group within a tap's
+  // 16-K step); every tap is then a constant offset
+  const char* base[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int q = min((wave + 4 * j) * 32 + col, MO - 1);  // pixels past the region repeat
+    const int qy = q / EO, qx = q - qy * EO;
+    base[j] = reinterpret_cast<const char*>(sin) + (qy * EIN + qx) * PB +
+              (CIN == 32 ? half * 16 : 0);
+  }
+  // K-step s: lane K group k8 = 2 s + half. With 32 channels the tap is
+  // s / 2 for the whole wave and the channel group 2 (s % 2) + half; with
+  // 8 channels the tap is k8 (zero beyond the ninth).
+  auto load = [&](int s, bf16x8 (&a)[NJ]) {
+    if (CIN == 32) {
+      const int tap = s >> 1;
+      const int off = ((tap / 3) * EIN + (tap % 3)) * PB + (s & 1) * 32;  // constant
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) a[j] = *reinterpret_cast<const bf16x8*>(base[j] + off);
+    } else {
+      const int tap = 2 * s + half;
+      const int off = ((tap / 3) * EIN + (tap % 3)) * PB;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        a[j] = tap < 9 ? *reinterpret_cast<const bf16x8*>(base[j] + off) : zero8;
+    }
+  };
+  // the pixel fragments of step s + 1 are read while the products of step
+  // s run (two register sets); the scheduling groups keep that order
+  bf16x8 a[2][NJ];
+  load(0, a[0]);
+  __builtin_amdgcn_sched_group_barrier(0x0100, NJ, 0);  // step 0's reads first
+#pragma unroll
+  for (int s = 0; s < KSTEPS; ++s) {
+    if (s + 1 < KSTEPS) load(s + 1, a[(s + 1) & 1]);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[s], a[s & 1][j], acc[j], 0, 0, 0);
+    if (s + 1 < KSTEPS) __builtin_amdgcn_sched_group_barrier(0x0100, NJ, 0);  // LDS reads
+    __builtin_amdgcn_sched_group_barrier(0x0008, NJ, 0);                       // products
+  }
+  if (!LAST) load_weights<32>(wnext, wn);
+  __builtin_amdgcn_sched_barrier(0);
+  // lane: pixel (block) * 32 + col, channels 8 g + 4 half + i. A region
+  // inside the image (most tiles; uniform over the workgroup) needs no mask.
+  const bool interior = oy0 >= 0 && ox0 >= 0 && oy0 + EO <= H && ox0 + EO <= W;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int q = (wave + 4 * j) * 32 + col;
+    if (q >= MO) continue;
+    if (LAST) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int c = 8 * g + 4 * half;
+        if (c >= kUsed) continue;
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(sout) + q * kUsed + c) =
+            make_float4(acc[j][4 * g], acc[j][4 * g + 1], acc[j][4 * g + 2], acc[j][4 * g + 3]);
+      }
+    } else {
+      bool in = true;
+      if (!interior) {
+        const int qy = q / EO, qx = q - qy * EO;
+        const int iy = oy0 + qy, ix = ox0 + qx;
+        in = iy >= 0 && iy < H && ix >= 0 && ix < W;
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = in ? fmaxf(acc[j][4 * g + i], 0.0f) : 0.0f;
+        *reinterpret_cast<uint2*>(reinterpret_cast<bf16*>(sout) + q * kPix + 8 * g + 4 * half) =
+            pack4(r);
+      }
+    }
+  }
+}
+
+// One layer: a wave takes MAXJ blocks, or MAXJ - 1 when its last one would
+// lie past the region (a uniform branch between two branch-free bodies).
+template <int CIN, int EIN, int MAXJ, bool LAST>
+__device__ __forceinline__ void fused_layer(const bf16* __restrict__ sin, void* __restrict__ sout,
+                                            const bf16x8 (&wf)[ksteps(CIN)],
+                                            const bf16x8* __restrict__ wnext,
+                                            bf16x8 (&wn)[ksteps(32)],
+                                            const float* __restrict__ bias, int oy0, int ox0,
+                                            int H, int W) {
+  constexpr int NBLK = ((EIN - 2) * (EIN - 2) + 31) / 32;
+  static_assert(4 * (MAXJ - 1) + 3 >= NBLK - 1, "every block has a wave");
+  static_assert(MAXJ == 1 || 4 * (MAXJ - 2) + 3 < NBLK, "only a wave's last block may be idle");
+  const int wave = threadIdx.x >> 6;
+  if (wave + 4 * (MAXJ - 1) < NBLK)
+    fused_blocks<CIN, EIN, MAXJ, LAST>(sin, sout, wf, wnext, wn, bias, oy0, ox0, H, W);
+  else
+    fused_blocks<CIN, EIN, MAXJ - 1, LAST>(sin, sout, wf, wnext, wn, bias, oy0, ox0, H, W);
+}
+
+// LDS allows two workgroups per CU (two waves per SIMD): the register
+// budget is set for that, so a K-step's reads can all be in flight.
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
+fused_forward_kernel(
+    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
+    float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
+    const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
+    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
+    float4* __restrict__ out, float* __restrict__ err, double* __restrict__ mse_sum) {
+  // LDS (kFusedLds bytes): U, V, then x0's rgba (bf16-rounded) on the tile
+  // and a 1-pixel ring for the bilinear base of the last phase, then the
+  // reduction scratch
+  extern __shared__ float4 fused_smem[];
+  bf16* sU = reinterpret_cast<bf16*>(fused_smem);
+  bf16* sV = sU + kBufU;
+  float4* sX = reinterpret_cast<float4*>(sV + kBufV);
+  double* red = reinterpret_cast<double*>(sX + kE1 * kE1);
+  const int n = blockIdx.z;
+  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+  bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
+  load_weights<8>(w0, wa);
+  // x0 on the tile and a 4-pixel halo (zero outside the image): every load
+  // is issued before any is used
+  constexpr int kPrep = (kE0 * kE0 + 255) / 256;
+  float4 pc[kPrep];
+  float pd[kPrep];
+#pragma unroll
+  for (int k = 0; k < kPrep; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
+    pc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pd[k] = INFINITY;
+    if (p < kE0 * kE0 && y >= 0 && y < H && x >= 0 && x < W) {
+      const int64_t q = ((int64_t)n * H + y) * W + x;
+      pc[k] = rgba[q];
+      pd[k] = depth[q];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPrep; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    if (p >= kE0 * kE0) continue;
+    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
+    bf16x8 v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = (bf16)0.0f;
+    if (y >= 0 && y < H && x >= 0 && x < W) {
+      const float4 c = pc[k];
+      const float d = pd[k];
+      const float code = isfinite(d) ? 1.0f / (1.0f + d * inv_scale) : 0.0f;
+      v[0] = (bf16)c.x;
+      v[1] = (bf16)c.y;
+      v[2] = (bf16)c.z;
+      v[3] = (bf16)c.w;
+      v[4] = (bf16)code;
+    }
+    reinterpret_cast<bf16x8*>(sV)[p] = v;
+    const int ry = p / kE0 - 3, rx = p % kE0 - 3;
+    if (ry >= 0 && ry < kE1 && rx >= 0 && rx < kE1)
+      sX[ry * kE1 + rx] = make_float4(bf(v[0]), bf(v[1]), bf(v[2]), bf(v[3]));
+  }
+  __syncthreads();
+  fused_layer<8, kE0, 4, false>(sV, sU, wa, w1, wb, b0, ty0 - 3, tx0 - 3, H, W);
+  __syncthreads();
+  fused_layer<32, kE0 - 2, 4, false>(sU, sV, wb, w2, wc, b1, ty0 - 2, tx0 - 2, H, W);
+  __syncthreads();
+  fused_layer<32, kE0 - 4, 3, false>(sV, sU, wc, w3, wb, b2, ty0 - 1, tx0 - 1, H, W);
+  __syncthreads();
+  fused_layer<32, kE0 - 6, 2, true>(sU, sV, wb, nullptr, wc, b3, ty0, tx0, H, W);
+  __syncthreads();
+  // pixel shuffle, bilinear residual and error head, one thread per pixel
+  const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
+  const int y = ty0 + qy, x = tx0 + qx;
+  float zsum = 0.f;
+  if (y < H && x < W) {
+    const float* op = reinterpret_cast<const float*>(sV) + threadIdx.x * kUsed;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int sy = s >> 1, sx = s & 1;
+      const int ya = sy ? y : y - 1, xa = sx ? x : x - 1;
+      const float fy = sy ? 0.25f : 0.75f, fx = sx ? 0.25f : 0.75f;
+      // neighbours clamped into the image, which keeps them in the ring
+      const int r0 = min(max(ya, 0), H - 1) - (ty0 - 1), r1 = min(max(ya + 1, 0), H - 1) - (ty0 - 1);
+      const int c0 = min(max(xa, 0), W - 1) - (tx0 - 1), c1 = min(max(xa + 1, 0), W - 1) - (tx0 - 1);
+      const float4 A = sX[r0 * kE1 + c0], B = sX[r0 * kE1 + c1], Cc = sX[r1 * kE1 + c0],
+                   D = sX[r1 * kE1 + c1];
+      const float av[4] = {A.x, A.y, A.z, A.w}, bvv[4] = {B.x, B.y, B.z, B.w},
+                  cv[4] = {Cc.x, Cc.y, Cc.z, Cc.w}, dv[4] = {D.x, D.y, D.z, D.w};
+      float o[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float top = av[c] + (bvv[c] - av[c]) * fx, bot = cv[c] + (dv[c] - cv[c]) * fx;
+        o[c] = top + (bot - top) * fy;
+      }
+      const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
+      out[q] = make_float4(o[0] + op[5 * s], o[1] + op[5 * s + 1], o[2] + op[5 * s + 2],
+                           o[3] + op[5 * s + 3]);
+      const float z = op[5 * s + 4];
+      if (err) err[q] = z * z;
+      zsum += z * z;
+    }
+  }
+  if (!mse_sum) return;
+  red[threadIdx.x] = (double)zsum;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(mse_sum + n, red[0]);
 }
 
 // Training loss and its gradient with respect to o (bf16, 32 channels,
@@ -358,6 +668,26 @@ __global__ void reduce_kernel(const float* part, int blocks, int64_t n, float* g
   }
 }
 
+// x[0 .. n) = 0 (a kernel rather than a memset: safe inside captured graphs)
+__global__ void zero_kernel(double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// The fallback decision on the device: the frame's predicted mean squared
+// error is the mean over its n images of sum_i / pixels; fallback = 1 when
+// the predicted PSNR (peak 1) is below threshold_db.
+__global__ void fallback_kernel(const double* sums, int n, double pixels, double threshold_db,
+                                int32_t* fallback) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m += sums[i] / pixels;
+  m /= (double)n;
+  const double psnr = m <= 0.0 ? INFINITY : 10.0 * log10(1.0 / m);
+  *fallback = psnr < threshold_db ? 1 : 0;
+}
+
 // Adam on the FP32 master weights.
 __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
                             float c1, float c2) {
@@ -418,6 +748,7 @@ struct sg_upsampler {
   double* acc = nullptr;    // device doubles: loss, per-image sums
   int64_t acc_n = 0;
   bool packed = false;
+  bool fused = true;        // inference through fused_forward_kernel
 };
 
 namespace {
@@ -529,6 +860,50 @@ sg_status gradients(sg_upsampler* u, int n, int h, int w, const float* rgba, con
   return wgrad<8>(u, u->x0, g, n, h, w, 0, s);
 }
 
+// Inference into out_rgba / out_err; with sums, the per-image sums of the
+// predicted squared error are left in acc[1 .. n].
+sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
+                const float* depth, double depth_scale, float* out_rgba, float* out_err,
+                bool sums, hipStream_t s) {
+  sg_status st = check_batch(up, n, h, w, rgba, depth);
+  if (st != SG_OK) return st;
+  if (!out_rgba || !(std::isfinite(depth_scale) && depth_scale > 0.0))
+    return fail(SG_ERR_INVALID_ARG, "sg_up_forward: NULL output or bad depth_scale");
+  DeviceGuard guard(up->device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  if (sums) {
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_of(n)), dim3(256), 0, s, up->acc + 1,
+                       (int64_t)n);
+    SG_HIP(hipGetLastError());
+  }
+  double* sum = sums ? up->acc + 1 : nullptr;
+  if (up->fused && n <= 65535) {
+    if (!up->packed && (st = pack_weights(up, s)) != SG_OK) return st;
+    const float* b = up->params;
+    const dim3 grid((unsigned)((w + kTile - 1) / kTile), (unsigned)((h + kTile - 1) / kTile),
+                    (unsigned)n);
+    SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fused_forward_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds));
+    hipLaunchKernelGGL(fused_forward_kernel, grid, dim3(256), kFusedLds, s,
+                       reinterpret_cast<const float4*>(rgba), depth, n, h, w,
+                       (float)(1.0 / depth_scale), reinterpret_cast<const bf16x8*>(up->fw[0]),
+                       reinterpret_cast<const bf16x8*>(up->fw[1]),
+                       reinterpret_cast<const bf16x8*>(up->fw[2]),
+                       reinterpret_cast<const bf16x8*>(up->fw[3]), b + layer_off(0) + 9 * 8 * kCh,
+                       b + layer_off(1) + 9 * 32 * kCh, b + layer_off(2) + 9 * 32 * kCh,
+                       b + layer_off(3) + 9 * 32 * kCh, reinterpret_cast<float4*>(out_rgba),
+                       out_err, sum);
+    SG_HIP(hipGetLastError());
+  } else {
+    if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
+    const int64_t P = (int64_t)n * h * w;
+    hipLaunchKernelGGL(shuffle_kernel, dim3(blocks_of(P)), dim3(256), 0, s, up->o, up->x0, n, h,
+                       w, reinterpret_cast<float4*>(out_rgba), out_err, sum);
+    SG_HIP(hipGetLastError());
+  }
+  return SG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,24 +989,32 @@ sg_status sg_up_get_weights(sg_upsampler* up, float* params, int64_t n) {
 sg_status sg_up_forward(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
                         const float* depth, double depth_scale, float* out_rgba, float* out_err,
                         double* mse_pred, void* hip_stream) {
-  sg_status st = check_batch(up, n, h, w, rgba, depth);
-  if (st != SG_OK) return st;
-  if (!out_rgba || !(std::isfinite(depth_scale) && depth_scale > 0.0))
-    return fail(SG_ERR_INVALID_ARG, "sg_up_forward: NULL output or bad depth_scale");
-  DeviceGuard guard(up->device);
-  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
   hipStream_t s = (hipStream_t)hip_stream;
-  if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
-  if (mse_pred) SG_HIP(hipMemsetAsync(up->acc + 1, 0, sizeof(double) * n, s));
-  const int64_t P = (int64_t)n * h * w;
-  hipLaunchKernelGGL(shuffle_kernel, dim3(blocks_of(P)), dim3(256), 0, s, up->o, up->x0, n, h, w,
-                     reinterpret_cast<float4*>(out_rgba), out_err, mse_pred ? up->acc + 1 : nullptr);
-  SG_HIP(hipGetLastError());
+  sg_status st = infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err,
+                       mse_pred != nullptr, s);
+  if (st != SG_OK) return st;
   if (mse_pred) {
+    DeviceGuard guard(up->device);
     SG_HIP(hipMemcpyAsync(mse_pred, up->acc + 1, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     SG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < n; ++i) mse_pred[i] /= 4.0 * (double)h * w;
   }
+  return SG_OK;
+}
+
+sg_status sg_up_forward_flag(sg_upsampler* up, int32_t n, int32_t h, int32_t w,
+                             const float* rgba, const float* depth, double depth_scale,
+                             float* out_rgba, float* out_err, double threshold_db,
+                             int32_t* fallback, void* hip_stream) {
+  if (!fallback || std::isnan(threshold_db))
+    return fail(SG_ERR_INVALID_ARG, "sg_up_forward_flag: NULL flag or NaN threshold");
+  hipStream_t s = (hipStream_t)hip_stream;
+  sg_status st = infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err, true, s);
+  if (st != SG_OK) return st;
+  DeviceGuard guard(up->device);
+  hipLaunchKernelGGL(fallback_kernel, dim3(1), dim3(64), 0, s, up->acc + 1, n,
+                     4.0 * (double)h * w, threshold_db, fallback);
+  SG_HIP(hipGetLastError());
   return SG_OK;
 }
 
@@ -669,6 +1052,12 @@ sg_status sg_up_train_step(sg_upsampler* up, int32_t n, int32_t h, int32_t w, co
                      up->grads, up->m, up->v, kParams, (float)lr, c1, c2);
   SG_HIP(hipGetLastError());
   return pack_weights(up, s);
+}
+
+sg_status sg_up_set_fused(sg_upsampler* up, int32_t fused) {
+  if (!up) return fail(SG_ERR_INVALID_ARG, "sg_up_set_fused: NULL upsampler");
+  up->fused = fused != 0;
+  return SG_OK;
 }
 
 sg_status sg_up_read_buffer(sg_upsampler* up, int32_t which, void* host, int64_t bytes) {

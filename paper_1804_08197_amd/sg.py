@@ -110,6 +110,8 @@ _lib.sg_render_graph_launch.argtypes = [_P, _P]
 _lib.sg_render_graph_destroy.argtypes = [_P]
 _lib.sg_cache_put.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                               C.POINTER(C.c_int32), _P, C.c_int32, _P]
+_lib.sg_render_views_if.argtypes = [_P, C.c_int32, C.POINTER(sg_view), C.POINTER(sg_render_params),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _P, _P]
 _lib.sg_cache_put_scattered.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_void_p), _P]
 _lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32),
@@ -128,7 +130,7 @@ for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_buil
            "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
            "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy",
            "sg_cache_put", "sg_cache_put_scattered", "sg_cache_requests", "sg_cache_get_info",
-           "sg_cache_resident"):
+           "sg_cache_resident", "sg_render_views_if"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -295,6 +297,23 @@ def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
         dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
     _check(_lib.sg_render_views(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
            "sg_render_views")
+
+
+def sg_render_views_if(vol, views, params, out_rgba, enable, out_depth=None, stream=None):
+    """sg_render_views carried out only if the device int32 `enable` (a
+    one-element tensor) is nonzero when the render runs."""
+    n = len(views)
+    varr = _views(views)
+    p = make_params(params)
+    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+    dep = None
+    if out_depth is not None:
+        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    if enable is None:
+        raise ValueError("sg_render_views_if needs a device flag")
+    _check(_lib.sg_render_views_if(vol, n, varr, C.byref(p), rgba, dep,
+                                   C.c_void_p(enable.data_ptr()), _stream(stream)),
+           "sg_render_views_if")
 
 
 def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samples=None,

@@ -26,6 +26,18 @@ from . import upsampler as up
 DEPTH_ALPHA = 0.5
 
 
+def render_params(base_params, lod):
+    """(full-resolution, half-resolution) render parameters. Without LOD the
+    target samples level 0 and the input level 1 everywhere; with the
+    screen-space LOD both use it, and the half-resolution render, whose
+    pixels span twice the angle, lands one level coarser on its own."""
+    if lod:
+        return (dict(base_params, lod=1, bias=0),
+                dict(base_params, lod=1, bias=0, depth_alpha=DEPTH_ALPHA))
+    return (dict(base_params, lod=0, bias=0),
+            dict(base_params, lod=0, bias=1, depth_alpha=DEPTH_ALPHA))
+
+
 def crop_view(view, x0, y0, w, h, scale=1):
     """The view restricted to full-resolution pixels [x0, x0+w) x [y0, y0+h)
     of `view`, rendered at w / scale x h / scale pixels."""
@@ -46,12 +58,11 @@ class Trainer:
     """Trains an upsampler on pairs rendered from a volume with >= 2 levels."""
 
     def __init__(self, vol, model: "up.Upsampler", depth_scale: float, base_params: dict,
-                 crop=256, batch=16):
+                 crop=256, batch=16, lod=False):
         import torch
         self.vol, self.model = vol, model
         self.depth_scale = float(depth_scale)
-        self.p_full = dict(base_params, lod=0, bias=0)
-        self.p_half = dict(base_params, lod=0, bias=1, depth_alpha=DEPTH_ALPHA)
+        self.p_full, self.p_half = render_params(base_params, lod)
         self.crop, self.batch = int(crop), int(batch)
         c2 = self.crop // 2
         self.rgba_lo = torch.empty(batch, c2, c2, 4, device="cuda")
@@ -81,12 +92,12 @@ class UpsampledPath:
     """Frames through the upsampler, with the full-resolution fallback."""
 
     def __init__(self, vol, model: "up.Upsampler", depth_scale: float, base_params: dict,
-                 width: int, height: int, n_views: int = 2, threshold_db: float = 40.0):
+                 width: int, height: int, n_views: int = 2, threshold_db: float = 40.0,
+                 lod=False):
         import torch
         self.vol, self.model = vol, model
         self.depth_scale = float(depth_scale)
-        self.p_full = dict(base_params, lod=0, bias=0)
-        self.p_half = dict(base_params, lod=0, bias=1, depth_alpha=DEPTH_ALPHA)
+        self.p_full, self.p_half = render_params(base_params, lod)
         self.threshold_db = float(threshold_db)
         w2, h2 = width // 2, height // 2
         self.rgba_lo = torch.empty(n_views, h2, w2, 4, device="cuda")
@@ -110,6 +121,17 @@ class UpsampledPath:
         if fell_back:
             sg.sg_render_views(self.vol, views, self.p_full, list(self.out))
         return self.out, fell_back
+
+    def render_device(self, views, flag):
+        """The same frame with the decision taken on the device, without a
+        host round trip: flag (one-element int32 device tensor) receives 1
+        when the frame fell back. Asynchronous; returns the images."""
+        sg.sg_render_views(self.vol, [half_view(v) for v in views], self.p_half,
+                           list(self.rgba_lo), list(self.depth_lo))
+        self.model.forward_flag(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
+                                self.threshold_db, flag)
+        sg.sg_render_views_if(self.vol, views, self.p_full, list(self.out), flag)
+        return self.out
 
 
 def init_params(rng, scale=0.5):

@@ -25,8 +25,12 @@ _lib.sg_up_gradients.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.
 _lib.sg_up_train_step.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P,
                                   C.c_double, C.c_double, C.POINTER(C.c_double), _P]
 _lib.sg_up_read_buffer.argtypes = [_P, C.c_int32, _P, C.c_int64]
+_lib.sg_up_set_fused.argtypes = [_P, C.c_int32]
+_lib.sg_up_forward_flag.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P,
+                                    _P, C.c_double, _P, _P]
 for _f in ("sg_up_create", "sg_up_destroy", "sg_up_set_weights", "sg_up_get_weights",
-           "sg_up_forward", "sg_up_gradients", "sg_up_train_step", "sg_up_read_buffer"):
+           "sg_up_forward", "sg_up_gradients", "sg_up_train_step", "sg_up_read_buffer",
+           "sg_up_set_fused", "sg_up_forward_flag"):
     getattr(_lib, _f).restype = C.c_int
 
 LAYERS = ((8, 32), (32, 32), (32, 32), (32, 32))
@@ -72,6 +76,10 @@ class Upsampler:
         sg._check(_lib.sg_up_set_weights(self.h, v.ctypes.data_as(C.POINTER(C.c_float)), len(v)),
                   "sg_up_set_weights")
 
+    def set_fused(self, fused: bool):
+        """Inference in one fused kernel (default) or layer by layer."""
+        sg._check(_lib.sg_up_set_fused(self.h, int(bool(fused))), "sg_up_set_fused")
+
     def get_weights(self) -> np.ndarray:
         v = np.zeros(param_count(), np.float32)
         sg._check(_lib.sg_up_get_weights(self.h, v.ctypes.data_as(C.POINTER(C.c_float)), len(v)),
@@ -86,6 +94,17 @@ class Upsampler:
                                      _dp(out_rgba), _dp(out_err), mse, sg._stream(stream)),
                   "sg_up_forward")
         return np.array(mse[:]) if predict else None
+
+    def forward_flag(self, rgba, depth, depth_scale, out_rgba, threshold_db, fallback,
+                     out_err=None, stream=None):
+        """Inference and the fallback decision on the device: fallback (a
+        one-element int32 device tensor) = 1 when the predicted PSNR of the
+        batch is below threshold_db. Asynchronous."""
+        n, h, w = rgba.shape[:3]
+        sg._check(_lib.sg_up_forward_flag(self.h, n, h, w, _dp(rgba), _dp(depth),
+                                          float(depth_scale), _dp(out_rgba), _dp(out_err),
+                                          float(threshold_db), _dp(fallback),
+                                          sg._stream(stream)), "sg_up_forward_flag")
 
     def gradients(self, rgba, depth, depth_scale, target, err_weight=1.0, stream=None):
         n, h, w = rgba.shape[:3]

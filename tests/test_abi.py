@@ -125,6 +125,14 @@ def test_null_arguments_are_invalid(sg):
         sg.SG_ERR_INVALID_ARG
     assert lib.sg_get_lod_cut(None, None, None, None, None, None, None) == sg.SG_ERR_INVALID_ARG
     assert lib.sg_volume_memory(None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_render_views_if(None, 1, None, None, None, None, None, None) == \
+        sg.SG_ERR_INVALID_ARG
+    assert lib.sg_cache_put_scattered(None, 0, 0, 0, 1, None, None, None) == \
+        sg.SG_ERR_INVALID_ARG
+    from paper_1804_08197_amd import upsampler as up
+    assert up._lib.sg_up_forward_flag(None, 1, 1, 1, None, None, 1.0, None, None, 40.0, None,
+                                      None) == sg.SG_ERR_INVALID_ARG
+    assert up._lib.sg_up_set_fused(None, 1) == sg.SG_ERR_INVALID_ARG
 
 
 def test_valid_description_without_gpu_reports_device_error(sg):

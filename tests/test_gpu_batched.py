@@ -201,3 +201,34 @@ def test_bad_launch_configs_are_rejected(blobs):
             sg.sg_set_launch_config(h, bad)
         assert ex.value.status == sg.SG_ERR_INVALID_ARG
     assert sg.sg_get_launch_config(h) == sg.DEFAULT_LAUNCH
+
+
+@pytest.mark.parametrize("launch", [None, (1, 8, 32, 8192, 0), (0, 16, 64, 8192, 1)])
+def test_render_if_follows_the_device_flag(blobs, launch):
+    """sg_render_views_if: a nonzero device flag renders exactly what
+    sg_render_views renders; a zero flag leaves the outputs untouched."""
+    import torch
+
+    from paper_1804_08197_amd import sg
+    h, _, _ = blobs
+    try:
+        if launch is not None:
+            sg.sg_set_launch_config(h, dict(zip(sg.LAUNCH_FIELDS, launch)))
+        vs = uneven_views(1010, 4)
+        p = {"ert": ERT, "tau": 1.0}
+        ref = render(h, vs, p)
+        for on in (1, 0, 1):
+            flag = torch.tensor([on], dtype=torch.int32, device="cuda")
+            outs = [torch.full((v["height"], v["width"], 4), float("nan"), device="cuda")
+                    for v in vs]
+            sg.sg_render_views_if(h, vs, p, outs, flag)
+            torch.cuda.synchronize()
+            for o, r in zip(outs, ref):
+                if on:
+                    assert torch.equal(o, r)
+                else:
+                    assert torch.isnan(o).all()
+        with pytest.raises(ValueError):
+            sg.sg_render_views_if(h, vs, p, ref, None)
+    finally:
+        sg.sg_set_launch_config(h, None)

@@ -73,6 +73,7 @@ def test_forward_layers_match_reference():
     u = up.Upsampler(N * H * W)
     try:
         u.set_weights(up.pack(params))
+        u.set_fused(False)  # layer by layer: the activations stay readable
         out = torch.full((N, 2 * H, 2 * W, 4), float("nan"), device="cuda")
         err = torch.full((N, 2 * H, 2 * W), float("nan"), device="cuda")
         mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True)
@@ -100,6 +101,43 @@ def test_forward_layers_match_reference():
         assert np.allclose(err.cpu().numpy(), sh[..., 4] ** 2, rtol=1e-5, atol=1e-7)
         assert np.allclose(mse, (sh[..., 4] ** 2).reshape(N, -1).mean(axis=1), rtol=1e-5)
         assert P == 874
+    finally:
+        u.close()
+
+
+@pytest.mark.parametrize("shape", [(2, 19, 23), (3, 45, 70), (1, 1, 1), (1, 16, 16),
+                                   (1, 33, 17)])
+def test_fused_inference_equals_the_layered_path(shape):
+    """The fused tile kernel must give the layer-by-layer output bit for bit
+    (same MFMA products in the same order, same epilogues, zero padding) on
+    ragged sizes spanning several 16 x 16 tiles; the predicted per-image
+    errors agree to double rounding."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    n, h, w = shape
+    rng = np.random.default_rng(20 + h * w)
+    params = bf16_params(rng, 0.5)
+    rgba = rng.uniform(0, 1, size=(n, h, w, 4)).astype(np.float32)
+    rgba[..., :3] *= rgba[..., 3:4]
+    depth = rng.uniform(0, 300, size=(n, h, w)).astype(np.float32)
+    depth[rng.uniform(size=depth.shape) < 0.2] = np.inf
+    trgba, tdepth = torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+    u = up.Upsampler(n * h * w)
+    try:
+        u.set_weights(up.pack(params))
+        res = []
+        for fused in (False, True):
+            u.set_fused(fused)
+            out = torch.full((n, 2 * h, 2 * w, 4), float("nan"), device="cuda")
+            err = torch.full((n, 2 * h, 2 * w), float("nan"), device="cuda")
+            mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True)
+            res.append((out.cpu().numpy(), err.cpu().numpy(), mse))
+        (o0, e0, m0), (o1, e1, m1) = res
+        assert np.isfinite(o1).all() and np.isfinite(e1).all()
+        assert np.array_equal(o0, o1) and np.array_equal(e0, e1)
+        assert np.allclose(m0, m1, rtol=1e-12, atol=0)
+        log("%s: fused == layered, mse %s" % (shape, m1))
     finally:
         u.close()
 
@@ -204,3 +242,73 @@ def test_bad_arguments():
             u.forward(x[:, :5], d[:, :5], -1.0, o)
     finally:
         u.close()
+
+
+def test_device_fallback_flag_matches_the_host_decision():
+    """sg_up_forward_flag: the same image as sg_up_forward and a flag equal
+    to the host-side decision (predicted PSNR below the threshold) for
+    thresholds on both sides of the prediction."""
+    import math
+
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(15)
+    params = bf16_params(rng)
+    _, _, trgba, tdepth = inputs(rng)
+    u = up.Upsampler(N * H * W)
+    try:
+        u.set_weights(up.pack(params))
+        ref = torch.empty(N, 2 * H, 2 * W, 4, device="cuda")
+        mse = u.forward(trgba, tdepth, SCALE, ref, predict=True)
+        pred = 10 * math.log10(1.0 / float(np.mean(mse)))
+        flag = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        for thr in (pred - 1.0, pred + 1.0, -math.inf, math.inf):
+            out = torch.full_like(ref, float("nan"))
+            u.forward_flag(trgba, tdepth, SCALE, out, thr, flag)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            assert int(flag.item()) == int(pred < thr), (thr, pred)
+    finally:
+        u.close()
+
+
+@pytest.mark.parametrize("lod", [False, True])
+def test_device_decided_path_equals_the_host_decided_path(lod):
+    """UpsampledPath.render_device (decision on the device, conditional
+    full-resolution render) gives the frame UpsampledPath.render gives:
+    the upsampled image when the prediction passes, the plain render when
+    it does not."""
+    import math
+
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg
+    from paper_1804_08197_amd import upsample as U
+    from paper_1804_08197_amd import upsampler as up
+    from tests.helpers import gpu_volume
+    vol = gen.random_volume((48, 40, 56), 31, dtype=np.uint8)
+    h = gpu_volume([vol], 16, 3, [gen.tf_identity()], [(0, 255)])
+    W2, H2 = 70, 46
+    vs = gen.stereo(np.array([150.0, -90.0, 80.0]), np.array([28.0, 20.0, 24.0]), 4.0, W2, H2,
+                    0.5, 0.5 * W2 / H2)
+    u = up.Upsampler(2 * (H2 // 2) * (W2 // 2))
+    try:
+        u.set_weights(up.pack(bf16_params(np.random.default_rng(16))))
+        path = U.UpsampledPath(h, u, 100.0, {"ert": 0.99, "skip_empty": 1}, W2, H2, 2, lod=lod)
+        pred = path.predicted_psnr(vs)
+        flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for thr in (pred - 1.0, pred + 1.0):
+            path.threshold_db = thr
+            want, fell = path.render(vs)
+            want = want.clone()
+            path.out.fill_(float("nan"))
+            got = path.render_device(vs, flag)
+            torch.cuda.synchronize()
+            assert bool(flag.item()) == fell == (pred < thr)
+            assert torch.equal(got, want), thr
+        assert math.isfinite(pred)
+    finally:
+        u.close()
+        sg.sg_volume_destroy(h)
