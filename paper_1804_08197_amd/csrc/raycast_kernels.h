@@ -59,7 +59,7 @@ namespace {
 // polynomial below 1/16 (avoids the cancellation of 1 - exp(-x); truncation
 // error below x^5/120 < 1e-8), the exponential above.
 __device__ __forceinline__ float one_minus_exp_neg(float x) {
-  float p = x * (1.0f - x * (0.5f - x * (0.16666667f - x * 0.041666668f)));
+  const float p = x * fmaf(-x, fmaf(-x, fmaf(-x, 0.041666668f, 0.16666667f), 0.5f), 1.0f);
   float q = 1.0f - __expf(-x);
   return x < 0.0625f ? p : q;
 }
@@ -112,6 +112,21 @@ __device__ __forceinline__ float trilinear(P p0, int sy, int sz, float fx, float
   return lerpf(c0, c1, fz);
 }
 
+// The same trilinear value from a byte address with row and plane steps in
+// bytes (saves the index scaling in the sample loop).
+template <typename T>
+__device__ __forceinline__ float trilinear_bytes(const char* p0, int syb, int szb, float fx,
+                                                 float fy, float fz) {
+  auto at = [&](int off) { return (float)*reinterpret_cast<const T*>(p0 + off); };
+  const float c00 = lerpf(at(0), at(sizeof(T)), fx);
+  const float c10 = lerpf(at(syb), at(syb + sizeof(T)), fx);
+  const float c01 = lerpf(at(szb), at(szb + sizeof(T)), fx);
+  const float c11 = lerpf(at(szb + syb), at(szb + syb + sizeof(T)), fx);
+  const float c0 = lerpf(c00, c10, fy);
+  const float c1 = lerpf(c01, c11, fy);
+  return lerpf(c0, c1, fz);
+}
+
 // ----------------------------------------------------------------- per ray
 struct Ray {
   double e[3], d[3];
@@ -129,6 +144,10 @@ struct Ray {
   int n, k;
   // accumulation
   float Cr, Cg, Cb, A, depth;
+  // depth: the smallest ray parameter in the current segment whose alpha
+  // reached dalpha (+inf: none yet, or no depth wanted), converted to the
+  // depth once, when the segment ends
+  float dtau, dalpha;
   float vmax[kMaxChannels];  // maximum intensity: running maxima
   bool sampled;              // maximum intensity: at least one sample taken
   int nsamp;
@@ -161,6 +180,8 @@ __device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const Vie
   for (int c = 0; c < kMaxChannels; ++c) r.vmax[c] = -INFINITY;
   r.sampled = false;
   r.depth = INFINITY;
+  r.dtau = INFINITY;
+  r.dalpha = V.depth ? a.depth_alpha : INFINITY;
   r.nsamp = 0;
   r.n = r.k = 0;
   const double lo[3] = {0.0, 0.0, 0.0};
@@ -222,12 +243,21 @@ __device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const Vie
   }
 }
 
+// The depth of the first sample found in the current segment: t0 + tau in
+// FP64, rounded once (the same operations as when formed at the sample);
+// later segments cannot replace it.
+__device__ __forceinline__ void finish_depth(Ray& r) {
+  if (r.depth == INFINITY && r.dtau != INFINITY) r.depth = (float)(r.t0 + (double)r.dtau);
+  r.dtau = INFINITY;
+}
+
 // Advance the ray to its next segment that needs samples: a cut node whose
 // parameter interval is non-empty and that is not skipped as empty. With
 // `first` the current DDA cell is examined before stepping.
 template <int MODEL, int CH>
 __device__ __forceinline__ void next_segment(Ray& r, const RenderArgs& a, const ViewDev& V,
                                              bool first) {
+  finish_depth(r);  // before t0 moves on
   const int32_t* cutmap = a.cutmap + V.cut_off;
   const double Bd = (double)a.B;
   bool step = !first;
@@ -341,9 +371,9 @@ __device__ __forceinline__ float sample_tau(const Ray& r, int k) {
 __device__ __forceinline__ float4 tf_lookup(const RenderArgs& a, const float4* s_tf, int ch,
                                             float val) {
   float u = fmaf(val, a.tf_scale[ch], a.tf_bias[ch]);
-  u = fminf(fmaxf(u, 0.0f), (float)(a.tf_n - 1));
+  u = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(a.tf_n - 1));  // clamp (u is finite)
   const int k0 = (int)u;
-  const float wt = u - (float)k0;
+  const float wt = __builtin_amdgcn_fractf(u);  // = u - k0 exactly, u >= 0
   const float4 t0v = s_tf[ch * (a.tf_n + 1) + k0];
   const float4 t1v = s_tf[ch * (a.tf_n + 1) + k0 + 1];
   return make_float4(lerpf(t0v.x, t1v.x, wt), lerpf(t0v.y, t1v.y, wt),
@@ -388,7 +418,7 @@ __device__ __forceinline__ void mark_microblocks(const Ray& r, const RenderArgs&
 // the ray has terminated (emission-absorption only).
 template <int MODEL, int CH, bool STATS, bool CLAMP = true, typename F>
 __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
-                                            bool want_depth, F&& fetch, int (*mb_key)[3]) {
+                                            F&& fetch, int (*mb_key)[3]) {
   const int k = r.k;
   const bool last = k == r.n - 1;
   const float s = last ? r.s_last : r.Df;
@@ -457,8 +487,10 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   r.Cg = fmaf(wgt, eg, r.Cg);
   r.Cb = fmaf(wgt, eb, r.Cb);
   r.A += wgt;
-  if (want_depth && r.depth == INFINITY && r.A >= a.depth_alpha)
-    r.depth = (float)(r.t0 + (double)tau);
+  // depth: tau rises along the segment, so the first sample whose alpha
+  // reached dalpha has the smallest tau (the depth itself, t0 + tau in FP64,
+  // is formed once per segment by finish_depth)
+  r.dtau = fminf(r.dtau, r.A >= r.dalpha ? tau : INFINITY);
   if (r.A >= a.ert) {
     r.alive = false;
     return false;
@@ -482,6 +514,7 @@ __device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T
 template <int MODEL, int CH>
 __device__ __forceinline__ void write_pixel(Ray& r, const RenderArgs& a, const ViewDev& V,
                                             const float4* s_tf, int px, int py) {
+  finish_depth(r);
   if (MODEL == kModelMip && r.sampled) {
     // the summed emission of the channel maxima
 #pragma unroll
@@ -595,7 +628,6 @@ template <typename T, int CH, bool STATS, int MODEL>
 __device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* s_tf,
                                              const TileLane& tl) {
   const ViewDev& V = a.views[tl.view];
-  const bool want_depth = V.depth != nullptr;
   int mb_key[CH][3];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
@@ -611,7 +643,7 @@ __device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* 
       return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
     };
     bool go = true;
-    while (go && r.k < r.n) go = sample_once<MODEL, CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key);
+    while (go && r.k < r.n) go = sample_once<MODEL, CH, STATS>(r, a, s_tf, fetch, mb_key);
     if (!go) break;
     next_segment<MODEL, CH>(r, a, V, false);
   }
@@ -709,6 +741,12 @@ __device__ __forceinline__ uint32_t wave_min_u16x2(uint32_t v) {
   });
 }
 
+// floor(x / d) for 0 <= x < 2^21, 1 <= d, from a reciprocal: within one of
+// the exact quotient (used only where any nearby value serves).
+__device__ __forceinline__ int quot(int x, int d) {
+  return (int)(((float)x + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 // Main-axis stencil layer of sample k (same arithmetic as the sample).
 __device__ __forceinline__ int sample_layer(const Ray& r, int k, float dqm, float qm0, int B) {
   return min(max((int)fmaf(sample_tau(r, k), dqm, qm0), 0), B);
@@ -746,7 +784,6 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
   constexpr int align = kRowAlignBytes / (int)sizeof(T);  // voxels per chunk
   const int cap = (a.stage_bytes / (int)sizeof(T) / CH) & ~(align - 1);
   const ViewDev& V = a.views[tl.view];
-  const bool want_depth = V.depth != nullptr;
   int mb_key[CH][3];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
@@ -754,6 +791,8 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
   r.alive = false;
   r.Cr = r.Cg = r.Cb = r.A = 0.f;
   r.depth = INFINITY;
+  r.dtau = INFINITY;
+  r.dalpha = V.depth ? a.depth_alpha : INFINITY;
   r.nsamp = 0;
   r.n = r.k = 0;
   if (tl.in_image) {
@@ -812,7 +851,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
             return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
           };
-          while (r.k < r.n && sample_once<MODEL, CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
+          while (r.k < r.n && sample_once<MODEL, CH, STATS>(r, a, s_tf, fetch, mb_key)) {
           }
         }
         continue;
@@ -827,9 +866,11 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         kb = r.k - 1;
         uint32_t plo = 0xFFFFFFFFu, phi = 0xFFFFFFFFu;  // packed min(lo), min(~hi)
         if (more) {
+          // a first guess of the last sample in the slab (reciprocals, not
+          // divisions: the two searches below make it exact)
           const float edge = sgn > 0 ? (float)(jh + 1) : (float)jl;
-          const float tlim = (edge - my_qm0) / my_dqm;
-          kb = (int)ceilf(tlim / r.Df - 0.5f) - 1;
+          const float tlim = (edge - my_qm0) * __builtin_amdgcn_rcpf(my_dqm);
+          kb = (int)ceilf(tlim * __builtin_amdgcn_rcpf(r.Df) - 0.5f) - 1;
           kb = min(max(kb, r.k - 1), r.n - 1);
           while (kb + 1 < r.n) {
             const int im = sample_layer(r, kb + 1, my_dqm, my_qm0, B);
@@ -873,17 +914,19 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         wd[1] = min(wd[1], S - o[1]);
         wd[2] = min(wd[2], S - o[2]);
         const int vox = wd[0] * wd[1] * wd[2];
+        // (the depth only shapes the slabs, never which samples they hold,
+        // so its quotients are taken with reciprocals)
+        const int area = max(1, quot(vox, max(1, wd[m])));
         if (vox <= cap) {
           fits = vox > 0;
           // next slab's depth from this slab's cross-section
-          const int area = max(1, vox / max(1, wd[m]));
-          D = min(max(cap / area - 1, 1), 64);
+          D = min(max(quot(cap, area) - 1, 1), 64);
           break;
         }
         if (D == 1) break;
         // the cross-section of a thinner slab is no larger (its samples are
         // a subset), so this depth fits unless even one layer does not
-        D = max(1, min(D - 1, cap / max(1, vox / max(1, wd[m])) - 1));
+        D = max(1, min(D - 1, quot(cap, area) - 1));
       }
       if (fits) {
         // --- stage the region of every channel: pass p moves chunks
@@ -924,15 +967,17 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
                     (unsigned long long)(total * kRowAlignBytes * CH));
         }
         if (kb >= r.k) {
-          const int sy_l = wd[0], sz_l = wd[0] * wd[1];
+          const int sy_l = wd[0], wy = wd[1];
           const int base_off = (o[2] * wd[1] + o[1]) * wd[0] + o[0];  // region origin
-          const int wy = wd[1];
+          // byte addresses: the region's origin, and the row and plane steps
+          const char* sb = reinterpret_cast<const char*>(stage - base_off);
+          const int syb = sy_l * (int)sizeof(T), szb = sy_l * wy * (int)sizeof(T);
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            const int idx = __mul24(__mul24(iz, wy) + iy, sy_l) + ix - base_off;
-            return trilinear(stage + ch * cap + idx, sy_l, sz_l, fx, fy, fz);
+            const int idx = __mul24(__mul24(iz, wy) + iy, sy_l) + ix;
+            return trilinear_bytes<T>(sb + (ch * cap + idx) * (int)sizeof(T), syb, szb, fx, fy,
+                                      fz);
           };
-          while (r.k <= kb &&
-                 sample_once<MODEL, CH, STATS, false>(r, a, s_tf, want_depth, fetch, mb_key)) {
+          while (r.k <= kb && sample_once<MODEL, CH, STATS, false>(r, a, s_tf, fetch, mb_key)) {
           }
         }
         wave_sync();
@@ -941,7 +986,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
           return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
         };
-        while (r.k <= kb && sample_once<MODEL, CH, STATS>(r, a, s_tf, want_depth, fetch, mb_key)) {
+        while (r.k <= kb && sample_once<MODEL, CH, STATS>(r, a, s_tf, fetch, mb_key)) {
         }
       }
       j = sgn > 0 ? jh + 1 : jl - 1;
