@@ -72,12 +72,13 @@ def main():
                     help="explicit launch configuration kernel,tile,block,stage_bytes,persistent "
                          "(no autotuning); profiles use the one the benchmark chose")
     ap.add_argument("--workload", default="tubes",
-                    choices=("tubes", "batched64", "upsampler", "stream"),
+                    choices=("tubes", "batched64", "upsampler", "stream", "hmd"),
                     help="tubes: the bricked stereo frame (default, the headline); "
                          "batched64: 64 uneven views of the 128^3 blob volume in one call; "
                          "upsampler: learned-upsampler path vs plain path on the blob scene; "
                          "stream: the 3-channel cell time series played through the "
-                         "out-of-core brick cache")
+                         "out-of-core brick cache; hmd: the bricked stereo frame under each "
+                         "HMD variant (optical models, lens, clipping, depth limit)")
     ap.add_argument("--stream-timepoints", type=int, default=6,
                     help="stream: timepoints held in the host tier (the movie loops over them)")
     ap.add_argument("--stream-slots", type=int, default=10000,
@@ -109,6 +110,9 @@ def main():
         return
     if args.workload == "stream":
         bench_stream(args)
+        return
+    if args.workload == "hmd":
+        bench_hmd(args)
         return
 
     import gen
@@ -374,6 +378,12 @@ def bench_upsampler(args):
     path = U.UpsampledPath(h, model, diag, base, W, H, 2, lod=sc["lod"])
     plain = torch.empty(2, H, W, 4, device="cuda")
     p_full = path.p_full
+    # set-up, untimed: the launch configuration tuned on the plain path's
+    # frame serves both paths (every configuration renders the same image)
+    launch, _ = sg.sg_autotune(h, gen.orbit_views(center, radius, 1, 4005, W, H, tan_t,
+                                                  stereo_ipd=sc["ipd"])[0], p_full, list(plain),
+                               repeats=2)
+    log("launch configuration: %s" % launch)
 
     def frame_psnr(views):
         sg.sg_render_views(h, views, p_full, list(plain))
@@ -469,7 +479,7 @@ def bench_upsampler(args):
                       "train_pairs": args.train_pairs, "train_steps": steps,
                       "eval_frames": len(ev)},
            "plain_ms": plain_ms, "plain_fps": 1e3 / plain_ms, "upsampler_path_ms": up_ms,
-           "speedup_vs_plain": plain_ms / up_ms, "timed_fallbacks": fell,
+           "speedup_vs_plain": plain_ms / up_ms, "timed_fallbacks": fell, "launch": launch,
            "upsampler_path_host_decision_ms": up_host_ms,
            "timed_fallbacks_host_decision": int(fell_host),
            "network_ms": net_ms,
@@ -487,6 +497,87 @@ def bench_upsampler(args):
            "delivered_frac_ge_40db": float(np.mean(delivered >= 40.0)),
            "train_seconds": train_s, "train_loss_first_last": [losses[0], losses[-1]]}
     model.close()
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def bench_hmd(args):
+    """The bricked stereo frame (tubes2048, both eyes, the launch the
+    autotuner picks for the plain frame) under each HMD variant, timed with
+    HIP events around the ray-casting kernel: emission-absorption (the plain
+    frame), emission-only, maximum intensity, wrapped-space rays (radial lens
+    k1 0.22, k2 0.24 about the view centre), a cut plane through the volume
+    centre, a region of interest (the central half of every axis), a
+    depth-buffer ray limit (a synthetic opaque plane 0.9 m from the head) and
+    first-hit depth output. One step = one stereo frame of every variant."""
+    import torch
+
+    import gen
+    from gen.large import TubeVolume, upload_generated
+    from paper_1804_08197_amd import sg
+    dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
+    tv = TubeVolume().to_device()
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
+    sg.sg_build_lod(h, 0, 0)
+    sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
+    sg.sg_volume_commit(h)
+    views = workload_views()
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    depth = [torch.empty(v["height"], v["width"], device="cuda") for v in views]
+    launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+    # the synthetic depth buffer: distance along each pixel's ray to a plane
+    # 0.9 m (1843.2 voxels) in front of the eye, perpendicular to the view axis
+    limits = []
+    for v in views:
+        W, H = v["width"], v["height"]
+        sx = v["tan_left"] + (np.arange(W) + 0.5) / W * (v["tan_right"] - v["tan_left"])
+        sy = v["tan_top"] - (np.arange(H) + 0.5) / H * (v["tan_top"] - v["tan_bottom"])
+        dist = 1843.2 * np.sqrt(1.0 + sx[None, :] ** 2 + sy[:, None] ** 2)
+        limits.append(torch.from_numpy(dist.astype(np.float32)).cuda())
+    c = np.array([1024.0, 1024.0, 1024.0])
+    n = gen.unit((1.0, 0.7, 0.4))
+    lens = (0.22, 0.24, 0.0, 0.0)
+    variants = [
+        ("emission_absorption", views, dict(PARAMS), None),
+        ("emission_only", views, dict(PARAMS, model="eo"), None),
+        ("max_intensity", views, dict(PARAMS, model="mip"), None),
+        ("wrapped_space_lens", [dict(v, lens=lens) for v in views], dict(PARAMS), None),
+        ("cut_plane", views, dict(PARAMS, planes=[(n[0], n[1], n[2], -float(n @ c))]), None),
+        ("roi_box", views, dict(PARAMS, roi=(512, 512, 512, 1536, 1536, 1536)), None),
+        ("depth_buffer_limit", [dict(v, ray_limit=l) for v, l in zip(views, limits)],
+         dict(PARAMS), None),
+        ("depth_output", views, dict(PARAMS), depth),
+    ]
+    res = {}
+    for name, vs, p, dep in variants:
+        st = sg.sg_render_views_stats(h, vs, p, outs, dep)
+        for _ in range(args.warmup):
+            sg.sg_render_views(h, vs, p, outs, dep)
+        torch.cuda.synchronize()
+        sg.sg_set_kernel_timing(h, True)
+        for _ in range(args.steps):
+            sg.sg_render_views(h, vs, p, outs, dep)
+        n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+        sg.sg_set_kernel_timing(h, False)
+        res[name] = {"raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
+                     "samples": st["total_samples"],
+                     "samples_per_s": st["total_samples"] / (ray_ms / n_k * 1e-3)}
+        log("%s: %.3f ms, %d samples" % (name, ray_ms / n_k, st["total_samples"]))
+    total_ms = sum(r["raycast_kernel_ms"] + r["cutmap_kernel_ms"] for r in res.values())
+    base = res["emission_absorption"]
+    alu = {"bound": "alu",
+           "achieved": base["samples"] * FLOP_PER_SAMPLE / (base["raycast_kernel_ms"] * 1e-3) / 1e12,
+           "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "traffic": None}
+    alu["frac"] = alu["achieved"] / alu["peak"]
+    out = {"metric": "stereo frames/s of the bricked frame under each HMD variant",
+           "value": 1e3 * len(res) / total_ms, "unit": "stereo frames/s (mean over variants)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_hmd_variants",
+                      "variants": list(res)},
+           "variants": res, "launch": launch, "roofline": alu}
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
 
