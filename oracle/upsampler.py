@@ -21,6 +21,14 @@ operation is written out from its definition in double precision:
 * bilinear upsampling by two with half-pixel centres: full-resolution pixel
   X samples low-resolution coordinate (X + 1/2) / 2 - 1/2, edges clamped.
 
+At inference (``forward(..., skip_empty=True)``) a low-resolution pixel
+whose 9 x 9 neighbourhood of x0 (the network's receptive field: four stacked
+3 x 3 convolutions; pixels outside the image count as zero) holds no nonzero
+value yields background: rgba 0 at its four full-resolution pixels and a
+predicted error of 0. Its bilinear base is 0 anyway (the base reads the
+1-pixel ring); only the network's constant response to an empty input is
+dropped. Training evaluates the network everywhere.
+
 ``loss_and_grads`` gives the training loss (mean squared RGBA error plus the
 error head's mean squared error against the actual per-pixel RMS RGB error,
 held constant) and its gradients by backpropagation written out step by
@@ -121,10 +129,26 @@ def pixel_unshuffle(g, channels=C_OUT):
     return out
 
 
-def forward(params, x0, act_round=None):
+def empty_neighbourhood(x0, radius=4):
+    """[N, H, W] booleans: no nonzero channel of x0 within `radius` pixels
+    (a (2 radius + 1)^2 window; outside the image counts as zero)."""
+    x0 = np.asarray(x0)
+    N, H, W, _ = x0.shape
+    nz = np.any(x0 != 0, axis=-1)
+    pad = np.zeros((N, H + 2 * radius, W + 2 * radius), dtype=bool)
+    pad[:, radius:radius + H, radius:radius + W] = nz
+    anyv = np.zeros((N, H, W), dtype=bool)
+    for dy in range(2 * radius + 1):
+        for dx in range(2 * radius + 1):
+            anyv |= pad[:, dy:dy + H, dx:dx + W]
+    return ~anyv
+
+
+def forward(params, x0, act_round=None, skip_empty=False):
     """params: list of (w, b) per layer. Returns (rgba [N,2H,2W,4], z
     [N,2H,2W], cache for backpropagation). act_round, if given, is applied
-    to every hidden activation (the precision they are stored in)."""
+    to every hidden activation (the precision they are stored in). With
+    skip_empty (inference), pixels with an empty neighbourhood yield 0."""
     h = [np.asarray(x0, np.float64)]
     pre = []
     for i, (w, b) in enumerate(params):
@@ -138,7 +162,12 @@ def forward(params, x0, act_round=None):
     sh = pixel_shuffle(h[-1])
     base = bilinear_up2(h[0][..., :4])
     rgba = base + sh[..., :4]
-    return rgba, sh[..., 4], (h, pre)
+    z = sh[..., 4]
+    if skip_empty:
+        e = np.repeat(np.repeat(empty_neighbourhood(h[0]), 2, axis=1), 2, axis=2)
+        rgba = np.where(e[..., None], 0.0, rgba)
+        z = np.where(e, 0.0, z)
+    return rgba, z, (h, pre)
 
 
 def loss_and_grads(params, x0, target, err_weight=1.0, act_round=None):

@@ -130,3 +130,40 @@ def test_psnr_and_depth_code():
     assert abs(U.psnr(a, b) - 40.0) < 1e-9
     assert U.psnr(a, a) == float("inf")
     assert np.allclose(U.depth_code([0.0, 221.7, np.inf], 221.7), [1.0, 0.5, 0.0])
+
+
+def test_empty_neighbourhood_matches_a_maximum_filter():
+    """The inference rule's neighbourhood (radius 4 = the receptive field of
+    four 3x3 layers) equals scipy's 9x9 maximum filter of the nonzero mask
+    with zero outside the image; one lit pixel lights exactly its 9x9 block."""
+    from scipy.ndimage import maximum_filter
+    rng = np.random.default_rng(21)
+    x0 = np.zeros((2, 23, 31, 8))
+    lit = rng.uniform(size=(2, 23, 31)) < 0.01
+    x0[lit, rng.integers(0, 5)] = rng.uniform(0.1, 1.0, size=lit.sum())
+    want = ~maximum_filter(np.any(x0 != 0, axis=-1), size=(1, 9, 9), mode="constant", cval=0)
+    assert np.array_equal(U.empty_neighbourhood(x0), want)
+    one = np.zeros((1, 20, 20, 8))
+    one[0, 7, 12, 4] = 0.5
+    ne = ~U.empty_neighbourhood(one)[0]
+    ys, xs = np.nonzero(ne)
+    assert (ys.min(), ys.max(), xs.min(), xs.max()) == (3, 11, 8, 16) and ne.sum() == 81
+
+
+def test_skip_empty_drops_only_the_constant_response():
+    """With skip_empty, pixels with an empty neighbourhood give 0 (their
+    bilinear base is already 0); every other pixel is unchanged."""
+    rng = np.random.default_rng(22)
+    params = [(rng.normal(size=(9, ci, co)) * 0.2, rng.normal(size=co) * 0.1)
+              for ci, co in U.LAYERS]
+    x0 = np.zeros((1, 26, 30, 8))
+    x0[0, 3:9, 4:12, :5] = rng.uniform(0, 1, size=(6, 8, 5))
+    rgba, z, _ = U.forward(params, x0)
+    srgba, sz, _ = U.forward(params, x0, skip_empty=True)
+    e = np.repeat(np.repeat(U.empty_neighbourhood(x0), 2, axis=1), 2, axis=2)[0]
+    assert e.any() and (~e).any()
+    assert np.array_equal(srgba[0][~e], rgba[0][~e]) and np.array_equal(sz[0][~e], z[0][~e])
+    assert np.all(srgba[0][e] == 0) and np.all(sz[0][e] == 0)
+    base = U.bilinear_up2(x0[..., :4])[0]
+    assert np.all(base[e] == 0)
+    assert np.abs(rgba[0][e]).max() > 0  # the network alone would not give 0 there
