@@ -384,6 +384,10 @@ def bench_upsampler(args):
                                                   stereo_ipd=sc["ipd"])[0], p_full, list(plain),
                                repeats=2)
     log("launch configuration: %s" % launch)
+    # the upsampler path's own launch: the same with workgroup tiles of at
+    # least 16 pixels, so its gated full-resolution render, when skipped,
+    # dispatches few workgroups (images are the same under every launch)
+    launch_up = dict(launch, tile=max(16, launch["tile"]), block=max(launch["block"], 32))
 
     def frame_psnr(views):
         sg.sg_render_views(h, views, p_full, list(plain))
@@ -427,10 +431,12 @@ def bench_upsampler(args):
     sub = ev[:min(len(ev), 200)]
 
     def run_plain():
+        sg.sg_set_launch_config(h, launch)
         for v in sub:
             sg.sg_render_views(h, v, p_full, list(plain))
 
     def run_up_host():
+        sg.sg_set_launch_config(h, launch_up)
         fell = 0
         for v in sub:
             fell += path.render(v)[1]
@@ -440,6 +446,7 @@ def bench_upsampler(args):
 
     def run_up():
         # the product path: the fallback decision stays on the device
+        sg.sg_set_launch_config(h, launch_up)
         for i, v in enumerate(sub):
             path.render_device(v, flags[i:i + 1])
 
@@ -480,6 +487,7 @@ def bench_upsampler(args):
                       "eval_frames": len(ev)},
            "plain_ms": plain_ms, "plain_fps": 1e3 / plain_ms, "upsampler_path_ms": up_ms,
            "speedup_vs_plain": plain_ms / up_ms, "timed_fallbacks": fell, "launch": launch,
+           "launch_upsampler_path": launch_up,
            "upsampler_path_host_decision_ms": up_host_ms,
            "timed_fallbacks_host_decision": int(fell_host),
            "network_ms": net_ms,

@@ -16,6 +16,13 @@
  *     err  = o[y][x][5s+4]^2, a prediction of that pixel's mean squared RGB
  *            error; its frame mean predicts the frame's PSNR, which decides
  *            whether the caller falls back to a full-resolution render.
+ *   At inference, a low-resolution pixel whose 9 x 9 neighbourhood of x0
+ *   (the receptive field of the four layers; outside the image counts as
+ *   zero) holds no nonzero value yields rgba 0 and err 0 at its four
+ *   full-resolution pixels (background: its bilinear base is 0; the
+ *   network's constant response to an empty input is dropped). Tiles whose
+ *   whole input region is empty skip the network. Training (sg_up_gradients,
+ *   sg_up_train_step) evaluates the network everywhere.
  * Weights are packed layer by layer as w[9][c_in][32] (tap = 3 (dy+1) +
  * (dx+1)) followed by b[32], with c_in = 8, 32, 32, 32.
  *

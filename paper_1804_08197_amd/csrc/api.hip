@@ -41,22 +41,25 @@ DeviceGuard::~DeviceGuard() {
 sg_status stage_to_device(Volume* v, const void* host, int64_t bytes, void* dev,
                           hipStream_t stream) {
   if (bytes <= 0) return SG_OK;
-  if (v->stage_pending) {
-    SG_HIP(hipEventSynchronize(v->stage_done));
-    v->stage_pending = false;
+  // the ring slot used Volume::kStageRing uploads ago is free once its copy ran
+  const int k = v->stage_next;
+  v->stage_next = (k + 1) % Volume::kStageRing;
+  if (v->stage_pending[k]) {
+    SG_HIP(hipEventSynchronize(v->stage_done[k]));
+    v->stage_pending[k] = false;
   }
-  if (bytes > v->stage_cap) {
-    if (v->stage_host) SG_HIP(hipHostFree(v->stage_host));
-    v->stage_host = nullptr;
-    v->stage_cap = 0;
+  if (bytes > v->stage_cap[k]) {
+    if (v->stage_host[k]) SG_HIP(hipHostFree(v->stage_host[k]));
+    v->stage_host[k] = nullptr;
+    v->stage_cap[k] = 0;
     int64_t cap = std::max<int64_t>(bytes, 1 << 16);
-    SG_HIP(hipHostMalloc((void**)&v->stage_host, (size_t)cap, hipHostMallocDefault));
-    v->stage_cap = cap;
+    SG_HIP(hipHostMalloc((void**)&v->stage_host[k], (size_t)cap, hipHostMallocDefault));
+    v->stage_cap[k] = cap;
   }
-  std::memcpy(v->stage_host, host, (size_t)bytes);
-  SG_HIP(hipMemcpyAsync(dev, v->stage_host, (size_t)bytes, hipMemcpyHostToDevice, stream));
-  SG_HIP(hipEventRecord(v->stage_done, stream));
-  v->stage_pending = true;
+  std::memcpy(v->stage_host[k], host, (size_t)bytes);
+  SG_HIP(hipMemcpyAsync(dev, v->stage_host[k], (size_t)bytes, hipMemcpyHostToDevice, stream));
+  SG_HIP(hipEventRecord(v->stage_done[k], stream));
+  v->stage_pending[k] = true;
   return SG_OK;
 }
 
@@ -93,8 +96,10 @@ void free_all(Volume* v) {
   hipFree(v->view_dev);
   hipFree(v->mb_bits);
   hipFree(v->counters);
-  if (v->stage_host) hipHostFree(v->stage_host);
-  if (v->stage_done) hipEventDestroy(v->stage_done);
+  for (int k = 0; k < Volume::kStageRing; ++k) {
+    if (v->stage_host[k]) hipHostFree(v->stage_host[k]);
+    if (v->stage_done[k]) hipEventDestroy(v->stage_done[k]);
+  }
   for (hipEvent_t e : v->ev_free) hipEventDestroy(e);
   for (hipEvent_t e : v->ev_rec) hipEventDestroy(e);
 }
@@ -190,11 +195,12 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
     (void)hipGetLastError();
     return fail(SG_ERR_OUT_OF_MEMORY, "device allocation failed (cache tables)");
   }
-  if (hipEventCreateWithFlags(&v->stage_done, hipEventDisableTiming) != hipSuccess) {
-    free_all(v);
-    delete h;
-    return fail(SG_ERR_DEVICE, "event creation failed");
-  }
+  for (int k = 0; k < Volume::kStageRing; ++k)
+    if (hipEventCreateWithFlags(&v->stage_done[k], hipEventDisableTiming) != hipSuccess) {
+      free_all(v);
+      delete h;
+      return fail(SG_ERR_DEVICE, "event creation failed");
+    }
   // page table: every node resident with slot = (t * C + c) * nodes + node,
   // or (cache) nothing resident and every slot free
   std::vector<int32_t> page((size_t)v->entries);

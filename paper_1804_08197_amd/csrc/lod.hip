@@ -101,14 +101,21 @@ __device__ __forceinline__ bool node_suits(const CutGeom& g, const double e[3],
   return (s * s) <= (K * d2);
 }
 
-__global__ void cutmap_kernel(CutGeom g, const ViewDev* views, int n_views,
-                              int32_t* cutmap) {
+__global__ void cutmap_kernel(CutGeom g, ViewDev* views, int n_views, int32_t* cutmap,
+                              InlineViews iv) {
   if (g.enable && *g.enable == 0) return;
+  if (iv.n && blockIdx.x == 0) {
+    // the small view table, from the arguments into the device table
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(iv.v);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(views);
+    const int words = iv.n * (int)(sizeof(ViewDev) / 4);
+    for (int k = threadIdx.x; k < words; k += blockDim.x) dst[k] = src[k];
+  }
   const int64_t total = (int64_t)n_views * g.cells;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t v = i / g.cells, cell = i - v * g.cells;
-    const ViewDev& V = views[v];
+    const ViewDev& V = iv.n ? iv.v[v] : views[v];
     int32_t cx = (int32_t)(cell % g.grid[0][0]);
     int32_t cy = (int32_t)((cell / g.grid[0][0]) % g.grid[0][1]);
     int32_t cz = (int32_t)(cell / ((int64_t)g.grid[0][0] * g.grid[0][1]));
@@ -158,7 +165,7 @@ CutGeom cut_geom(const Volume* v, int bias, bool lod, int timepoint) {
 
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
                         bool lod, int timepoint, int32_t* cutmap, Launch* out,
-                        const int32_t* enable) {
+                        const int32_t* enable, const InlineViews* iv) {
   CutGeom g = cut_geom(v, bias, lod, timepoint);
   g.enable = enable;
   int64_t total = (int64_t)n_views * g.cells;
@@ -168,18 +175,21 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
   out->block = dim3(256);
   out->lds = 0;
   out->arg.clear();
+  InlineViews inl{};
+  if (iv && iv->n) inl = *iv;
   out->push(g);
-  out->push(dviews);
+  out->push(const_cast<ViewDev*>(dviews));
   out->push(n_views);
   out->push(cutmap);
+  out->push(inl);
   return SG_OK;
 }
 
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
                         bool lod, int timepoint, hipStream_t s, const int32_t* enable) {
   Launch l;
-  sg_status st =
-      cutmap_launch(v, dviews, n_views, bias, lod, timepoint, v->cutmap, &l, enable);
+  sg_status st = cutmap_launch(v, dviews, n_views, bias, lod, timepoint, v->cutmap, &l, enable,
+                               &v->inline_views);
   if (st != SG_OK) return st;
   return l.run(s);
 }

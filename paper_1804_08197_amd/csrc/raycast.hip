@@ -299,8 +299,15 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
       return fail(SG_ERR_OUT_OF_MEMORY, "view table allocation failed");
     v->view_cap = vbytes;
   }
-  st = stage_to_device(v, hv.data(), vbytes, v->view_dev, s);
-  if (st != SG_OK) return st;
+  if (n_views <= kInlineViews) {
+    // carried by the cut-map kernel's arguments (see InlineViews)
+    v->inline_views.n = n_views;
+    for (int i = 0; i < n_views; ++i) v->inline_views.v[i] = hv[(size_t)i];
+  } else {
+    v->inline_views.n = 0;
+    st = stage_to_device(v, hv.data(), vbytes, v->view_dev, s);
+    if (st != SG_OK) return st;
+  }
   *total_blocks = (int)blocks;
   return SG_OK;
 }

@@ -97,6 +97,35 @@ __device__ __forceinline__ uint64_t visibility_key(int key_levels, int B, const 
   return key << (3 * L);
 }
 
+// Per-view constants consumed by the LOD and ray-casting kernels.
+struct ViewDev {
+  double e[3];
+  double R[9];  // row-major rotation, camera -> world
+  double tl, tr, tb, tt;
+  double K;     // (tau * theta)^2
+  int32_t W, H;
+  int32_t tiles_x, tiles_y;  // 16x16 pixel tiles
+  int32_t blocks_x;          // 4x4-tile blocks per row
+  int32_t block_begin;       // first block of this view
+  int64_t cut_off;     // offset of this view's cut map
+  float* rgba;
+  float* depth;
+  int32_t* nsamp;
+  const float* limit;  // per-pixel ray limit or NULL
+  double lens[4];      // k1, k2, cx, cy
+  int32_t lens_on;
+};
+
+// Up to kInlineViews view records travel inside the cut-map kernel's
+// arguments; its first workgroup writes them to the device view table that
+// the ray-casting kernel reads (stream order), so small renders need no
+// host-to-device copy.
+constexpr int kInlineViews = 4;
+struct InlineViews {
+  ViewDev v[kInlineViews];
+  int32_t n;  // 0: the device table is already in place
+};
+
 struct Volume {
   sg_volume_desc d{};
   int bpv = 0;       // bytes per voxel
@@ -130,11 +159,16 @@ struct Volume {
   int32_t* cutmap = nullptr;  // [views][cells0] cut node of each level-0 cell
   int64_t cutmap_cap = 0;
   uint8_t* view_dev = nullptr;
+  InlineViews inline_views{};  // the last prepare_views' table when it is small
   int64_t view_cap = 0;
-  uint8_t* stage_host = nullptr;  // pinned staging for small uploads
-  int64_t stage_cap = 0;
-  hipEvent_t stage_done = nullptr;
-  bool stage_pending = false;
+  // pinned staging for small uploads (view tables): a ring, so the host can
+  // enqueue several renders ahead of the device
+  static constexpr int kStageRing = 4;
+  uint8_t* stage_host[kStageRing] = {};
+  int64_t stage_cap[kStageRing] = {};
+  hipEvent_t stage_done[kStageRing] = {};
+  bool stage_pending[kStageRing] = {};
+  int stage_next = 0;
   uint32_t* mb_bits = nullptr;  // micro-block bitmap (stats only)
   int64_t mb_words = 0;
   uint64_t* counters = nullptr;  // device counters (stats only)
@@ -174,7 +208,8 @@ struct DeviceGuard {
 };
 
 // Stage `bytes` of host data into device memory on `stream` through the
-// volume's pinned buffer (waits for the previous staged copy first).
+// volume's ring of pinned buffers (waits for the copy that last used the
+// slot).
 sg_status stage_to_device(Volume* v, const void* host, int64_t bytes,
                           void* dev, hipStream_t stream);
 
@@ -191,25 +226,9 @@ sg_status launch_empty(Volume* v, hipStream_t s);
 bool top_level_resident(const Volume* v, int t);
 sg_status commit(Volume* v, hipStream_t s);
 
-// Per-view constants consumed by the LOD and ray-casting kernels.
-struct ViewDev {
-  double e[3];
-  double R[9];  // row-major rotation, camera -> world
-  double tl, tr, tb, tt;
-  double K;     // (tau * theta)^2
-  int32_t W, H;
-  int32_t tiles_x, tiles_y;  // 16x16 pixel tiles
-  int32_t blocks_x;          // 4x4-tile blocks per row
-  int32_t block_begin;       // first block of this view
-  int64_t cut_off;     // offset of this view's cut map
-  float* rgba;
-  float* depth;
-  int32_t* nsamp;
-  const float* limit;  // per-pixel ray limit or NULL
-  double lens[4];      // k1, k2, cx, cy
-  int32_t lens_on;
-};
 
+
+// Uses (and writes to the device table) v->inline_views when its n is set.
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views,
                         int bias, bool lod, int timepoint, hipStream_t s,
                         const int32_t* enable = nullptr);
@@ -226,9 +245,10 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       int64_t* total_blocks);
 // The cut-map kernel for views already on the device, writing `cutmap`.
 // enable: NULL, or a device flag read by the kernel (0: it does nothing).
+// iv: NULL or n == 0, or the views to use and to write to dviews.
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
                         bool lod, int timepoint, int32_t* cutmap, Launch* out,
-                        const int32_t* enable = nullptr);
+                        const int32_t* enable = nullptr, const InlineViews* iv = nullptr);
 
 struct RenderArgs {
   const uint8_t* pool;

@@ -213,6 +213,22 @@ __device__ __forceinline__ float4 base_rgba(const bf16* x0, int n, int H, int W,
   return make_float4(o[0], o[1], o[2], o[3]);
 }
 
+// Inference rule: a pixel whose 9 x 9 neighbourhood of x0 (the receptive
+// field of the four 3 x 3 layers; outside the image counts as zero) holds
+// no nonzero value yields background and a predicted error of 0.
+constexpr int kReach = 4;
+__device__ __forceinline__ bool x0_nonzero(const bf16x8& v) {
+  const uint4 u = __builtin_bit_cast(uint4, v);
+  return ((u.x | u.y | u.z | u.w) & 0x7FFF7FFFu) != 0u;  // -0 counts as zero
+}
+__device__ bool empty_neighbourhood(const bf16* x0, int n, int H, int W, int y, int x) {
+  for (int yy = max(y - kReach, 0); yy <= min(y + kReach, H - 1); ++yy)
+    for (int xx = max(x - kReach, 0); xx <= min(x + kReach, W - 1); ++xx)
+      if (x0_nonzero(reinterpret_cast<const bf16x8*>(x0)[((int64_t)n * H + yy) * W + xx]))
+        return false;
+  return true;
+}
+
 // Inference epilogue: full-resolution rgba and predicted squared error; the
 // per-image sum of the prediction accumulates in mse_sum[n] (doubles).
 __global__ __launch_bounds__(256) void shuffle_kernel(const float* o, const bf16* x0, int N, int H,
@@ -226,11 +242,17 @@ __global__ __launch_bounds__(256) void shuffle_kernel(const float* o, const bf16
     n = (int)(p / ((int64_t)H * W));
     const int r = (int)(p - (int64_t)n * H * W), y = r / W, x = r - y * W;
     const float* op = o + p * kCh;
+    const bool empty = empty_neighbourhood(x0, n, H, W, y, x);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int sy = s >> 1, sx = s & 1;
-      const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
       const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
+      if (empty) {  // background, and no predicted error
+        out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (err) err[q] = 0.f;
+        continue;
+      }
+      const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
       out[q] = make_float4(b.x + op[5 * s], b.y + op[5 * s + 1], b.z + op[5 * s + 2],
                            b.w + op[5 * s + 3]);
       const float z = op[5 * s + 4];
@@ -430,68 +452,87 @@ __device__ __forceinline__ void fused_layer(const bf16* __restrict__ sin, void* 
     fused_blocks<CIN, EIN, MAXJ - 1, LAST>(sin, sout, wf, wnext, wn, bias, oy0, ox0, H, W);
 }
 
-// LDS allows two workgroups per CU (two waves per SIMD): the register
-// budget is set for that, so a K-step's reads can all be in flight.
-__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
-fused_forward_kernel(
-    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
-    float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
-    const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
-    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
-    float4* __restrict__ out, float* __restrict__ err, double* __restrict__ mse_sum) {
-  // LDS (kFusedLds bytes): U, V, then x0's rgba (bf16-rounded) on the tile
-  // and a 1-pixel ring for the bilinear base of the last phase, then the
-  // reduction scratch
-  extern __shared__ float4 fused_smem[];
-  bf16* sU = reinterpret_cast<bf16*>(fused_smem);
-  bf16* sV = sU + kBufU;
-  float4* sX = reinterpret_cast<float4*>(sV + kBufV);
-  double* red = reinterpret_cast<double*>(sX + kE1 * kE1);
-  const int n = blockIdx.z;
-  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
-  bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
-  load_weights<8>(w0, wa);
-  // x0 on the tile and a 4-pixel halo (zero outside the image): every load
-  // is issued before any is used
-  constexpr int kPrep = (kE0 * kE0 + 255) / 256;
-  float4 pc[kPrep];
-  float pd[kPrep];
-#pragma unroll
-  for (int k = 0; k < kPrep; ++k) {
-    const int p = threadIdx.x + 256 * k;
-    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
-    pc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    pd[k] = INFINITY;
-    if (p < kE0 * kE0 && y >= 0 && y < H && x >= 0 && x < W) {
-      const int64_t q = ((int64_t)n * H + y) * W + x;
-      pc[k] = rgba[q];
-      pd[k] = depth[q];
+// Per-image sums of the predicted squared error. The fused kernel writes
+// one partial per workgroup (no atomics: device-wide atomics on one address
+// serialise across the XCDs); tile_sum_kernel then adds each image's
+// partials in a fixed order (deterministic), and takes the fallback
+// decision if asked. The layer-by-layer path adds into zeroed sums directly
+// and finish_kernel copies them out.
+struct SumArgs {
+  double* sum;        // fused: [workgroups] partials; layered: [N] sums
+  double* result;     // [N] per-image sums of this launch
+  int32_t* fallback;  // NULL, or the frame's decision (predicted PSNR < threshold)
+  int32_t images;     // N
+  int32_t tiles;      // fused: workgroups per image
+  double pixels;      // full-resolution pixels per image
+  double threshold_db;
+};
+
+// fallback = 1 when 10 log10(1 / m) < threshold, m the mean over the
+// images of sum_i / pixels (the frame's predicted mean squared error)
+__device__ __forceinline__ int32_t decide(const double* result, int n, double pixels,
+                                          double threshold_db) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m += result[i] / pixels;
+  m /= (double)n;
+  const double psnr = m <= 0.0 ? INFINITY : 10.0 * log10(1.0 / m);
+  return psnr < threshold_db ? 1 : 0;
+}
+
+// One workgroup: result[i] = the partials of image i added in a fixed order.
+__global__ __launch_bounds__(256) void tile_sum_kernel(SumArgs a) {
+  __shared__ double red[256];
+  for (int i = 0; i < a.images; ++i) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < a.tiles; t += 256) v += a.sum[(int64_t)i * a.tiles + t];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
     }
+    if (threadIdx.x == 0) a.result[i] = red[0];
+    __syncthreads();
   }
+  if (threadIdx.x == 0 && a.fallback)
+    *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
+}
+
+// the workgroup's share of the predicted error, into its partial slot
+__device__ void tile_partial(const SumArgs& a, double* red, float zsum) {
+  red[threadIdx.x] = (double)zsum;
+  __syncthreads();
+  for (int st = (int)blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    a.sum[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// The network on a tile with content (every layer, then the pixel shuffle,
+// bilinear residual and error head); returns this thread's share of the
+// predicted squared error.
+__device__ __forceinline__ float fused_tile(
+    bf16* sU, bf16* sV, const float4* sX, const uint8_t* nzf, uint8_t* rowany,
+    const bf16x8 (&wa)[ksteps(8)], bf16x8 (&wb)[ksteps(32)], bf16x8 (&wc)[ksteps(32)],
+    const bf16x8* __restrict__ w1, const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3,
+    const float* __restrict__ b0, const float* __restrict__ b1, const float* __restrict__ b2,
+    const float* __restrict__ b3, int n, int H, int W, int ty0, int tx0, int qy, int qx, int y,
+    int x, float4* __restrict__ out, float* __restrict__ err) {
+  // per pixel: any nonzero in its 9 x 9 window (rows qy .. qy+8, columns
+  // qx .. qx+8 of the region), as a row pass and a column pass
+  for (int e = threadIdx.x; e < kE0 * kTile; e += 256) {
+    const int ry = e / kTile, cx = e % kTile;
+    uint8_t m = 0;
 #pragma unroll
-  for (int k = 0; k < kPrep; ++k) {
-    const int p = threadIdx.x + 256 * k;
-    if (p >= kE0 * kE0) continue;
-    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
-    bf16x8 v;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = (bf16)0.0f;
-    if (y >= 0 && y < H && x >= 0 && x < W) {
-      const float4 c = pc[k];
-      const float d = pd[k];
-      const float code = isfinite(d) ? 1.0f / (1.0f + d * inv_scale) : 0.0f;
-      v[0] = (bf16)c.x;
-      v[1] = (bf16)c.y;
-      v[2] = (bf16)c.z;
-      v[3] = (bf16)c.w;
-      v[4] = (bf16)code;
-    }
-    reinterpret_cast<bf16x8*>(sV)[p] = v;
-    const int ry = p / kE0 - 3, rx = p % kE0 - 3;
-    if (ry >= 0 && ry < kE1 && rx >= 0 && rx < kE1)
-      sX[ry * kE1 + rx] = make_float4(bf(v[0]), bf(v[1]), bf(v[2]), bf(v[3]));
+    for (int d = 0; d <= 2 * kReach; ++d) m |= nzf[ry * kE0 + cx + d];
+    rowany[e] = m;
   }
   __syncthreads();
+  bool empty = true;
+#pragma unroll
+  for (int d = 0; d <= 2 * kReach; ++d) empty &= rowany[(qy + d) * kTile + qx] == 0;
   fused_layer<8, kE0, 4, false>(sV, sU, wa, w1, wb, b0, ty0 - 3, tx0 - 3, H, W);
   __syncthreads();
   fused_layer<32, kE0 - 2, 4, false>(sU, sV, wb, w2, wc, b1, ty0 - 2, tx0 - 2, H, W);
@@ -501,10 +542,15 @@ fused_forward_kernel(
   fused_layer<32, kE0 - 6, 2, true>(sU, sV, wb, nullptr, wc, b3, ty0, tx0, H, W);
   __syncthreads();
   // pixel shuffle, bilinear residual and error head, one thread per pixel
-  const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
-  const int y = ty0 + qy, x = tx0 + qx;
   float zsum = 0.f;
-  if (y < H && x < W) {
+  if (y < H && x < W && empty) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {  // background, and no predicted error
+      const int64_t q = ((int64_t)n * 2 * H + 2 * y + (s >> 1)) * (2 * W) + 2 * x + (s & 1);
+      out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (err) err[q] = 0.f;
+    }
+  } else if (y < H && x < W) {
     const float* op = reinterpret_cast<const float*>(sV) + threadIdx.x * kUsed;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -532,14 +578,96 @@ fused_forward_kernel(
       zsum += z * z;
     }
   }
-  if (!mse_sum) return;
-  red[threadIdx.x] = (double)zsum;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  return zsum;
+}
+
+// LDS allows two workgroups per CU (two waves per SIMD): the register
+// budget is set for that, so a K-step's reads can all be in flight.
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
+fused_forward_kernel(
+    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
+    float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
+    const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
+    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
+    float4* __restrict__ out, float* __restrict__ err, SumArgs sums) {
+  // LDS (kFusedLds bytes): U, V, then x0's rgba (bf16-rounded) on the tile
+  // and a 1-pixel ring for the bilinear base of the last phase, then the
+  // reduction scratch
+  extern __shared__ float4 fused_smem[];
+  bf16* sU = reinterpret_cast<bf16*>(fused_smem);
+  bf16* sV = sU + kBufU;
+  float4* sX = reinterpret_cast<float4*>(sV + kBufV);
+  double* red = reinterpret_cast<double*>(sX + kE1 * kE1);
+  // nonzero flags of the x0 region, then their 9-wide row maxima (both in
+  // the reduction scratch, which is free until the last phase)
+  uint8_t* nzf = reinterpret_cast<uint8_t*>(red);
+  uint8_t* rowany = nzf + kE0 * kE0;
+  static_assert(kE0 * kE0 + kE0 * kTile <= 256 * 8, "flags fit the scratch");
+  const int n = blockIdx.z;
+  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+  bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
+  load_weights<8>(w0, wa);
+  // x0 on the tile and a 4-pixel halo (zero outside the image): every load
+  // is issued before any is used
+  constexpr int kPrep = (kE0 * kE0 + 255) / 256;
+  float4 pc[kPrep];
+  float pd[kPrep];
+#pragma unroll
+  for (int k = 0; k < kPrep; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
+    pc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    pd[k] = INFINITY;
+    if (p < kE0 * kE0 && y >= 0 && y < H && x >= 0 && x < W) {
+      const int64_t q = ((int64_t)n * H + y) * W + x;
+      pc[k] = rgba[q];
+      pd[k] = depth[q];
+    }
   }
-  if (threadIdx.x == 0) atomicAdd(mse_sum + n, red[0]);
+  bool any_nz = false;
+#pragma unroll
+  for (int k = 0; k < kPrep; ++k) {
+    const int p = threadIdx.x + 256 * k;
+    if (p >= kE0 * kE0) continue;
+    const int y = ty0 - 4 + p / kE0, x = tx0 - 4 + p % kE0;
+    bf16x8 v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = (bf16)0.0f;
+    if (y >= 0 && y < H && x >= 0 && x < W) {
+      const float4 c = pc[k];
+      const float d = pd[k];
+      const float code = isfinite(d) ? 1.0f / (1.0f + d * inv_scale) : 0.0f;
+      v[0] = (bf16)c.x;
+      v[1] = (bf16)c.y;
+      v[2] = (bf16)c.z;
+      v[3] = (bf16)c.w;
+      v[4] = (bf16)code;
+    }
+    reinterpret_cast<bf16x8*>(sV)[p] = v;
+    const bool nz = x0_nonzero(v);
+    nzf[p] = nz ? 1 : 0;
+    any_nz |= nz;
+    const int ry = p / kE0 - 3, rx = p % kE0 - 3;
+    if (ry >= 0 && ry < kE1 && rx >= 0 && rx < kE1)
+      sX[ry * kE1 + rx] = make_float4(bf(v[0]), bf(v[1]), bf(v[2]), bf(v[3]));
+  }
+  const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
+  const int y = ty0 + qy, x = tx0 + qx;
+  float zsum = 0.f;
+  if (!__syncthreads_or(any_nz)) {
+    // the whole region is empty: every pixel of the tile is background
+    if (y < H && x < W)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t q = ((int64_t)n * 2 * H + 2 * y + (s >> 1)) * (2 * W) + 2 * x + (s & 1);
+        out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (err) err[q] = 0.f;
+      }
+  } else {
+    zsum = fused_tile(sU, sV, sX, nzf, rowany, wa, wb, wc, w1, w2, w3, b0, b1, b2, b3, n, H, W,
+                      ty0, tx0, qy, qx, y, x, out, err);
+  }
+  if (sums.sum) tile_partial(sums, red, zsum);
 }
 
 // Training loss and its gradient with respect to o (bf16, 32 channels,
@@ -675,17 +803,13 @@ __global__ void zero_kernel(double* x, int64_t n) {
     x[i] = 0.0;
 }
 
-// The fallback decision on the device: the frame's predicted mean squared
-// error is the mean over its n images of sum_i / pixels; fallback = 1 when
-// the predicted PSNR (peak 1) is below threshold_db.
-__global__ void fallback_kernel(const double* sums, int n, double pixels, double threshold_db,
-                                int32_t* fallback) {
-  if (threadIdx.x != 0) return;
-  double m = 0.0;
-  for (int i = 0; i < n; ++i) m += sums[i] / pixels;
-  m /= (double)n;
-  const double psnr = m <= 0.0 ? INFINITY : 10.0 * log10(1.0 / m);
-  *fallback = psnr < threshold_db ? 1 : 0;
+// The layer-by-layer path's end of a launch (one workgroup, after the
+// epilogue has added the sums): the results and the decision.
+__global__ void finish_kernel(SumArgs a) {
+  for (int i = threadIdx.x; i < a.images; i += blockDim.x) a.result[i] = a.sum[i];
+  __syncthreads();
+  if (threadIdx.x == 0 && a.fallback)
+    *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
 }
 
 // Adam on the FP32 master weights.
@@ -745,7 +869,7 @@ struct sg_upsampler {
   bf16* gb = nullptr;
   float* part = nullptr;    // weight-gradient partial sums
   int part_blocks = 0;
-  double* acc = nullptr;    // device doubles: loss, per-image sums
+  double* acc = nullptr;    // device doubles: loss, partials or sums, per-image results
   int64_t acc_n = 0;
   bool packed = false;
   bool fused = true;        // inference through fused_forward_kernel
@@ -861,27 +985,33 @@ sg_status gradients(sg_upsampler* u, int n, int h, int w, const float* rgba, con
 }
 
 // Inference into out_rgba / out_err; with sums, the per-image sums of the
-// predicted squared error are left in acc[1 .. n].
+// predicted squared error end up in acc[1 + max_pixels ..] (and, with a
+// fallback flag, the frame's decision in *fallback), the sums themselves
+// cleared again for the next launch.
 sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
                 const float* depth, double depth_scale, float* out_rgba, float* out_err,
-                bool sums, hipStream_t s) {
+                bool sums, int32_t* fallback, double threshold_db, hipStream_t s) {
   sg_status st = check_batch(up, n, h, w, rgba, depth);
   if (st != SG_OK) return st;
   if (!out_rgba || !(std::isfinite(depth_scale) && depth_scale > 0.0))
     return fail(SG_ERR_INVALID_ARG, "sg_up_forward: NULL output or bad depth_scale");
   DeviceGuard guard(up->device);
   if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  SumArgs sa{};
   if (sums) {
-    hipLaunchKernelGGL(zero_kernel, dim3(blocks_of(n)), dim3(256), 0, s, up->acc + 1,
-                       (int64_t)n);
-    SG_HIP(hipGetLastError());
+    sa.sum = up->acc + 1;  // per-workgroup partials (fused) or per-image sums (layered)
+    sa.result = up->acc + 1 + up->max_pixels;
+    sa.fallback = fallback;
+    sa.images = n;
+    sa.pixels = 4.0 * (double)h * w;
+    sa.threshold_db = threshold_db;
   }
-  double* sum = sums ? up->acc + 1 : nullptr;
   if (up->fused && n <= 65535) {
     if (!up->packed && (st = pack_weights(up, s)) != SG_OK) return st;
     const float* b = up->params;
     const dim3 grid((unsigned)((w + kTile - 1) / kTile), (unsigned)((h + kTile - 1) / kTile),
                     (unsigned)n);
+    sa.tiles = (int32_t)(grid.x * grid.y);
     SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fused_forward_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds));
     hipLaunchKernelGGL(fused_forward_kernel, grid, dim3(256), kFusedLds, s,
@@ -892,13 +1022,17 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
                        reinterpret_cast<const bf16x8*>(up->fw[3]), b + layer_off(0) + 9 * 8 * kCh,
                        b + layer_off(1) + 9 * 32 * kCh, b + layer_off(2) + 9 * 32 * kCh,
                        b + layer_off(3) + 9 * 32 * kCh, reinterpret_cast<float4*>(out_rgba),
-                       out_err, sum);
+                       out_err, sa);
+    if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(256), 0, s, sa);
     SG_HIP(hipGetLastError());
   } else {
     if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
     const int64_t P = (int64_t)n * h * w;
+    if (sums)
+      hipLaunchKernelGGL(zero_kernel, dim3(blocks_of(n)), dim3(256), 0, s, sa.sum, (int64_t)n);
     hipLaunchKernelGGL(shuffle_kernel, dim3(blocks_of(P)), dim3(256), 0, s, up->o, up->x0, n, h,
-                       w, reinterpret_cast<float4*>(out_rgba), out_err, sum);
+                       w, reinterpret_cast<float4*>(out_rgba), out_err, sa.sum);
+    if (sums) hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, sa);
     SG_HIP(hipGetLastError());
   }
   return SG_OK;
@@ -920,7 +1054,9 @@ sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler** out) {
   u->device = device;
   u->max_pixels = max_pixels;
   u->part_blocks = 512;
-  u->acc_n = std::max<int64_t>(2, max_pixels + 1);
+  // loss, partials or sums [max_pixels] (a tile holds at least one pixel),
+  // results [max_pixels]
+  u->acc_n = 2 + 2 * max_pixels;
   bool ok = true;
   auto al = [&](void** p, int64_t bytes) {
     ok = ok && hipMalloc(p, (size_t)std::max<int64_t>(bytes, 16)) == hipSuccess;
@@ -947,7 +1083,9 @@ sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler** out) {
   }
   if (hipMemset(u->params, 0, kParams * 4) != hipSuccess ||
       hipMemset(u->m, 0, kParams * 4) != hipSuccess ||
-      hipMemset(u->v, 0, kParams * 4) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(u->v, 0, kParams * 4) != hipSuccess ||
+      hipMemset(u->acc, 0, (size_t)u->acc_n * 8) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     up_free(u);
     return fail(SG_ERR_DEVICE, "sg_up_create: initialisation failed");
   }
@@ -991,11 +1129,12 @@ sg_status sg_up_forward(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const
                         double* mse_pred, void* hip_stream) {
   hipStream_t s = (hipStream_t)hip_stream;
   sg_status st = infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err,
-                       mse_pred != nullptr, s);
+                       mse_pred != nullptr, nullptr, 0.0, s);
   if (st != SG_OK) return st;
   if (mse_pred) {
     DeviceGuard guard(up->device);
-    SG_HIP(hipMemcpyAsync(mse_pred, up->acc + 1, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    SG_HIP(hipMemcpyAsync(mse_pred, up->acc + 1 + up->max_pixels, sizeof(double) * n,
+                          hipMemcpyDeviceToHost, s));
     SG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < n; ++i) mse_pred[i] /= 4.0 * (double)h * w;
   }
@@ -1008,14 +1147,8 @@ sg_status sg_up_forward_flag(sg_upsampler* up, int32_t n, int32_t h, int32_t w,
                              int32_t* fallback, void* hip_stream) {
   if (!fallback || std::isnan(threshold_db))
     return fail(SG_ERR_INVALID_ARG, "sg_up_forward_flag: NULL flag or NaN threshold");
-  hipStream_t s = (hipStream_t)hip_stream;
-  sg_status st = infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err, true, s);
-  if (st != SG_OK) return st;
-  DeviceGuard guard(up->device);
-  hipLaunchKernelGGL(fallback_kernel, dim3(1), dim3(64), 0, s, up->acc + 1, n,
-                     4.0 * (double)h * w, threshold_db, fallback);
-  SG_HIP(hipGetLastError());
-  return SG_OK;
+  return infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err, true, fallback,
+               threshold_db, (hipStream_t)hip_stream);
 }
 
 sg_status sg_up_gradients(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,

@@ -288,9 +288,10 @@ def _views(views):
 
 
 def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
+    """params: a dict (see make_params) or a prebuilt sg_render_params."""
     n = len(views)
     varr = _views(views)
-    p = make_params(params)
+    p = params if isinstance(params, sg_render_params) else make_params(params)
     rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
     dep = None
     if out_depth is not None:
@@ -304,7 +305,7 @@ def sg_render_views_if(vol, views, params, out_rgba, enable, out_depth=None, str
     one-element tensor) is nonzero when the render runs."""
     n = len(views)
     varr = _views(views)
-    p = make_params(params)
+    p = params if isinstance(params, sg_render_params) else make_params(params)
     rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
     dep = None
     if out_depth is not None:

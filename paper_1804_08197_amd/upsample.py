@@ -103,6 +103,7 @@ class UpsampledPath:
         self.rgba_lo = torch.empty(n_views, h2, w2, 4, device="cuda")
         self.depth_lo = torch.empty(n_views, h2, w2, device="cuda")
         self.out = torch.empty(n_views, height, width, 4, device="cuda")
+        self._structs = None
 
     def predicted_psnr(self, views):
         """Half-resolution render and network pass; returns the predicted
@@ -126,11 +127,14 @@ class UpsampledPath:
         """The same frame with the decision taken on the device, without a
         host round trip: flag (one-element int32 device tensor) receives 1
         when the frame fell back. Asynchronous; returns the images."""
-        sg.sg_render_views(self.vol, [half_view(v) for v in views], self.p_half,
-                           list(self.rgba_lo), list(self.depth_lo))
+        if self._structs is None:  # built once: the per-frame calls only pack views
+            self._structs = (sg.make_params(self.p_half), sg.make_params(self.p_full),
+                             list(self.rgba_lo), list(self.depth_lo), list(self.out))
+        ph, pf, lo, dlo, out = self._structs
+        sg.sg_render_views(self.vol, [half_view(v) for v in views], ph, lo, dlo)
         self.model.forward_flag(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
                                 self.threshold_db, flag)
-        sg.sg_render_views_if(self.vol, views, self.p_full, list(self.out), flag)
+        sg.sg_render_views_if(self.vol, views, pf, out, flag)
         return self.out
 
 

@@ -312,3 +312,53 @@ def test_device_decided_path_equals_the_host_decided_path(lod):
     finally:
         u.close()
         sg.sg_volume_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(2, 45, 70), (1, 33, 17), (3, 40, 48)])
+def test_empty_neighbourhoods_yield_background(shape):
+    """Sparse inputs (empty tiles, partly empty tiles, ragged edges): the
+    fused kernel equals the layered path bit for bit, and the layered output
+    equals the FP64 reconstruction from its own buffers with the inference
+    rule (background where the 9x9 neighbourhood of x0 is empty)."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    n, h, w = shape
+    rng = np.random.default_rng(30 + h + w)
+    params = bf16_params(rng, 0.5)
+    rgba = np.zeros((n, h, w, 4), np.float32)
+    depth = np.full((n, h, w), np.inf, np.float32)
+    for i in range(n):
+        for _ in range(3):  # a few small patches of content
+            y0, x0_ = rng.integers(0, h), rng.integers(0, w)
+            sl = (i, slice(y0, min(h, y0 + 3)), slice(x0_, min(w, x0_ + 4)))
+            a = rng.uniform(0.2, 1.0, size=rgba[sl].shape[:-1] + (1,)).astype(np.float32)
+            rgba[sl] = np.concatenate([rng.uniform(0, 1, size=a.shape[:-1] + (3,)) * a, a], -1)
+            depth[sl] = rng.uniform(10, 300, size=depth[sl].shape)
+    trgba, tdepth = torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+    u = up.Upsampler(n * h * w)
+    try:
+        u.set_weights(up.pack(params))
+        res = []
+        for fused in (False, True):
+            u.set_fused(fused)
+            out = torch.full((n, 2 * h, 2 * w, 4), float("nan"), device="cuda")
+            err = torch.full((n, 2 * h, 2 * w), float("nan"), device="cuda")
+            mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True)
+            res.append((out.cpu().numpy(), err.cpu().numpy(), mse))
+            if not fused:
+                x0 = u.read_buffer(0, (n, h, w, 8), "bf16")
+                o = u.read_buffer(4, (n, h, w, 32), "f32")
+        (o0, e0, m0), (o1, e1, m1) = res
+        assert np.array_equal(o0, o1) and np.array_equal(e0, e1)
+        assert np.allclose(m0, m1, rtol=1e-12, atol=0)
+        empty = np.repeat(np.repeat(U.empty_neighbourhood(x0), 2, axis=1), 2, axis=2)
+        assert empty.any() and (~empty).any()
+        sh = U.pixel_shuffle(o)
+        ref = np.where(empty[..., None], 0.0, U.bilinear_up2(x0[..., :4]) + sh[..., :4])
+        assert np.abs(o0 - ref).max() <= 1e-5
+        assert np.array_equal(e0[empty], np.zeros(empty.sum(), np.float32))
+        assert np.allclose(e0[~empty], (sh[..., 4] ** 2)[~empty], rtol=1e-5, atol=1e-7)
+        log("%s: %.1f%% of output pixels background" % (shape, 100 * empty.mean()))
+    finally:
+        u.close()
