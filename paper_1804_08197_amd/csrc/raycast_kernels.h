@@ -415,8 +415,10 @@ __device__ __forceinline__ void mark_microblocks(const Ray& r, const RenderArgs&
 // Take sample r.k of the current segment under optical model MODEL;
 // `fetch(ch, ix, iy, iz, fx, fy, fz)` returns the trilinear value of
 // channel ch at stored index (ix, iy, iz) plus fraction. Returns false once
-// the ray has terminated (emission-absorption only).
-template <int MODEL, int CH, bool STATS, bool CLAMP = true, typename F>
+// the ray has terminated (emission-absorption only). DEPTH false: the caller
+// knows that the view asks for no depth (dalpha is +inf), so the depth
+// bookkeeping is left out.
+template <int MODEL, int CH, bool STATS, bool CLAMP = true, bool DEPTH = true, typename F>
 __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
                                             F&& fetch, int (*mb_key)[3]) {
   const int k = r.k;
@@ -490,7 +492,7 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   // depth: tau rises along the segment, so the first sample whose alpha
   // reached dalpha has the smallest tau (the depth itself, t0 + tau in FP64,
   // is formed once per segment by finish_depth)
-  r.dtau = fminf(r.dtau, r.A >= r.dalpha ? tau : INFINITY);
+  if (DEPTH) r.dtau = (r.A >= r.dalpha && tau < r.dtau) ? tau : r.dtau;
   if (r.A >= a.ert) {
     r.alive = false;
     return false;
@@ -800,6 +802,8 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     if (r.alive) next_segment<MODEL, CH>(r, a, V, true);
   }
   const int B = a.B, S = a.S, Sx = a.Sx;
+  // the wave's rays belong to one view: its depth request is wave-uniform
+  const bool depth_on = uniform(V.depth ? 1 : 0) != 0;
 
   while (true) {
     // --- the wave's next node: smallest front-to-back key among its rays
@@ -973,11 +977,19 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           const char* sb = reinterpret_cast<const char*>(stage - base_off);
           const int syb = sy_l * (int)sizeof(T), szb = sy_l * wy * (int)sizeof(T);
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            const int idx = __mul24(__mul24(iz, wy) + iy, sy_l) + ix;
-            return trilinear_bytes<T>(sb + (ch * cap + idx) * (int)sizeof(T), syb, szb, fx, fy,
+            // stencil corner in bytes: every term below 2^23 (24-bit products)
+            const int off = __mul24(iz, szb) + __mul24(iy, syb) + ix * (int)sizeof(T);
+            return trilinear_bytes<T>(sb + ch * cap * (int)sizeof(T) + off, syb, szb, fx, fy,
                                       fz);
           };
-          while (r.k <= kb && sample_once<MODEL, CH, STATS, false>(r, a, s_tf, fetch, mb_key)) {
+          if (depth_on) {
+            while (r.k <= kb &&
+                   sample_once<MODEL, CH, STATS, false, true>(r, a, s_tf, fetch, mb_key)) {
+            }
+          } else {
+            while (r.k <= kb &&
+                   sample_once<MODEL, CH, STATS, false, false>(r, a, s_tf, fetch, mb_key)) {
+            }
           }
         }
         wave_sync();
