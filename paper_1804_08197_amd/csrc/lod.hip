@@ -101,32 +101,34 @@ __device__ __forceinline__ bool node_suits(const CutGeom& g, const double e[3],
   return (s * s) <= (K * d2);
 }
 
-__global__ void cutmap_kernel(CutGeom g, ViewDev* views, int n_views, int32_t* cutmap,
-                              InlineViews iv) {
+// Grid: x strides over the level-0 cells, y is the view (so the view's
+// record is read once per workgroup, from the arguments when inline).
+__global__ void cutmap_kernel(CutGeom g, ViewDev* views, int32_t* cutmap, InlineViews iv) {
   if (g.enable && *g.enable == 0) return;
-  if (iv.n && blockIdx.x == 0) {
+  const int v = (int)blockIdx.y;
+  if (iv.n && blockIdx.x == 0 && v == 0) {
     // the small view table, from the arguments into the device table
     const uint32_t* src = reinterpret_cast<const uint32_t*>(iv.v);
     uint32_t* dst = reinterpret_cast<uint32_t*>(views);
     const int words = iv.n * (int)(sizeof(ViewDev) / 4);
     for (int k = threadIdx.x; k < words; k += blockDim.x) dst[k] = src[k];
   }
-  const int64_t total = (int64_t)n_views * g.cells;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t v = i / g.cells, cell = i - v * g.cells;
-    const ViewDev& V = iv.n ? iv.v[v] : views[v];
+  const ViewDev& V = iv.n ? iv.v[v] : views[v];
+  const double e[3] = {V.e[0], V.e[1], V.e[2]};
+  const double K = V.K;
+  int32_t* out = cutmap + V.cut_off;
+  for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < g.cells;
+       cell += (int64_t)gridDim.x * blockDim.x) {
     int32_t cx = (int32_t)(cell % g.grid[0][0]);
     int32_t cy = (int32_t)((cell / g.grid[0][0]) % g.grid[0][1]);
     int32_t cz = (int32_t)(cell / ((int64_t)g.grid[0][0] * g.grid[0][1]));
-    double e[3] = {V.e[0], V.e[1], V.e[2]};
     int L = (g.lod || g.cache) ? g.top : g.bias;
     for (; L > g.bias; --L) {
-      if (g.lod && node_suits(g, e, V.K, L, cx >> L, cy >> L, cz >> L)) break;
+      if (g.lod && node_suits(g, e, K, L, cx >> L, cy >> L, cz >> L)) break;
       if (g.cache && !children_resident(g, L, cx >> L, cy >> L, cz >> L)) break;
     }
     const int64_t node = node_index(g, L, cx >> L, cy >> L, cz >> L);
-    cutmap[V.cut_off + cell] = (int32_t)node;
+    out[cell] = (int32_t)node;
   }
 }
 
@@ -168,10 +170,9 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
                         const int32_t* enable, const InlineViews* iv) {
   CutGeom g = cut_geom(v, bias, lod, timepoint);
   g.enable = enable;
-  int64_t total = (int64_t)n_views * g.cells;
-  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  const int64_t blocks = std::min<int64_t>((g.cells + 255) / 256, 4096);
   out->func = reinterpret_cast<const void*>(cutmap_kernel);
-  out->grid = dim3((unsigned)std::max<int64_t>(blocks, 1));
+  out->grid = dim3((unsigned)std::max<int64_t>(blocks, 1), (unsigned)std::max(n_views, 1));
   out->block = dim3(256);
   out->lds = 0;
   out->arg.clear();
@@ -179,7 +180,6 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
   if (iv && iv->n) inl = *iv;
   out->push(g);
   out->push(const_cast<ViewDev*>(dviews));
-  out->push(n_views);
   out->push(cutmap);
   out->push(inl);
   return SG_OK;

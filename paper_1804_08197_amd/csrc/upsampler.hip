@@ -479,23 +479,39 @@ __device__ __forceinline__ int32_t decide(const double* result, int n, double pi
   return psnr < threshold_db ? 1 : 0;
 }
 
-// One workgroup: result[i] = the partials of image i added in a fixed order.
-__global__ __launch_bounds__(256) void tile_sum_kernel(SumArgs a) {
-  __shared__ double red[256];
+// One workgroup of kSumThreads: result[i] = the partials of image i added
+// in a fixed order (deterministic): thread t adds partials t, t + kSumThreads,
+// ... (loaded four at a time so the loads are in flight together), then the
+// 64 lanes of each wave fold by xor-shuffles and wave 0 adds the waves' sums.
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void tile_sum_kernel(SumArgs a) {
+  __shared__ double red[kSumThreads / 64];
+  const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int i = 0; i < a.images; ++i) {
+    const double* p = a.sum + (int64_t)i * a.tiles;
     double v = 0.0;
-    for (int t = threadIdx.x; t < a.tiles; t += 256) v += a.sum[(int64_t)i * a.tiles + t];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
+    for (int base = 0; base < a.tiles; base += 4 * kSumThreads) {
+      double x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = base + j * kSumThreads + t;
+        x[j] = k < a.tiles ? p[k] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v += x[j];
     }
-    if (threadIdx.x == 0) a.result[i] = red[0];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (t == 0) {
+      double r = 0.0;
+      for (int w = 0; w < kSumThreads / 64; ++w) r += red[w];
+      a.result[i] = r;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && a.fallback)
-    *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
+  if (t == 0 && a.fallback) *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
 }
 
 // the workgroup's share of the predicted error, into its partial slot
@@ -1023,7 +1039,7 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
                        b + layer_off(1) + 9 * 32 * kCh, b + layer_off(2) + 9 * 32 * kCh,
                        b + layer_off(3) + 9 * 32 * kCh, reinterpret_cast<float4*>(out_rgba),
                        out_err, sa);
-    if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(256), 0, s, sa);
+    if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sa);
     SG_HIP(hipGetLastError());
   } else {
     if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
