@@ -671,7 +671,8 @@ fused_forward_kernel(
   const int y = ty0 + qy, x = tx0 + qx;
   float zsum = 0.f;
   if (!__syncthreads_or(any_nz)) {
-    // the whole region is empty: every pixel of the tile is background
+    // the whole region is empty: every pixel of the tile is background, and
+    // the tile's partial sum is zero
     if (y < H && x < W)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -679,10 +680,12 @@ fused_forward_kernel(
         out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (err) err[q] = 0.f;
       }
-  } else {
-    zsum = fused_tile(sU, sV, sX, nzf, rowany, wa, wb, wc, w1, w2, w3, b0, b1, b2, b3, n, H, W,
-                      ty0, tx0, qy, qx, y, x, out, err);
+    if (sums.sum && threadIdx.x == 0)
+      sums.sum[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = 0.0;
+    return;
   }
+  zsum = fused_tile(sU, sV, sX, nzf, rowany, wa, wb, wc, w1, w2, w3, b0, b1, b2, b3, n, H, W,
+                    ty0, tx0, qy, qx, y, x, out, err);
   if (sums.sum) tile_partial(sums, red, zsum);
 }
 
