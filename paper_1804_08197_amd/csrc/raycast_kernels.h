@@ -55,15 +55,6 @@ namespace sg {
 
 namespace {
 
-// 1 - exp(-x) for x >= 0 with small absolute and relative error: a Taylor
-// polynomial below 1/16 (avoids the cancellation of 1 - exp(-x); truncation
-// error below x^5/120 < 1e-8), the exponential above.
-__device__ __forceinline__ float one_minus_exp_neg(float x) {
-  const float p = x * fmaf(-x, fmaf(-x, fmaf(-x, 0.041666668f, 0.16666667f), 0.5f), 1.0f);
-  float q = 1.0f - __expf(-x);
-  return x < 0.0625f ? p : q;
-}
-
 __device__ __forceinline__ float lerpf(float a, float b, float t) {
   return fmaf(t, b - a, a);
 }
@@ -143,7 +134,8 @@ struct Ray {
   float tau, tau_last;  // ray parameter of sample k and of the last sample
   int n, k;
   // accumulation
-  float Cr, Cg, Cb, A, depth;
+  // accumulation: premultiplied colour and the transmittance T = 1 - alpha
+  float Cr, Cg, Cb, T, depth;
   // depth: the smallest ray parameter in the current segment whose alpha
   // reached dalpha (+inf: none yet, or no depth wanted), converted to the
   // depth once, when the segment ends
@@ -175,7 +167,8 @@ __device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const Vie
   const double len = sqrt((w3[0] * w3[0] + w3[1] * w3[1]) + w3[2] * w3[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) r.d[i] = w3[i] / len;
-  r.Cr = r.Cg = r.Cb = r.A = 0.f;
+  r.Cr = r.Cg = r.Cb = 0.f;
+  r.T = 1.f;
 #pragma unroll
   for (int c = 0; c < kMaxChannels; ++c) r.vmax[c] = -INFINITY;
   r.sampled = false;
@@ -483,17 +476,21 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
     eg *= inv_r;
     eb *= inv_r;
   }
-  const float al = one_minus_exp_neg(rho * s);
-  const float wgt = (1.0f - r.A) * al;
+  // over-compositing in transmittance form: the sample's opacity is
+  // 1 - exp(-rho s) and its weight (1 - A) times that, i.e. T - T exp(-rho s)
+  // with T = 1 - A (the same recurrence; exp(-rho s) = 2^(-rho s log2 e))
+  const float tn = r.T * __builtin_amdgcn_exp2f((rho * s) * -1.44269504f);
+  const float wgt = r.T - tn;
   r.Cr = fmaf(wgt, er, r.Cr);
   r.Cg = fmaf(wgt, eg, r.Cg);
   r.Cb = fmaf(wgt, eb, r.Cb);
-  r.A += wgt;
+  r.T = tn;
+  const float A = 1.0f - tn;
   // depth: tau rises along the segment, so the first sample whose alpha
   // reached dalpha has the smallest tau (the depth itself, t0 + tau in FP64,
   // is formed once per segment by finish_depth)
-  if (DEPTH) r.dtau = (r.A >= r.dalpha && tau < r.dtau) ? tau : r.dtau;
-  if (r.A >= a.ert) {
+  if (DEPTH) r.dtau = (A >= r.dalpha && tau < r.dtau) ? tau : r.dtau;
+  if (A >= a.ert) {
     r.alive = false;
     return false;
   }
@@ -527,13 +524,13 @@ __device__ __forceinline__ void write_pixel(Ray& r, const RenderArgs& a, const V
       r.Cb += c.z;
     }
   }
-  const float omA = 1.0f - r.A;
+  const float omA = r.T;
   const int64_t pix = (int64_t)py * V.W + px;
   float4 out;
   out.x = fmaf(omA, a.bg[0], r.Cr);
   out.y = fmaf(omA, a.bg[1], r.Cg);
   out.z = fmaf(omA, a.bg[2], r.Cb);
-  out.w = fmaf(omA, a.bg[3], r.A);
+  out.w = fmaf(omA, a.bg[3], 1.0f - r.T);
   reinterpret_cast<float4*>(V.rgba)[pix] = out;
   if (V.depth) V.depth[pix] = r.depth;
 }
@@ -791,7 +788,8 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
   for (int ch = 0; ch < CH; ++ch) mb_key[ch][0] = mb_key[ch][1] = mb_key[ch][2] = -1;
   Ray r;
   r.alive = false;
-  r.Cr = r.Cg = r.Cb = r.A = 0.f;
+  r.Cr = r.Cg = r.Cb = 0.f;
+  r.T = 1.f;
   r.depth = INFINITY;
   r.dtau = INFINITY;
   r.dalpha = V.depth ? a.depth_alpha : INFINITY;
