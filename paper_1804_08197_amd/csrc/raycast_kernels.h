@@ -405,19 +405,17 @@ __device__ __forceinline__ void mark_microblocks(const Ray& r, const RenderArgs&
       }
 }
 
-// Take sample r.k of the current segment under optical model MODEL;
-// `fetch(ch, ix, iy, iz, fx, fy, fz)` returns the trilinear value of
-// channel ch at stored index (ix, iy, iz) plus fraction. Returns false once
-// the ray has terminated (emission-absorption only). DEPTH false: the caller
-// knows that the view asks for no depth (dalpha is +inf), so the depth
-// bookkeeping is left out.
-template <int MODEL, int CH, bool STATS, bool CLAMP = true, bool DEPTH = true, typename F>
-__device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
-                                            F&& fetch, int (*mb_key)[3]) {
-  const int k = r.k;
-  const bool last = k == r.n - 1;
-  const float s = last ? r.s_last : r.Df;
-  const float tau = last ? r.tau_last : r.tau;  // = sample_tau(r, k)
+// Emission and extinction of the sample at ray parameter tau (from the
+// segment start) of the emission-absorption model: the trilinear value of
+// every channel, its table entry, channels added (extinction-weighted
+// colour); `fetch(ch, ix, iy, iz, fx, fy, fz)` returns the trilinear value
+// of channel ch at stored index (ix, iy, iz) plus fraction.
+struct Shade {
+  float rho, er, eg, eb;
+};
+template <int CH, bool STATS, bool CLAMP, typename F>
+__device__ __forceinline__ Shade shade_ea(const Ray& r, const RenderArgs& a, const float4* s_tf,
+                                          F&& fetch, float tau, int (*mb_key)[3]) {
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
@@ -431,59 +429,44 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
   // q >= 0, so fract(q) = q - floor(q) = q - ix (exact)
   const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
               fz = __builtin_amdgcn_fractf(qz);
-  float rho = 0.f, er = 0.f, eg = 0.f, eb = 0.f;
+  Shade z{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) {
     const float val = fetch(ch, ix, iy, iz, fx, fy, fz);
     if (STATS) mark_microblocks(r, a, ch, ix, iy, iz, mb_key[ch]);
-    if (MODEL == kModelMip) {
-      r.vmax[ch] = fmaxf(r.vmax[ch], val);
-      continue;
-    }
     const float4 c = tf_lookup(a, s_tf, ch, val);
     if (CH == 1) {
-      er = c.x;
-      eg = c.y;
-      eb = c.z;
-      rho = c.w;
-    } else if (MODEL == kModelEmission) {
-      er += c.x;
-      eg += c.y;
-      eb += c.z;
+      z = Shade{c.w, c.x, c.y, c.z};
     } else {
-      rho += c.w;
-      er = fmaf(c.w, c.x, er);
-      eg = fmaf(c.w, c.y, eg);
-      eb = fmaf(c.w, c.z, eb);
+      z.rho += c.w;
+      z.er = fmaf(c.w, c.x, z.er);
+      z.eg = fmaf(c.w, c.y, z.eg);
+      z.eb = fmaf(c.w, c.z, z.eb);
     }
   }
-  r.k = k + 1;
-  r.tau += r.Df;
-  if (STATS) ++r.nsamp;
-  if (MODEL == kModelMip) {
-    r.sampled = true;
-    return true;
-  }
-  if (MODEL == kModelEmission) {
-    r.Cr = fmaf(er, s, r.Cr);
-    r.Cg = fmaf(eg, s, r.Cg);
-    r.Cb = fmaf(eb, s, r.Cb);
-    return true;
-  }
   if (CH > 1) {
-    const float inv_r = rho > 0.f ? 1.0f / rho : 0.f;
-    er *= inv_r;
-    eg *= inv_r;
-    eb *= inv_r;
+    const float inv_r = z.rho > 0.f ? 1.0f / z.rho : 0.f;
+    z.er *= inv_r;
+    z.eg *= inv_r;
+    z.eb *= inv_r;
   }
-  // over-compositing in transmittance form: the sample's opacity is
-  // 1 - exp(-rho s) and its weight (1 - A) times that, i.e. T - T exp(-rho s)
-  // with T = 1 - A (the same recurrence; exp(-rho s) = 2^(-rho s log2 e))
-  const float tn = r.T * __builtin_amdgcn_exp2f((rho * s) * -1.44269504f);
+  return z;
+}
+
+// Over-compositing of one emission-absorption sample of length s at ray
+// parameter tau, in transmittance form: the sample's opacity is
+// 1 - exp(-rho s) and its weight (1 - A) times that, i.e. T - T exp(-rho s)
+// with T = 1 - A (the same recurrence; exp(-rho s) = 2^(-rho s log2 e)).
+// Returns false once the ray has terminated. DEPTH false: the view asks for
+// no depth (dalpha is +inf), so the depth bookkeeping is left out.
+template <bool DEPTH>
+__device__ __forceinline__ bool composite_ea(Ray& r, const RenderArgs& a, const Shade& z,
+                                             float s, float tau) {
+  const float tn = r.T * __builtin_amdgcn_exp2f((z.rho * s) * -1.44269504f);
   const float wgt = r.T - tn;
-  r.Cr = fmaf(wgt, er, r.Cr);
-  r.Cg = fmaf(wgt, eg, r.Cg);
-  r.Cb = fmaf(wgt, eb, r.Cb);
+  r.Cr = fmaf(wgt, z.er, r.Cr);
+  r.Cg = fmaf(wgt, z.eg, r.Cg);
+  r.Cb = fmaf(wgt, z.eb, r.Cb);
   r.T = tn;
   const float A = 1.0f - tn;
   // depth: tau rises along the segment, so the first sample whose alpha
@@ -494,6 +477,59 @@ __device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const f
     r.alive = false;
     return false;
   }
+  return true;
+}
+
+// Take sample r.k of the current segment under optical model MODEL (see
+// shade_ea for `fetch`). Returns false once the ray has terminated
+// (emission-absorption only).
+template <int MODEL, int CH, bool STATS, bool CLAMP = true, bool DEPTH = true, typename F>
+__device__ __forceinline__ bool sample_once(Ray& r, const RenderArgs& a, const float4* s_tf,
+                                            F&& fetch, int (*mb_key)[3]) {
+  const int k = r.k;
+  const bool last = k == r.n - 1;
+  const float s = last ? r.s_last : r.Df;
+  const float tau = last ? r.tau_last : r.tau;  // = sample_tau(r, k)
+  if (MODEL != kModelEmission && MODEL != kModelMip) {
+    const Shade z = shade_ea<CH, STATS, CLAMP>(r, a, s_tf, fetch, tau, mb_key);
+    r.k = k + 1;
+    r.tau += r.Df;
+    if (STATS) ++r.nsamp;
+    return composite_ea<DEPTH>(r, a, z, s, tau);
+  }
+  const float qx = fmaf(tau, r.dq[0], r.q0[0]);
+  const float qy = fmaf(tau, r.dq[1], r.q0[1]);
+  const float qz = fmaf(tau, r.dq[2], r.q0[2]);
+  const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
+  const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
+  const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
+  const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
+              fz = __builtin_amdgcn_fractf(qz);
+  float er = 0.f, eg = 0.f, eb = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    const float val = fetch(ch, ix, iy, iz, fx, fy, fz);
+    if (STATS) mark_microblocks(r, a, ch, ix, iy, iz, mb_key[ch]);
+    if (MODEL == kModelMip) {
+      r.vmax[ch] = fmaxf(r.vmax[ch], val);
+      continue;
+    }
+    const float4 c = tf_lookup(a, s_tf, ch, val);
+    er += c.x;
+    eg += c.y;
+    eb += c.z;
+  }
+  r.k = k + 1;
+  r.tau += r.Df;
+  if (STATS) ++r.nsamp;
+  if (MODEL == kModelMip) {
+    r.sampled = true;
+    return true;
+  }
+  // emission only
+  r.Cr = fmaf(er, s, r.Cr);
+  r.Cg = fmaf(eg, s, r.Cg);
+  r.Cb = fmaf(eb, s, r.Cb);
   return true;
 }
 
