@@ -174,6 +174,13 @@ def main():
     samples = stats["total_samples"]
     mb = stats["microblocks"]
     log("samples/frame %d, microblocks %d" % (samples, mb))
+    # brick-granular bytes: the non-empty nodes of both views' cuts (the
+    # bricks the frame may read, whole, core plus apron)
+    cut = set()
+    for v in views:
+        nodes, empty = sg.sg_get_lod_cut(h, v, PARAMS)
+        cut |= set(nodes[~empty].tolist())
+    brick_bytes = len(cut) * (B + 2) ** 3 * 2
 
     for _ in range(args.warmup):
         sg.sg_render_views(h, views, PARAMS, outs)
@@ -224,7 +231,8 @@ def main():
            "step_ms_median": float(np.median(step_ms)),
            "step_ms_p10": float(np.percentile(step_ms, 10)),
            "step_ms_p90": float(np.percentile(step_ms, 90)),
-           "microblocks_per_frame": mb, "roofline": roof, "roofline_other": other,
+           "microblocks_per_frame": mb, "brick_bytes_per_frame": brick_bytes,
+           "cut_nonempty_nodes": len(cut), "roofline": roof, "roofline_other": other,
            "launch": launch, "setup_ms": setup}
 
     if want_cpu:
