@@ -843,8 +843,19 @@ def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
             done_samp += r["total_samples"]
         n = min(n * 2, 8192)
     frame_s = spent / done_pix * npix
+    # the same oracle on one thread, on 4,096 further random pixels per eye
+    one_pix, one_samp, one_s = 0, 0, 0.0
+    for i, v in enumerate(views):
+        pix = np.stack([rng.integers(0, v["width"], 4096), rng.integers(0, v["height"], 4096)], 1)
+        t = time.perf_counter()
+        r = sc.render(v, PARAMS, pixels=pix, cut=cuts[i], empty=emps[i], threads=1)
+        one_s += time.perf_counter() - t
+        one_pix += len(pix)
+        one_samp += r["total_samples"]
     return {"value": 1.0 / frame_s, "unit": "stereo frames/s", "cores": threads,
             "kind": "oracle", "samples_per_s": done_samp / spent,
+            "single_thread": {"value": one_pix / (one_s * npix), "unit": "stereo frames/s",
+                              "samples_per_s": one_samp / one_s, "pixels": one_pix},
             "sample": "%d uniformly random pixels of both eyes (%.1f%% of the frame's pixel "
                       "count), %.1fs of wall time on %d threads, extrapolated to the frame by "
                       "pixel count" % (done_pix, 100.0 * done_pix / npix, spent, threads)}
