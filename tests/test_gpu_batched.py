@@ -232,3 +232,24 @@ def test_render_if_follows_the_device_flag(blobs, launch):
             sg.sg_render_views_if(h, vs, p, ref, None)
     finally:
         sg.sg_set_launch_config(h, None)
+
+
+def test_small_calls_carry_their_views_inline_with_the_same_images(blobs):
+    """Up to four views travel in the cut-map kernel's arguments, larger
+    calls through a staged device table: both give the same images, and
+    alternating the two routes leaves no stale view records behind."""
+    h, vol, tf = blobs
+    views = uneven_views(n=7)
+    params = {"step": 0.5, "ert": ERT, "tau": 1.0, "lod": 1, "skip_empty": 1, "bias": 0}
+    big = render(h, views, params)  # 9 views: staged table
+    for n in (1, 2, 4):
+        small = render(h, views[:n], params)  # inline records
+        for i in range(n):
+            assert np.array_equal(small[i].cpu().numpy(), big[i].cpu().numpy()), (n, i)
+    # a staged call after inline ones, then an inline call of other views
+    again = render(h, views, params)
+    for i in range(len(views)):
+        assert np.array_equal(again[i].cpu().numpy(), big[i].cpu().numpy()), i
+    tail = render(h, views[5:9], params)
+    for i in range(4):
+        assert np.array_equal(tail[i].cpu().numpy(), big[5 + i].cpu().numpy()), i
