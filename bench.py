@@ -95,7 +95,7 @@ def main():
         copy_calibration(args.copy_bytes)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (multi-GPU sort-last compositing is "
+        print("bench.py: the renderer runs on one GPU only (multi-GPU sort-last compositing is "
               "a design, not an implementation); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -46,7 +46,7 @@ typedef enum {
   SG_ERR_OUT_OF_MEMORY = -2, /* device allocation failed (e.g. pool > HBM)   */
   SG_ERR_DEVICE = -3,        /* no device, or a HIP runtime call failed        */
   SG_ERR_STATE = -4,         /* call not valid now (e.g. no transfer function) */
-  SG_ERR_UNSUPPORTED = -5    /* valid request this build does not implement   */
+  SG_ERR_UNSUPPORTED = -5    /* valid request the library does not implement  */
 } sg_status;
 
 typedef enum { SG_U8 = 1, SG_U16 = 2 } sg_dtype;
