@@ -72,7 +72,7 @@ def main():
                     help="explicit launch configuration kernel,tile,block,stage_bytes,persistent "
                          "(no autotuning); profiles use the one the benchmark chose")
     ap.add_argument("--workload", default="tubes",
-                    choices=("tubes", "batched64", "upsampler", "stream", "hmd"),
+                    choices=("tubes", "batched64", "upsampler", "stream", "hmd", "octants"),
                     help="tubes: the bricked stereo frame (default, the headline); "
                          "batched64: 64 uneven views of the 128^3 blob volume in one call; "
                          "upsampler: learned-upsampler path vs plain path on the blob scene; "
@@ -113,6 +113,9 @@ def main():
         return
     if args.workload == "hmd":
         bench_hmd(args)
+        return
+    if args.workload == "octants":
+        bench_octants(args)
         return
 
     import gen
@@ -619,6 +622,73 @@ def bench_hmd(args):
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_hmd_variants",
                       "variants": list(res)},
            "variants": res, "launch": launch, "roofline": alu}
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def bench_octants(args):
+    """One GPU's share of a sort-last split of the bricked stereo frame: each
+    of the eight 1024^3 octants of the tubes volume rendered alone for both
+    eyes (the region of interest clips every ray to the octant, so a GPU
+    that owned only that octant's bricks would run the same kernel on the
+    same samples), timed with HIP events around the ray-casting kernel, in
+    the launch the autotuner picks for the whole frame. With eight GPUs the
+    frame takes as long as the slowest octant plus the composite, so the
+    headline figure is 1 / (slowest octant). One step = every octant once."""
+    import torch
+
+    import gen
+    from gen.large import TubeVolume, upload_generated
+    from paper_1804_08197_amd import sg
+    dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
+    tv = TubeVolume().to_device()
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
+    sg.sg_build_lod(h, 0, 0)
+    sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
+    sg.sg_volume_commit(h)
+    views = workload_views()
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+    half = [d // 2 for d in dims]
+    res = {}
+    for o in range(9):
+        if o < 8:
+            lo = [half[a] * ((o >> a) & 1) for a in range(3)]
+            name = "octant_%d%d%d" % tuple((o >> a) & 1 for a in range(3))
+            p = dict(PARAMS, roi=tuple(lo) + tuple(l + h_ for l, h_ in zip(lo, half)))
+        else:
+            name, p = "whole_frame", dict(PARAMS)
+        st = sg.sg_render_views_stats(h, views, p, outs)
+        for _ in range(args.warmup):
+            sg.sg_render_views(h, views, p, outs)
+        torch.cuda.synchronize()
+        sg.sg_set_kernel_timing(h, True)
+        for _ in range(args.steps):
+            sg.sg_render_views(h, views, p, outs)
+        n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+        sg.sg_set_kernel_timing(h, False)
+        res[name] = {"raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
+                     "samples": st["total_samples"]}
+        log("%s: %.3f ms, %d samples" % (name, ray_ms / n_k, st["total_samples"]))
+    octs = {k: v for k, v in res.items() if k.startswith("octant")}
+    slow = max(octs, key=lambda k: octs[k]["raycast_kernel_ms"])
+    slow_ms = octs[slow]["raycast_kernel_ms"] + octs[slow]["cutmap_kernel_ms"]
+    step_ms = sum(v["raycast_kernel_ms"] + v["cutmap_kernel_ms"] for v in octs.values())
+    alu = {"bound": "alu",
+           "achieved": octs[slow]["samples"] * FLOP_PER_SAMPLE
+           / (octs[slow]["raycast_kernel_ms"] * 1e-3) / 1e12,
+           "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "traffic": None}
+    alu["frac"] = alu["achieved"] / alu["peak"]
+    out = {"metric": "stereo frames/s of one GPU's octant share (slowest of eight)",
+           "value": 1e3 / slow_ms, "unit": "stereo frames/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+           "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_octant_share",
+                      "octant": "1024^3", "slowest": slow},
+           "octants": res, "samples_octants_sum": sum(v["samples"] for v in octs.values()),
+           "launch": launch, "roofline": alu}
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
 
