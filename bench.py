@@ -650,15 +650,20 @@ def bench_octants(args):
     views = workload_views()
     outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
     launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+    del outs
     half = [d // 2 for d in dims]
-    res = {}
+    res, boxes, parts = {}, [], []
     for o in range(9):
         if o < 8:
             lo = [half[a] * ((o >> a) & 1) for a in range(3)]
             name = "octant_%d%d%d" % tuple((o >> a) & 1 for a in range(3))
-            p = dict(PARAMS, roi=tuple(lo) + tuple(l + h_ for l, h_ in zip(lo, half)))
+            boxes.append(tuple(lo) + tuple(l + h_ for l, h_ in zip(lo, half)))
+            p = dict(PARAMS, roi=boxes[-1])
+            outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+            parts.append(outs)
         else:
             name, p = "whole_frame", dict(PARAMS)
+            outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
         st = sg.sg_render_views_stats(h, views, p, outs)
         for _ in range(args.warmup):
             sg.sg_render_views(h, views, p, outs)
@@ -671,6 +676,23 @@ def bench_octants(args):
         res[name] = {"raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
                      "samples": st["total_samples"]}
         log("%s: %.3f ms, %d samples" % (name, ray_ms / n_k, st["total_samples"]))
+    # the local composite of all eight parts of both eyes (sg_composite_over);
+    # each part terminates its rays on its own opacity, so the composite
+    # differs from the whole frame where early termination cut the whole
+    # render short (by at most 1 - ert)
+    comp = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for it in range(args.warmup + args.steps):
+        if it == args.warmup:
+            ev[0].record()
+        for i, v in enumerate(views):
+            sg.sg_composite_over(v, [pp[i] for pp in parts], boxes, comp[i])
+    ev[1].record()
+    torch.cuda.synchronize()
+    comp_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    comp_err = max(float((comp[i] - outs[i]).abs().max()) for i in range(len(views)))
+    log("composite of 8 parts, both eyes: %.3f ms, max diff to the whole frame %.2e" % (
+        comp_ms, comp_err))
     octs = {k: v for k, v in res.items() if k.startswith("octant")}
     slow = max(octs, key=lambda k: octs[k]["raycast_kernel_ms"])
     slow_ms = octs[slow]["raycast_kernel_ms"] + octs[slow]["cutmap_kernel_ms"]
@@ -688,6 +710,7 @@ def bench_octants(args):
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_octant_share",
                       "octant": "1024^3", "slowest": slow},
            "octants": res, "samples_octants_sum": sum(v["samples"] for v in octs.values()),
+           "composite_ms_all_parts": comp_ms, "composite_max_diff_to_whole": comp_err,
            "launch": launch, "roofline": alu}
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)

@@ -241,6 +241,24 @@ sg_status sg_render_views_if(sg_volume *vol, int32_t n_views, const sg_view *vie
                              float *const *out_depth, const int32_t *enable,
                              void *hip_stream);
 
+/* Sort-last compositing of one view's part images (Sec 5.1: the over
+ * operator is associative, so renders of disjoint parts of the volume
+ * combine): parts[k] is the premultiplied RGBA image (float4 per pixel,
+ * row-major, view->width x view->height, device memory, 16-byte aligned) of
+ * the render of box k alone, rendered on a zero background with the region
+ * of interest set to that box; boxes holds 6 host doubles per part (lo x, y,
+ * z, hi x, y, z; level-0 voxel units; the boxes must not overlap). Per
+ * pixel the parts whose box the pixel's ray crosses are combined front over
+ * back in the order the ray enters the boxes, C = sum_k (prod_{j<k} (1 -
+ * A_j)) C_k and A likewise, into out_rgba (same layout; may not alias a
+ * part). 1 <= n_parts <= 8. The ray of each pixel is the renderer's (same
+ * FP64 arithmetic, lens included). Errors: SG_ERR_INVALID_ARG for NULL or
+ * misaligned pointers, a bad view, n_parts out of range, non-finite or empty
+ * boxes. Asynchronous on hip_stream; runs on the current device. */
+sg_status sg_composite_over(const sg_view *view, int32_t n_parts,
+                            const float *const *parts, const double *boxes,
+                            float *out_rgba, void *hip_stream);
+
 /* Same render with instrumentation (per-pixel sample counts, total samples,
  * distinct micro-blocks read). Synchronises hip_stream before returning so
  * that the host counters are valid. Slower; for tests and measurement. */

@@ -202,6 +202,40 @@ sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out) {
   return SG_OK;
 }
 
+sg_status view_geometry(const sg_view& w, ViewDev* out) {
+  for (int k = 0; k < 16; ++k)
+    if (!finite(w.cam_to_world[k])) return fail(SG_ERR_INVALID_ARG, "camera matrix not finite");
+  if (!(finite(w.tan_left) && finite(w.tan_right) && finite(w.tan_bottom) &&
+        finite(w.tan_top) && w.tan_left < w.tan_right && w.tan_bottom < w.tan_top))
+    return fail(SG_ERR_INVALID_ARG, "view tangents must be finite with left<right, bottom<top");
+  if (w.width < 1 || w.height < 1 || w.width > 32768 || w.height > 32768)
+    return fail(SG_ERR_INVALID_ARG, "view size must be in [1, 32768]");
+  for (int k = 0; k < 4; ++k)
+    if (!finite(w.lens[k])) return fail(SG_ERR_INVALID_ARG, "lens coefficients not finite");
+  if (w.ray_limit && reinterpret_cast<uintptr_t>(w.ray_limit) % 4 != 0)
+    return fail(SG_ERR_INVALID_ARG, "ray_limit must be 4-byte aligned");
+  const double* m = w.cam_to_world;
+  double det = m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
+               m[2] * (m[4] * m[9] - m[5] * m[8]);
+  if (!(std::fabs(det) > 1e-12)) return fail(SG_ERR_INVALID_ARG, "singular camera rotation");
+  ViewDev& o = *out;
+  std::memset(&o, 0, sizeof(o));
+  o.e[0] = m[3];
+  o.e[1] = m[7];
+  o.e[2] = m[11];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) o.R[3 * r + c] = m[4 * r + c];
+  o.tl = w.tan_left;
+  o.tr = w.tan_right;
+  o.tb = w.tan_bottom;
+  o.tt = w.tan_top;
+  o.W = w.width;
+  o.H = w.height;
+  o.lens_on = (w.lens[0] != 0.0 || w.lens[1] != 0.0) ? 1 : 0;
+  for (int k = 0; k < 4; ++k) o.lens[k] = w.lens[k];
+  return SG_OK;
+}
+
 sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       const sg_render_params* p, float* const* rgba, float* const* depth,
                       int32_t* const* nsamp, int bt_log, std::vector<ViewDev>* out,
@@ -217,36 +251,12 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
   const int bpx = 8 << bt_log;  // block edge in pixels
   for (int i = 0; i < n_views; ++i) {
     const sg_view& w = views[i];
-    for (int k = 0; k < 16; ++k)
-      if (!finite(w.cam_to_world[k])) return fail(SG_ERR_INVALID_ARG, "camera matrix not finite");
-    if (!(finite(w.tan_left) && finite(w.tan_right) && finite(w.tan_bottom) &&
-          finite(w.tan_top) && w.tan_left < w.tan_right && w.tan_bottom < w.tan_top))
-      return fail(SG_ERR_INVALID_ARG, "view tangents must be finite with left<right, bottom<top");
-    if (w.width < 1 || w.height < 1 || w.width > 32768 || w.height > 32768)
-      return fail(SG_ERR_INVALID_ARG, "view size must be in [1, 32768]");
-    for (int k = 0; k < 4; ++k)
-      if (!finite(w.lens[k])) return fail(SG_ERR_INVALID_ARG, "lens coefficients not finite");
-    if (w.ray_limit && reinterpret_cast<uintptr_t>(w.ray_limit) % 4 != 0)
-      return fail(SG_ERR_INVALID_ARG, "ray_limit must be 4-byte aligned");
-    const double* m = w.cam_to_world;
-    double det = m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
-                 m[2] * (m[4] * m[9] - m[5] * m[8]);
-    if (!(std::fabs(det) > 1e-12)) return fail(SG_ERR_INVALID_ARG, "singular camera rotation");
+    if ((st = view_geometry(w, &hv[i])) != SG_OK) return st;
     if (rgba && !rgba[i]) return fail(SG_ERR_INVALID_ARG, "out_rgba entry is NULL");
     if ((rgba && reinterpret_cast<uintptr_t>(rgba[i]) % 16 != 0) ||
         (depth && depth[i] && reinterpret_cast<uintptr_t>(depth[i]) % 4 != 0))
       return fail(SG_ERR_INVALID_ARG, "output buffers must be 16-byte (rgba) / 4-byte aligned");
     ViewDev& o = hv[i];
-    std::memset(&o, 0, sizeof(o));
-    o.e[0] = m[3];
-    o.e[1] = m[7];
-    o.e[2] = m[11];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) o.R[3 * r + c] = m[4 * r + c];
-    o.tl = w.tan_left;
-    o.tr = w.tan_right;
-    o.tb = w.tan_bottom;
-    o.tt = w.tan_top;
     const double theta = (w.tan_top - w.tan_bottom) / (double)w.height;
     o.K = (p->lod_tau_px * theta) * (p->lod_tau_px * theta);
     o.W = w.width;
@@ -261,8 +271,6 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
     o.depth = depth ? depth[i] : nullptr;
     o.nsamp = nsamp ? nsamp[i] : nullptr;
     o.limit = w.ray_limit;
-    o.lens_on = (w.lens[0] != 0.0 || w.lens[1] != 0.0) ? 1 : 0;
-    for (int k = 0; k < 4; ++k) o.lens[k] = w.lens[k];
     if (blocks > (1 << 24)) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
   }
   *total_blocks = blocks;

@@ -145,8 +145,10 @@ struct Ray {
   int nsamp;
 };
 
-__device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const ViewDev& V, int px,
-                                          int py) {
+// The ray of pixel (px, py) of a view (Sec 5.1): eye e and unit direction d
+// through the pixel centre, in FP64.
+__device__ __forceinline__ void view_ray(const ViewDev& V, int px, int py, double e[3],
+                                         double d[3]) {
   double sx = V.tl + (((double)px + 0.5) / (double)V.W) * (V.tr - V.tl);
   double sy = V.tt - (((double)py + 0.5) / (double)V.H) * (V.tt - V.tb);
   if (V.lens_on) {
@@ -161,12 +163,17 @@ __device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const Vie
   double w3[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    r.e[i] = V.e[i];
+    e[i] = V.e[i];
     w3[i] = (V.R[3 * i + 0] * sx + V.R[3 * i + 1] * sy) + V.R[3 * i + 2] * (-1.0);
   }
   const double len = sqrt((w3[0] * w3[0] + w3[1] * w3[1]) + w3[2] * w3[2]);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) r.d[i] = w3[i] / len;
+  for (int i = 0; i < 3; ++i) d[i] = w3[i] / len;
+}
+
+__device__ __forceinline__ void ray_setup(Ray& r, const RenderArgs& a, const ViewDev& V, int px,
+                                          int py) {
+  view_ray(V, px, py, r.e, r.d);
   r.Cr = r.Cg = r.Cb = 0.f;
   r.T = 1.f;
 #pragma unroll

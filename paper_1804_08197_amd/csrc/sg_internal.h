@@ -239,6 +239,10 @@ sg_status prepare_views(Volume* v, int n_views, const sg_view* views,
                         hipStream_t s, int* total_blocks);
 // Checked host copy of the per-view constants (screen blocks of 2^bt_log
 // wave tiles per side) and the number of blocks over all views.
+// Checks a view (finite matrix and tangents, sizes, lens, ray-limit
+// alignment, non-singular rotation) and fills its eye, rotation, tangents,
+// size and lens fields; the other fields are zero.
+sg_status view_geometry(const sg_view& w, ViewDev* out);
 sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       const sg_render_params* p, float* const* rgba, float* const* depth,
                       int32_t* const* nsamp, int bt_log, std::vector<ViewDev>* hv,

@@ -112,6 +112,8 @@ _lib.sg_cache_put.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                               C.POINTER(C.c_int32), _P, C.c_int32, _P]
 _lib.sg_render_views_if.argtypes = [_P, C.c_int32, C.POINTER(sg_view), C.POINTER(sg_render_params),
                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _P, _P]
+_lib.sg_composite_over.argtypes = [C.POINTER(sg_view), C.c_int32, C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_double), _P, _P]
 _lib.sg_cache_put_scattered.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_void_p), _P]
 _lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32),
@@ -315,6 +317,20 @@ def sg_render_views_if(vol, views, params, out_rgba, enable, out_depth=None, str
     _check(_lib.sg_render_views_if(vol, n, varr, C.byref(p), rgba, dep,
                                    C.c_void_p(enable.data_ptr()), _stream(stream)),
            "sg_render_views_if")
+
+
+def sg_composite_over(view, parts, boxes, out_rgba, stream=None):
+    """Front-over-back composite of the part images (device float4 tensors,
+    one per box) of one view, in the order each pixel's ray enters the boxes
+    (boxes: one (lo x, y, z, hi x, y, z) per part)."""
+    n = len(parts)
+    v = make_view(view)
+    arr = (C.c_void_p * n)(*[p.data_ptr() for p in parts])
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(n, 6))
+    _check(_lib.sg_composite_over(C.byref(v), n, arr,
+                                  b.ctypes.data_as(C.POINTER(C.c_double)),
+                                  C.c_void_p(out_rgba.data_ptr()), _stream(stream)),
+           "sg_composite_over")
 
 
 def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samples=None,

@@ -129,6 +129,7 @@ def test_null_arguments_are_invalid(sg):
         sg.SG_ERR_INVALID_ARG
     assert lib.sg_cache_put_scattered(None, 0, 0, 0, 1, None, None, None) == \
         sg.SG_ERR_INVALID_ARG
+    assert lib.sg_composite_over(None, 1, None, None, None, None) == sg.SG_ERR_INVALID_ARG
     from paper_1804_08197_amd import upsampler as up
     assert up._lib.sg_up_forward_flag(None, 1, 1, 1, None, None, 1.0, None, None, 40.0, None,
                                       None) == sg.SG_ERR_INVALID_ARG
@@ -155,3 +156,29 @@ def test_pack_bricks_layout():
                 for x in range(4):
                     gz, gy, gx = min(4 * bz + z, 4), min(4 * by + y, 5), min(4 * bx + x, 6)
                     assert core[z, y, x] == v[gz, gy, gx]
+
+
+def test_composite_argument_checks_need_no_device(sg):
+    """sg_composite_over rejects bad part counts, misaligned images and
+    empty or non-finite boxes before it touches a device."""
+    import ctypes as C
+
+    import gen
+    lib = sg.lib()
+    v = sg.make_view(gen.view(gen.look_at((-100.0, 50.0, 40.0), (16, 16, 16)), 8, 6, 0.5))
+    buf = np.zeros(8 * 6 * 4 + 8, np.float32)
+    base = buf.ctypes.data + (-buf.ctypes.data) % 16
+    parts = (C.c_void_p * 2)(base, base)
+    out = C.c_void_p(base)
+
+    def call(n, boxes, arr=parts, o=out):
+        b = np.ascontiguousarray(np.asarray(boxes, np.float64))
+        return lib.sg_composite_over(C.byref(v), n, arr, b.ctypes.data_as(C.POINTER(C.c_double)),
+                                     o, None)
+    good = [[0, 0, 0, 16, 32, 32], [16, 0, 0, 32, 32, 32]]
+    assert call(0, good) == sg.SG_ERR_INVALID_ARG
+    assert call(9, good * 5) == sg.SG_ERR_INVALID_ARG
+    assert call(2, [[0, 0, 0, 16, 32, 32], [16, 0, 0, 16, 32, 32]]) == sg.SG_ERR_INVALID_ARG
+    assert call(2, [[0, 0, 0, 16, 32, 32], [16, 0, np.nan, 32, 32, 32]]) == sg.SG_ERR_INVALID_ARG
+    assert call(2, good, arr=(C.c_void_p * 2)(base, base + 4)) == sg.SG_ERR_INVALID_ARG
+    assert call(2, good, o=C.c_void_p(base + 8)) == sg.SG_ERR_INVALID_ARG

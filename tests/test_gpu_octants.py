@@ -1,8 +1,10 @@
 """Sort-last split on one GPU: the region of interest clips each ray to one
 octant of the volume (the share one GPU would own); the eight octant
 renders of a view, composited front over back per pixel in the order the
-ray enters the octants, equal the whole render (the oracle pins the same
-identity in FP64; here the renders are FP32, so up to rounding).
+ray enters the octants (sg_composite_over, checked against the same
+composite done here on the host with the oracle's rays), equal the whole
+render (the oracle pins the same identity in FP64; here the renders are
+FP32, so up to rounding).
 """
 import numpy as np
 import pytest
@@ -35,16 +37,25 @@ def test_octant_renders_composite_to_the_whole_frame():
                     for v in views]
             sg.sg_render_views(h, views, p, outs)
             torch.cuda.synchronize()
-            return [o.cpu().numpy().astype(np.float64) for o in outs]
+            return outs
 
-        whole = render(params)
-        boxes, parts = [], []
+        whole_d = render(params)
+        whole = [o.cpu().numpy().astype(np.float64) for o in whole_d]
+        boxes, parts_d = [], []
         for o in range(8):
             lo = [64.0 * ((o >> a) & 1) for a in range(3)]
             hi = [x + 64.0 for x in lo]
             boxes.append((lo, hi))
-            parts.append(render(dict(params, roi=tuple(lo) + tuple(hi))))
+            parts_d.append(render(dict(params, roi=tuple(lo) + tuple(hi))))
+        parts = [[x.cpu().numpy().astype(np.float64) for x in p] for p in parts_d]
         for i, v in enumerate(views):
+            # on the device, through the C-ABI
+            dev = torch.full((v["height"], v["width"], 4), float("nan"), device="cuda")
+            sg.sg_composite_over(v, [p[i] for p in parts_d], [lo + hi for lo, hi in boxes], dev)
+            torch.cuda.synchronize()
+            dev = dev.cpu().numpy().astype(np.float64)
+            err_dev = np.abs(dev - whole[i]).max()
+            assert err_dev <= 2e-5, "view %d: device composite differs by %g" % (i, err_dev)
             comp = np.zeros_like(whole[i])
             for y in range(v["height"]):
                 for x in range(v["width"]):
@@ -62,6 +73,7 @@ def test_octant_renders_composite_to_the_whole_frame():
                     comp[y, x] = c
             err = np.abs(comp - whole[i]).max()
             assert err <= 2e-5, "view %d: composite differs by %g" % (i, err)
+            assert np.abs(comp - dev).max() <= 2e-6
             assert whole[i][..., 3].max() > 0.3  # the rays do cross content
     finally:
         sg.sg_volume_destroy(h)
