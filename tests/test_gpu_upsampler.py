@@ -362,3 +362,104 @@ def test_empty_neighbourhoods_yield_background(shape):
         log("%s: %.1f%% of output pixels background" % (shape, 100 * empty.mean()))
     finally:
         u.close()
+
+
+def test_full_size_stereo_input_sampled_parity():
+    """The benchmark's network input (two eyes of 720 x 800, sparse content
+    as in the blob scene): fused inference equals the layered path bit for
+    bit over the whole frame; at sampled pixels (corners, edges, tile seams,
+    content) every layer of the layered path matches the FP64 reference on
+    the GPU's own input of that layer (the bars of the small case); the
+    whole upsampled output matches its FP64 reconstruction from the GPU's x0
+    and last layer with the inference rule."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    n, h, w = 2, 800, 720
+    rng = np.random.default_rng(41)
+    params = bf16_params(rng, 0.5)
+    rgba = np.zeros((n, h, w, 4), np.float32)
+    depth = np.full((n, h, w), np.inf, np.float32)
+    yy, xx = np.mgrid[0:h, 0:w]
+    centres = []
+    for i in range(n):
+        for _ in range(6):  # discs of content
+            cy, cx, r = rng.integers(0, h), rng.integers(0, w), rng.integers(20, 90)
+            m = (yy - cy) ** 2 + (xx - cx) ** 2 < r * r
+            a = rng.uniform(0.1, 1.0, size=m.sum()).astype(np.float32)
+            rgba[i][m] = np.stack([rng.uniform(0, 1, m.sum()) * a, rng.uniform(0, 1, m.sum()) * a,
+                                   rng.uniform(0, 1, m.sum()) * a, a], -1)
+            depth[i][m] = rng.uniform(10, 300, m.sum())
+            centres.append((i, int(cy), int(cx)))
+    trgba, tdepth = torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+    u = up.Upsampler(n * h * w)
+    try:
+        u.set_weights(up.pack(params))
+        res = []
+        for fused in (True, False):
+            u.set_fused(fused)
+            out = torch.full((n, 2 * h, 2 * w, 4), float("nan"), device="cuda")
+            err = torch.full((n, 2 * h, 2 * w), float("nan"), device="cuda")
+            mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True)
+            res.append((out.cpu().numpy(), err.cpu().numpy(), mse))
+        (o1, e1, m1), (o0, e0, m0) = res  # fused, then layered (buffers readable)
+        assert np.array_equal(o0, o1) and np.array_equal(e0, e1)
+        assert np.allclose(m0, m1, rtol=1e-12, atol=0)
+        # sampled pixels: corners, edges, 16-pixel tile seams, content
+        pix = [(i, y, x) for i in range(n) for y in (0, h - 1) for x in (0, w - 1)]
+        pix += [(i, 15, 16) for i in range(n)] + [(i, 400, 367) for i in range(n)]
+        pix += [(i, min(h - 1, max(0, cy + int(rng.integers(-30, 31)))),
+                 min(w - 1, max(0, cx + int(rng.integers(-30, 31))))) for i, cy, cx in centres]
+        pix += [(int(rng.integers(0, n)), int(rng.integers(0, h)), int(rng.integers(0, w)))
+                for _ in range(40)]
+
+        def conv_at(inp, wgt, b, i, y, x):
+            c = inp.shape[-1]
+            crop = np.zeros((1, 3, 3, c))
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if 0 <= y + dy < h and 0 <= x + dx < w:
+                        crop[0, dy + 1, dx + 1] = inp[i, y + dy, x + dx]
+            return U.conv3x3(crop, wgt, b)[0, 1, 1]
+
+        x0 = u.read_buffer(0, (n, h, w, 8), "bf16")
+        assert np.array_equal(x0, x0_reference_of(rgba, depth))
+        prev = x0
+        bad = total = 0
+        for layer in range(3):
+            got = u.read_buffer(1 + layer, (n, h, w, 32), "bf16")
+            wgt, b = params[layer]
+            for i, y, x in pix:
+                ref = U.to_bf16(U.relu(conv_at(prev, wgt, b, i, y, x)))
+                ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7
+                d = np.abs(got[i, y, x] - ref)
+                assert (d <= 2 * ulp.max()).all(), (layer, i, y, x)
+                bad += int((d > ulp).sum())
+                total += d.size
+            prev = got
+        assert bad <= max(4, 2e-3 * total)
+        o = u.read_buffer(4, (n, h, w, 32), "f32")
+        wgt, b = params[3]
+        for i, y, x in pix:
+            oref = conv_at(prev, wgt, b, i, y, x)
+            assert np.abs(o[i, y, x] - oref).max() <= 1e-5 * max(1.0, np.abs(oref).max())
+        empty = np.repeat(np.repeat(U.empty_neighbourhood(x0), 2, axis=1), 2, axis=2)
+        assert empty.any() and (~empty).any()
+        sh = U.pixel_shuffle(o)
+        ref = np.where(empty[..., None], 0.0, U.bilinear_up2(x0[..., :4]) + sh[..., :4])
+        assert np.abs(o0 - ref).max() <= 1e-5
+        log("full size: %d sampled pixels, %.4f%% one bf16 step off, %.1f%% background" % (
+            len(pix), 100.0 * bad / total, 100 * empty.mean()))
+    finally:
+        u.close()
+
+
+def x0_reference_of(rgba, depth):
+    """x0_reference for any input shape."""
+    inv = np.float32(1.0 / SCALE)
+    code = np.where(np.isfinite(depth), np.float32(1) / (np.float32(1) + depth * inv),
+                    np.float32(0)).astype(np.float32)
+    x0 = np.zeros(rgba.shape[:-1] + (8,))
+    x0[..., :4] = U.to_bf16(rgba)
+    x0[..., 4] = U.to_bf16(code)
+    return x0
