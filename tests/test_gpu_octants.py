@@ -77,3 +77,38 @@ def test_octant_renders_composite_to_the_whole_frame():
             assert whole[i][..., 3].max() > 0.3  # the rays do cross content
     finally:
         sg.sg_volume_destroy(h)
+
+
+def test_slab_parts_with_a_lens_view_composite_to_the_whole_frame():
+    """Three slabs of unequal width along x, a wrapped-space (lens) view and
+    a view from inside the volume's bounding planes: the composite follows
+    the renderer's own rays (lens included) and ignores parts a ray misses."""
+    import torch
+
+    from paper_1804_08197_amd import sg
+    vol = gen.blobs128()
+    tf = gen.tf_identity()
+    tf[:, 3] *= 0.3
+    h = gpu_volume([vol], 32, 3, [tf], [(0, 255)])
+    try:
+        params = {"step": 0.5, "ert": 2.0, "tau": 1.0, "lod": 0, "skip_empty": 1, "bias": 0}
+        lens_view = dict(gen.view(gen.look_at((64.0, -170.0, 90.0), (64, 64, 64)), 48, 40, 0.6),
+                         lens=(0.2, 0.1, 0.05, -0.03))
+        side_view = gen.view(gen.look_at((64.0, 64.0, 300.0), (64, 64, 0), up=(0, 1, 0)), 33, 29,
+                             0.4)
+        boxes = [(0, 0, 0, 32, 128, 128), (32, 0, 0, 96, 128, 128), (96, 0, 0, 128, 128, 128)]
+        for v in (lens_view, side_view):
+            def render(p):
+                o = torch.full((v["height"], v["width"], 4), float("nan"), device="cuda")
+                sg.sg_render_views(h, [v], p, [o])
+                return o
+            whole = render(params)
+            parts = [render(dict(params, roi=b)) for b in boxes]
+            comp = torch.full_like(whole, float("nan"))
+            sg.sg_composite_over(v, parts, boxes, comp)
+            torch.cuda.synchronize()
+            err = float((comp - whole).abs().max())
+            assert err <= 2e-5, err
+            assert float(whole[..., 3].max()) > 0.3
+    finally:
+        sg.sg_volume_destroy(h)
