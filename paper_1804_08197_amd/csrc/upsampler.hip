@@ -672,14 +672,19 @@ fused_forward_kernel(
   float zsum = 0.f;
   if (!__syncthreads_or(any_nz)) {
     // the whole region is empty: every pixel of the tile is background, and
-    // the tile's partial sum is zero
-    if (y < H && x < W)
+    // the tile's partial sum is zero. The 32 x 32 output pixels are written
+    // row by row (store j of lane i: pixel j * 256 + i), so that each store
+    // covers whole 512-byte output rows.
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t q = ((int64_t)n * 2 * H + 2 * y + (s >> 1)) * (2 * W) + 2 * x + (s & 1);
+    for (int j = 0; j < 4; ++j) {
+      const int e = j * 256 + (int)threadIdx.x;
+      const int oy = 2 * ty0 + e / (2 * kTile), ox = 2 * tx0 + e % (2 * kTile);
+      if (oy < 2 * H && ox < 2 * W) {
+        const int64_t q = ((int64_t)n * 2 * H + oy) * (2 * W) + ox;
         out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (err) err[q] = 0.f;
       }
+    }
     if (sums.sum && threadIdx.x == 0)
       sums.sum[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = 0.0;
     return;
