@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "samples/s and stereo frames/s, plain vs learned-upsampler path at PSNR≥40 dB"
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector (packed FMA)
-FLOP_PER_SAMPLE = 56         # algorithmic FP32 operations of one single-channel sample
+FLOP_PER_SAMPLE = 31         # algorithmic FLOP of one single-channel sample (see flop_per_sample)
 
 
 def log(msg):
@@ -717,11 +717,13 @@ def bench_octants(args):
 
 
 def flop_per_sample(channels):
-    """Algorithmic FP32 operations of one emission-absorption sample: 56 for
-    one channel; each further channel adds trilinear 21, table index 3,
-    table lerps 12 and its weighted colour sum 7; several channels add the
-    colour normalisation 4."""
-    return FLOP_PER_SAMPLE + 43 * (channels - 1) + (4 if channels > 1 else 0)
+    """Algorithmic FLOP of one emission-absorption sample, with a linear
+    interpolation counted as one multiply-add (2 FLOP): trilinear 7 lerps
+    14, table 4 lerps 8, the exponential 1, compositing 8 -- 31 for one
+    channel. Each further channel adds its trilinear 14 and table 8 and its
+    share of the sum 7 (extinction add, weighted colour); several channels
+    add the colour normalisation 4."""
+    return FLOP_PER_SAMPLE + 29 * (channels - 1) + (4 if channels > 1 else 0)
 
 
 def bench_stream(args):
