@@ -947,8 +947,18 @@ def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
         one_s += time.perf_counter() - t
         one_pix += len(pix)
         one_samp += r["total_samples"]
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / frame_s, "unit": "stereo frames/s", "cores": threads,
             "kind": "oracle", "samples_per_s": done_samp / spent,
+            "cpu_model": cpu_model, "nproc": os.cpu_count(),
             "single_thread": {"value": one_pix / (one_s * npix), "unit": "stereo frames/s",
                               "samples_per_s": one_samp / one_s, "pixels": one_pix},
             "sample": "%d uniformly random pixels of both eyes (%.1f%% of the frame's pixel "
