@@ -114,13 +114,20 @@ typedef struct {
  * a depth texture): NULL, or a device float [height][width] of distances
  * along each pixel's ray from the eye (level-0 units); samples lie in front
  * of it (+inf or NaN: no limit). Read in stream order; ignored by
- * sg_get_lod_cut. */
+ * sg_get_lod_cut.
+ * tile_any: NULL, or a device uint8 [(height + 7) / 8][(width + 7) / 8]
+ * that the render fills, one byte per 8x8-pixel block of the image (block
+ * (bx, by) holds pixels 8 bx .. 8 bx + 7, 8 by .. 8 by + 7): 1 if any of its
+ * pixels has a nonzero output RGBA (background included) or, when depth is
+ * written, a finite depth; else 0. A content mask for later passes over the
+ * image (the learned upsampler skips empty screen regions with it). */
 typedef struct {
   double cam_to_world[16];
   double tan_left, tan_right, tan_bottom, tan_top;
   int32_t width, height; /* >= 1 */
   double lens[4];        /* k1, k2, cx, cy; all 0 = rectilinear           */
   const float *ray_limit;
+  uint8_t *tile_any;
 } sg_view;
 
 typedef struct {

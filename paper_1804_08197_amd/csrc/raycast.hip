@@ -271,6 +271,7 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
     o.depth = depth ? depth[i] : nullptr;
     o.nsamp = nsamp ? nsamp[i] : nullptr;
     o.limit = w.ray_limit;
+    o.tile_any = w.tile_any;
     if (blocks > (1 << 24)) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
   }
   *total_blocks = blocks;

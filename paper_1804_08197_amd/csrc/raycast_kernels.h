@@ -554,7 +554,9 @@ __device__ __forceinline__ void slot_ptrs(const RenderArgs& a, int node, const T
 }
 
 template <int MODEL, int CH>
-__device__ __forceinline__ void write_pixel(Ray& r, const RenderArgs& a, const ViewDev& V,
+// Returns whether the pixel has content (a nonzero RGBA or, when depth is
+// written, a finite depth).
+__device__ __forceinline__ bool write_pixel(Ray& r, const RenderArgs& a, const ViewDev& V,
                                             const float4* s_tf, int px, int py) {
   finish_depth(r);
   if (MODEL == kModelMip && r.sampled) {
@@ -576,7 +578,10 @@ __device__ __forceinline__ void write_pixel(Ray& r, const RenderArgs& a, const V
   out.w = fmaf(omA, a.bg[3], 1.0f - r.T);
   reinterpret_cast<float4*>(V.rgba)[pix] = out;
   if (V.depth) V.depth[pix] = r.depth;
+  return out.x != 0.f || out.y != 0.f || out.z != 0.f || out.w != 0.f ||
+         (V.depth != nullptr && r.depth < INFINITY);
 }
+
 
 // Work decomposition. A wave renders a tile of 8x8 pixels. A workgroup
 // covers a square screen tile of 2^tile_log wave tiles per side with
@@ -598,6 +603,18 @@ struct TileLane {
   bool in_image;
   bool tile_valid;
 };
+
+// The content byte of the wave's 8x8-pixel tile, when the view asks for the
+// mask. Called by the whole wave (converged); nz: the lane's pixel has
+// content.
+__device__ __forceinline__ void mark_tile(const RenderArgs& a, const TileLane& tl, bool nz) {
+  if (!tl.tile_valid) return;  // the same for every lane of the wave
+  const ViewDev& V = a.views[tl.view];
+  if (!V.tile_any) return;
+  const uint64_t m = __ballot(nz);
+  if ((threadIdx.x & 63) == 0)  // lane 0 holds the tile's first pixel
+    V.tile_any[(int64_t)(tl.py >> 3) * ((V.W + 7) >> 3) + (tl.px >> 3)] = m != 0 ? 1 : 0;
+}
 
 // Lane's pixel of wave tile k (row-major) of workgroup tile t in global
 // block `block`.
@@ -667,7 +684,7 @@ __device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
 
 // ------------------------------------------------------------ gather kernel
 template <typename T, int CH, bool STATS, int MODEL>
-__device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* s_tf,
+__device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* s_tf,
                                              const TileLane& tl) {
   const ViewDev& V = a.views[tl.view];
   int mb_key[CH][3];
@@ -689,11 +706,12 @@ __device__ __forceinline__ void gather_pixel(const RenderArgs& a, const float4* 
     if (!go) break;
     next_segment<MODEL, CH>(r, a, V, false);
   }
-  write_pixel<MODEL, CH>(r, a, V, s_tf, tl.px, tl.py);
+  const bool nz = write_pixel<MODEL, CH>(r, a, V, s_tf, tl.px, tl.py);
   if (STATS) {
     if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
     atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
   }
+  return nz;
 }
 
 // LOOP: the wave renders several tiles (persistent grid, or a direct grid
@@ -706,15 +724,22 @@ __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
   load_tf<CH>(a, s_tf);
   if (!LOOP) {
     const TileLane tl = tile_lane(a, 0);
-    if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+    bool nz = false;
+    if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+    mark_tile(a, tl, nz);
   } else if (a.persistent) {
     TileLane tl;
-    while (next_tile(a, tl))
-      if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+    while (next_tile(a, tl)) {
+      bool nz = false;
+      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+      mark_tile(a, tl, nz);
+    }
   } else {
     for (int it = 0; it < a.wave_tiles; ++it) {
       const TileLane tl = tile_lane(a, it);
-      if (tl.in_image) gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+      bool nz = false;
+      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+      mark_tile(a, tl, nz);
     }
   }
 }
@@ -1047,13 +1072,15 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     // --- rays that finished this node move on to their next segment
     if (mine && r.alive) next_segment<MODEL, CH>(r, a, V, false);
   }
+  bool nz = false;
   if (tl.in_image) {
-    write_pixel<MODEL, CH>(r, a, V, s_tf, tl.px, tl.py);
+    nz = write_pixel<MODEL, CH>(r, a, V, s_tf, tl.px, tl.py);
     if (STATS) {
       if (V.nsamp) V.nsamp[(int64_t)tl.py * V.W + tl.px] = r.nsamp;
       atomicAdd((unsigned long long*)a.counters, (unsigned long long)r.nsamp);
     }
   }
+  mark_tile(a, tl, nz);
 }
 
 template <typename T, int CH, bool STATS, int MODEL, bool LOOP>

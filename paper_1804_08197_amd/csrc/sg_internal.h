@@ -114,6 +114,7 @@ struct ViewDev {
   const float* limit;  // per-pixel ray limit or NULL
   double lens[4];      // k1, k2, cx, cy
   int32_t lens_on;
+  uint8_t* tile_any;   // per 8x8-pixel block content flag or NULL
 };
 
 // Up to kInlineViews view records travel inside the cut-map kernel's

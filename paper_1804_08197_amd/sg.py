@@ -45,7 +45,7 @@ class sg_view(C.Structure):
     _fields_ = [("cam_to_world", C.c_double * 16), ("tan_left", C.c_double),
                 ("tan_right", C.c_double), ("tan_bottom", C.c_double), ("tan_top", C.c_double),
                 ("width", C.c_int32), ("height", C.c_int32), ("lens", C.c_double * 4),
-                ("ray_limit", C.c_void_p)]
+                ("ray_limit", C.c_void_p), ("tile_any", C.c_void_p)]
 
 
 class sg_render_params(C.Structure):
@@ -184,6 +184,8 @@ def make_view(v) -> sg_view:
         o.lens[i] = float(lens[i])
     lim = _ptr(v.get("ray_limit"))
     o.ray_limit = lim.value if lim is not None else None
+    ta = _ptr(v.get("tile_any"))
+    o.tile_any = ta.value if ta is not None else None
     return o
 
 

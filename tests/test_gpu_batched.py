@@ -253,3 +253,50 @@ def test_small_calls_carry_their_views_inline_with_the_same_images(blobs):
     tail = render(h, views[5:9], params)
     for i in range(4):
         assert np.array_equal(tail[i].cpu().numpy(), big[5 + i].cpu().numpy()), i
+
+
+@pytest.mark.parametrize("launch", [None, (1, 8, 32, 8192, 0), (0, 16, 64, 8192, 1),
+                                    (1, 32, 64, 8192, 1)])
+def test_content_mask_marks_the_blocks_with_content(blobs, launch):
+    """tile_any: one byte per 8x8-pixel block, 1 exactly where a pixel of the
+    block has a nonzero RGBA or (with depth output) a finite depth, in every
+    launch configuration; ragged views included."""
+    import torch
+
+    from paper_1804_08197_amd import sg
+    h, vol, tf = blobs
+    views = uneven_views(n=5)
+    params = {"step": 0.5, "ert": ERT, "tau": 1.0, "lod": 1, "skip_empty": 1, "bias": 0}
+    sg.sg_set_launch_config(h, None if launch is None else
+                            dict(zip(sg.LAUNCH_FIELDS, launch)))
+    try:
+        for with_depth in (False, True):
+            masks = [torch.full(((v["height"] + 7) // 8, (v["width"] + 7) // 8), 7,
+                                dtype=torch.uint8, device="cuda") for v in views]
+            vs = [dict(v, tile_any=m) for v, m in zip(views, masks)]
+            outs = [torch.full((v["height"], v["width"], 4), float("nan"), device="cuda")
+                    for v in views]
+            deps = [torch.full((v["height"], v["width"]), float("nan"), device="cuda")
+                    for v in views] if with_depth else None
+            sg.sg_render_views(h, vs, params, outs, deps)
+            torch.cuda.synchronize()
+            for i, v in enumerate(views):
+                nz = (outs[i] != 0).any(-1)
+                if with_depth:
+                    nz |= torch.isfinite(deps[i])
+                H8, W8 = masks[i].shape
+                pad = torch.zeros(H8 * 8, W8 * 8, dtype=torch.bool, device="cuda")
+                pad[:v["height"], :v["width"]] = nz
+                want = pad.view(H8, 8, W8, 8).any(3).any(1).to(torch.uint8)
+                assert torch.equal(masks[i], want), (launch, with_depth, i)
+        # a nonzero background gives every block content
+        v = views[0]
+        m = torch.zeros(((v["height"] + 7) // 8, (v["width"] + 7) // 8), dtype=torch.uint8,
+                        device="cuda")
+        o = torch.empty(v["height"], v["width"], 4, device="cuda")
+        sg.sg_render_views(h, [dict(v, tile_any=m)], dict(params, bg=(0, 0, 0.1, 1)),
+                           [o])
+        torch.cuda.synchronize()
+        assert bool((m == 1).all())
+    finally:
+        sg.sg_set_launch_config(h, None)
