@@ -496,6 +496,15 @@ def bench_upsampler(args):
     ev_net[1].record()
     torch.cuda.synchronize()
     net_ms = ev_net[0].elapsed_time(ev_net[1]) / 50
+    # the network as the device-decided path runs it, with the fallback decision
+    flag1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ev_f = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev_f[0].record()
+    for _ in range(50):
+        model.forward_flag(path.rgba_lo, path.depth_lo, diag, path.out, thr, flag1)
+    ev_f[1].record()
+    torch.cuda.synchronize()
+    flag_ms = ev_f[0].elapsed_time(ev_f[1]) / 50
     # the network runs only on 16x16 input tiles with a nonzero input pixel
     # within its 4-pixel reach (empty tiles write background): the
     # algorithmic work counts the pixels of those tiles, at 2 x 9 x 32 x
@@ -527,7 +536,7 @@ def bench_upsampler(args):
            "launch_upsampler_path": launch_up,
            "upsampler_path_host_decision_ms": up_host_ms,
            "timed_fallbacks_host_decision": int(fell_host),
-           "network_ms": net_ms,
+           "network_ms": net_ms, "network_flag_ms": flag_ms,
            "network_tiles_run": tiles_run, "network_tiles": tiles_all,
            "network_tflops": flops / (net_ms * 1e-3) / 1e12,
            "roofline": net_roof[0], "roofline_other": net_roof[1],

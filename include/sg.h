@@ -119,8 +119,8 @@ typedef struct {
  * that the render fills, one byte per 8x8-pixel block of the image (block
  * (bx, by) holds pixels 8 bx .. 8 bx + 7, 8 by .. 8 by + 7): 1 if any of its
  * pixels has a nonzero output RGBA (background included) or, when depth is
- * written, a finite depth; else 0. A content mask for later passes over the
- * image (the learned upsampler skips empty screen regions with it). */
+ * written, a finite depth; else 0: a content mask of the image for passes
+ * that run over it later. */
 typedef struct {
   double cam_to_world[16];
   double tan_left, tan_right, tan_bottom, tan_top;

@@ -515,15 +515,14 @@ __global__ __launch_bounds__(kSumThreads) void tile_sum_kernel(SumArgs a) {
 }
 
 // the workgroup's share of the predicted error, into its partial slot
-__device__ void tile_partial(const SumArgs& a, double* red, float zsum) {
+__device__ void tile_partial(const SumArgs& a, double* red, float zsum, int64_t slot) {
   red[threadIdx.x] = (double)zsum;
   __syncthreads();
   for (int st = (int)blockDim.x / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-    a.sum[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) a.sum[slot] = red[0];
 }
 
 // The network on a tile with content (every layer, then the pixel shuffle,
@@ -599,33 +598,15 @@ __device__ __forceinline__ float fused_tile(
 
 // LDS allows two workgroups per CU (two waves per SIMD): the register
 // budget is set for that, so a K-step's reads can all be in flight.
-__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
-fused_forward_kernel(
-    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
-    float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
-    const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
-    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
-    float4* __restrict__ out, float* __restrict__ err, SumArgs sums) {
-  // LDS (kFusedLds bytes): U, V, then x0's rgba (bf16-rounded) on the tile
-  // and a 1-pixel ring for the bilinear base of the last phase, then the
-  // reduction scratch
-  extern __shared__ float4 fused_smem[];
-  bf16* sU = reinterpret_cast<bf16*>(fused_smem);
-  bf16* sV = sU + kBufU;
-  float4* sX = reinterpret_cast<float4*>(sV + kBufV);
-  double* red = reinterpret_cast<double*>(sX + kE1 * kE1);
-  // nonzero flags of the x0 region, then their 9-wide row maxima (both in
-  // the reduction scratch, which is free until the last phase)
-  uint8_t* nzf = reinterpret_cast<uint8_t*>(red);
-  uint8_t* rowany = nzf + kE0 * kE0;
-  static_assert(kE0 * kE0 + kE0 * kTile <= 256 * 8, "flags fit the scratch");
-  const int n = blockIdx.z;
-  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
-  bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
-  load_weights<8>(w0, wa);
-  // x0 on the tile and a 4-pixel halo (zero outside the image): every load
-  // is issued before any is used
-  constexpr int kPrep = (kE0 * kE0 + 255) / 256;
+// x0 of tile (n, ty0, tx0) with a 4-pixel halo (zero outside the image)
+// into LDS: the bf16 region in sV, its nonzero flags in nzf and the rgba of
+// the tile plus a 1-pixel ring in sX. Every load is issued before any is
+// used. Returns whether this thread saw a nonzero input pixel.
+constexpr int kPrep = (kE0 * kE0 + 255) / 256;
+__device__ __forceinline__ bool prep_region(const float4* __restrict__ rgba,
+                                            const float* __restrict__ depth, int H, int W,
+                                            float inv_scale, int n, int ty0, int tx0, bf16* sV,
+                                            uint8_t* nzf, float4* sX) {
   float4 pc[kPrep];
   float pd[kPrep];
 #pragma unroll
@@ -667,32 +648,81 @@ fused_forward_kernel(
     if (ry >= 0 && ry < kE1 && rx >= 0 && rx < kE1)
       sX[ry * kE1 + rx] = make_float4(bf(v[0]), bf(v[1]), bf(v[2]), bf(v[3]));
   }
+  return any_nz;
+}
+
+// Background for every output pixel of tile (n, ty0, tx0): the 32 x 32
+// output pixels written row by row (store j of lane i: pixel j * 256 + i),
+// so that each store covers whole 512-byte output rows.
+__device__ __forceinline__ void clear_tile(int n, int H, int W, int ty0, int tx0,
+                                           float4* __restrict__ out, float* __restrict__ err) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = j * 256 + (int)threadIdx.x;
+    const int oy = 2 * ty0 + e / (2 * kTile), ox = 2 * tx0 + e % (2 * kTile);
+    if (oy < 2 * H && ox < 2 * W) {
+      const int64_t q = ((int64_t)n * 2 * H + oy) * (2 * W) + ox;
+      out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (err) err[q] = 0.f;
+    }
+  }
+}
+
+// LDS (kFusedLds bytes): U, V, then x0's rgba (bf16-rounded) on the tile and
+// a 1-pixel ring for the bilinear base of the last phase, then the reduction
+// scratch, which also holds x0's nonzero flags and their 9-wide row maxima
+// until the last phase.
+extern __shared__ float4 fused_smem[];  // the dynamic LDS of the fused kernel
+
+struct FusedLds {
+  bf16* sU;
+  bf16* sV;
+  float4* sX;
+  double* red;
+  uint8_t* nzf;
+  uint8_t* rowany;
+};
+__device__ __forceinline__ FusedLds fused_lds(float4* smem) {
+  FusedLds l;
+  l.sU = reinterpret_cast<bf16*>(smem);
+  l.sV = l.sU + kBufU;
+  l.sX = reinterpret_cast<float4*>(l.sV + kBufV);
+  l.red = reinterpret_cast<double*>(l.sX + kE1 * kE1);
+  l.nzf = reinterpret_cast<uint8_t*>(l.red);
+  l.rowany = l.nzf + kE0 * kE0;
+  return l;
+}
+static_assert(kE0 * kE0 + kE0 * kTile <= 256 * 8, "flags fit the scratch");
+
+// One workgroup per 16 x 16 tile (grid: tiles x, tiles y, images).
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
+fused_forward_kernel(
+    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
+    float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
+    const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
+    const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
+    float4* __restrict__ out, float* __restrict__ err, SumArgs sums) {
+  const FusedLds l = fused_lds(fused_smem);
+  const int n = blockIdx.z;
+  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+  const int64_t slot = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
+  load_weights<8>(w0, wa);
+  const bool any_nz = prep_region(rgba, depth, H, W, inv_scale, n, ty0, tx0, l.sV, l.nzf, l.sX);
   const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
   const int y = ty0 + qy, x = tx0 + qx;
-  float zsum = 0.f;
   if (!__syncthreads_or(any_nz)) {
     // the whole region is empty: every pixel of the tile is background, and
-    // the tile's partial sum is zero. The 32 x 32 output pixels are written
-    // row by row (store j of lane i: pixel j * 256 + i), so that each store
-    // covers whole 512-byte output rows.
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = j * 256 + (int)threadIdx.x;
-      const int oy = 2 * ty0 + e / (2 * kTile), ox = 2 * tx0 + e % (2 * kTile);
-      if (oy < 2 * H && ox < 2 * W) {
-        const int64_t q = ((int64_t)n * 2 * H + oy) * (2 * W) + ox;
-        out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (err) err[q] = 0.f;
-      }
-    }
-    if (sums.sum && threadIdx.x == 0)
-      sums.sum[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = 0.0;
+    // the tile's partial sum is zero
+    clear_tile(n, H, W, ty0, tx0, out, err);
+    if (sums.sum && threadIdx.x == 0) sums.sum[slot] = 0.0;
     return;
   }
-  zsum = fused_tile(sU, sV, sX, nzf, rowany, wa, wb, wc, w1, w2, w3, b0, b1, b2, b3, n, H, W,
-                    ty0, tx0, qy, qx, y, x, out, err);
-  if (sums.sum) tile_partial(sums, red, zsum);
+  const float zsum = fused_tile(l.sU, l.sV, l.sX, l.nzf, l.rowany, wa, wb, wc, w1, w2, w3, b0,
+                                b1, b2, b3, n, H, W, ty0, tx0, qy, qx, y, x, out, err);
+  if (sums.sum) tile_partial(sums, l.red, zsum, slot);
 }
+
 
 // Training loss and its gradient with respect to o (bf16, 32 channels,
 // zeros beyond the 20 used): per low-resolution pixel, its four
@@ -1036,17 +1066,18 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
     const dim3 grid((unsigned)((w + kTile - 1) / kTile), (unsigned)((h + kTile - 1) / kTile),
                     (unsigned)n);
     sa.tiles = (int32_t)(grid.x * grid.y);
+    const float4* in4 = reinterpret_cast<const float4*>(rgba);
+    const bf16x8* fw0 = reinterpret_cast<const bf16x8*>(up->fw[0]);
+    const bf16x8* fw1 = reinterpret_cast<const bf16x8*>(up->fw[1]);
+    const bf16x8* fw2 = reinterpret_cast<const bf16x8*>(up->fw[2]);
+    const bf16x8* fw3 = reinterpret_cast<const bf16x8*>(up->fw[3]);
+    const float *b0 = b + layer_off(0) + 9 * 8 * kCh, *b1 = b + layer_off(1) + 9 * 32 * kCh,
+                *b2 = b + layer_off(2) + 9 * 32 * kCh, *b3 = b + layer_off(3) + 9 * 32 * kCh;
     SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fused_forward_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds));
-    hipLaunchKernelGGL(fused_forward_kernel, grid, dim3(256), kFusedLds, s,
-                       reinterpret_cast<const float4*>(rgba), depth, n, h, w,
-                       (float)(1.0 / depth_scale), reinterpret_cast<const bf16x8*>(up->fw[0]),
-                       reinterpret_cast<const bf16x8*>(up->fw[1]),
-                       reinterpret_cast<const bf16x8*>(up->fw[2]),
-                       reinterpret_cast<const bf16x8*>(up->fw[3]), b + layer_off(0) + 9 * 8 * kCh,
-                       b + layer_off(1) + 9 * 32 * kCh, b + layer_off(2) + 9 * 32 * kCh,
-                       b + layer_off(3) + 9 * 32 * kCh, reinterpret_cast<float4*>(out_rgba),
-                       out_err, sa);
+    hipLaunchKernelGGL(fused_forward_kernel, grid, dim3(256), kFusedLds, s, in4, depth, n, h, w,
+                       (float)(1.0 / depth_scale), fw0, fw1, fw2, fw3, b0, b1, b2, b3,
+                       reinterpret_cast<float4*>(out_rgba), out_err, sa);
     if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sa);
     SG_HIP(hipGetLastError());
   } else {

@@ -463,3 +463,4 @@ def x0_reference_of(rgba, depth):
     x0[..., :4] = U.to_bf16(rgba)
     x0[..., 4] = U.to_bf16(code)
     return x0
+
