@@ -28,6 +28,7 @@ def lib():
         if not os.path.exists(_LIB):
             from . import build
             build.build()
+        import torch  # noqa: F401  -- torch's HIP runtime first: see paper_1804_08197_amd/sg.py
         L = C.CDLL(_LIB)
         vp = C.c_void_p
         L.sggen_tubes.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32,

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SG_ABI_VERSION 2
+#define SG_ABI_VERSION 3
 
 typedef enum {
   SG_OK = 0,
@@ -120,7 +120,10 @@ typedef struct {
  * (bx, by) holds pixels 8 bx .. 8 bx + 7, 8 by .. 8 by + 7): 1 if any of its
  * pixels has a nonzero output RGBA (background included) or, when depth is
  * written, a finite depth; else 0: a content mask of the image for passes
- * that run over it later. */
+ * that run over it later. The mask describes the pixels of each block only:
+ * a consumer whose output at a pixel depends on neighbouring pixels (a
+ * filter or a network with a receptive field) must dilate it by that reach
+ * itself. */
 typedef struct {
   double cam_to_world[16];
   double tan_left, tan_right, tan_bottom, tan_top;
@@ -164,14 +167,17 @@ typedef struct {
   uint64_t staged_bytes;   /* out: bytes copied from the pool into LDS       */
 } sg_render_stats;
 
-/* Create a volume on desc->device: allocates the brick pool for every
- * channel, timepoint and node, the page table (node -> pool slot) and the
- * per-node value ranges. The pool starts zeroed.
+/* Create a volume on desc->device (Sec 4.2: the GPU-side store of volume
+ * chunks; Sec 5.2: blocks of every level of the multi-resolution pyramid):
+ * allocates the brick pool for every channel, timepoint and node (or
+ * cache_slots slots), the page table (node -> pool slot) and the per-node
+ * value ranges. The pool starts zeroed.
  * Errors: SG_ERR_INVALID_ARG (bad desc, out NULL), SG_ERR_OUT_OF_MEMORY,
  * SG_ERR_DEVICE. On success *out owns all of it until sg_volume_destroy. */
 sg_status sg_volume_create(const sg_volume_desc *desc, sg_volume **out);
 
-/* Release every device allocation of vol (after synchronising its device). */
+/* Release every device allocation of vol (after synchronising its device):
+ * the end of the GPU store of Sec 4.2. vol must not be used afterwards. */
 sg_status sg_volume_destroy(sg_volume *vol);
 
 /* Upload n brick cores of one (channel, timepoint, level) into the pool
@@ -195,10 +201,14 @@ sg_status sg_upload_bricks(sg_volume *vol, int32_t channel, int32_t timepoint,
 sg_status sg_build_lod(sg_volume *vol, int32_t channel, int32_t timepoint,
                        void *hip_stream);
 
-/* Finish pending uploads/builds on the device: fill every brick's apron
- * (and out-of-extent core voxels) with clamped neighbour values, recompute
+/* Finish pending uploads/builds on the device (Sec 5.2: every block of the
+ * pyramid samples on its own, so each carries the neighbour voxels its
+ * trilinear stencils reach; Sec 5.1: blocks whose opacity is zero under the
+ * transfer function contribute nothing): fill every brick's apron (and
+ * out-of-extent core voxels) with clamped neighbour values, recompute
  * per-brick min/max, and recompute empty-node flags. sg_render_views calls
- * this itself when something is pending. */
+ * this itself when something is pending. Errors: SG_ERR_INVALID_ARG (vol
+ * NULL), SG_ERR_DEVICE. Asynchronous on hip_stream. */
 sg_status sg_volume_commit(sg_volume *vol, void *hip_stream);
 
 /* Set the transfer function of a channel (Sec 5.1 tau and T; Sec 8):
@@ -420,6 +430,38 @@ sg_status sg_cache_get_info(const sg_volume *vol, sg_cache_info *info);
  * 1 or 0. */
 sg_status sg_cache_resident(const sg_volume *vol, int32_t channel, int32_t timepoint,
                             int32_t level, const int32_t b[3], int32_t *resident);
+
+/* ---------------------------------------------------------------------
+ * Import of an out-of-core volume (Sec 4.1: chunks of the volume made once
+ * at several resolutions; Sec 4.2: chunks move whole between the CPU and GPU
+ * caches). These work on plain device arrays of voxels of type dtype
+ * (SG_U8 or SG_U16), x fastest (indexed [z][y][x]), need no volume and run
+ * on the current device, asynchronously on hip_stream. */
+/* One coarser level of the resolution pyramid (Sec 5.2): src has src_dims
+ * voxels (each in [1, 2^20]); dst receives ceil(src_dims / 2) voxels, voxel
+ * g = (sum of the 2x2x2 children 2g + delta, each child index clamped to
+ * src_dims - 1, + 4) >> 3 -- the rule sg_build_lod applies to a resident
+ * volume. src and dst are caller-owned device buffers and must not overlap.
+ * Errors: SG_ERR_INVALID_ARG (NULL pointer, bad dtype or dims, overlap),
+ * SG_ERR_DEVICE. */
+sg_status sg_pyramid_level(int32_t dtype, const int32_t src_dims[3], const void *src,
+                           void *dst, void *hip_stream);
+/* Whole bricks of one level in the form sg_cache_put takes: out receives n
+ * regions of (brick+2)^3 voxels, x fastest; region i holds the level's
+ * voxels brick*b_i - 1 .. brick*b_i + brick per axis with indices clamped
+ * to [0, dims - 1] (the core and its one-voxel apron).
+ *   dims  : host int32 [3], the level's voxels per axis, each in [1, 2^20]
+ *   level : device array of the level
+ *   brick : core edge, a power of two in [2, 256]
+ *   coords: host int32 [n][3] brick indices (bx, by, bz), each inside the
+ *           level's brick grid ceil(dims / brick); consumed before return
+ *   out   : device buffer of n (brick+2)^3 voxels, caller-owned
+ * n = 0 does nothing. Errors: SG_ERR_INVALID_ARG (NULL pointer, bad dtype,
+ * dims or brick, n < 0, a coordinate outside the grid),
+ * SG_ERR_OUT_OF_MEMORY / SG_ERR_DEVICE (staging of the coordinates). */
+sg_status sg_brick_regions(int32_t dtype, const int32_t dims[3], const void *level,
+                           int32_t brick, int32_t n, const int32_t *coords, void *out,
+                           void *hip_stream);
 
 /* Bytes of device memory the volume holds (pool, tables, scratch). */
 sg_status sg_volume_memory(const sg_volume *vol, uint64_t *bytes);

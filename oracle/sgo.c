@@ -497,12 +497,11 @@ int64_t sgo_lod_cut(const int32_t dims0[3], int32_t B, int32_t levels,
   return c.n;
 }
 
-/* O18: the cut when only some nodes are in the GPU cache (Sec 5.2: if one
- * or more children of a block that does not suit are missing from the cache,
- * they are added to the request queue and the block itself, one level
- * coarser, is rendered). The traversal above with one change: a node that
- * does not suit descends only when every existing child is resident;
- * otherwise it is registered and its missing children are requested.
+/* O18: the cut when only some nodes are in the GPU cache (Sec 5.2). The
+ * traversal above with one change: a node that is too coarse for the view
+ * descends only if all of its existing children are resident; otherwise the
+ * node itself is drawn, one level coarser than wanted, and the children that
+ * are absent are recorded as requests for the loader.
  * `resident` is the ascending list of resident node identifiers; every
  * top-level node must be in it (returns -2 otherwise). The requested
  * identifiers (ascending, without repeats) go to req (first req_cap),

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libsg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "volume.hip", "lod.hip", "cache.hip", "raycast.hip", "raycast_ea.hip",
-           "raycast_eo.hip", "raycast_mip.hip", "upsampler.hip", "composite.hip"]
+           "raycast_eo.hip", "raycast_mip.hip", "upsampler.hip", "composite.hip", "bricks.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

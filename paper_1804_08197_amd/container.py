@@ -3,19 +3,20 @@
 Sec 4.1 stores a volume as chunks at several resolutions, made once at
 import; Sec 4.2 keeps recently used chunks in a GPU cache and Sec 5.2 loads
 the blocks a render asks for. This module is that import step and loader
-for a cache volume (``sg_volume_create(..., cache_slots=...)``):
+for a cache volume (``sg_volume_create(..., cache_slots=...)``); the voxel
+work runs in the library, this module allocates, calls and copies:
 
-* ``build_levels`` makes the resolution pyramid of a level-0 array: each
-  coarser voxel is the rounded mean (sum + 4) >> 3 of its 2x2x2 children,
-  with child indices clamped at the far faces (the same rule the device
-  pyramid builder applies);
-* ``brick_regions`` cuts whole bricks out of a level: the core plus a
-  one-voxel apron, indices clamped at the volume border, x fastest;
+* ``build_levels`` makes the resolution pyramid of a level-0 array on the
+  device, one ``sg_pyramid_level`` call per level;
+* ``brick_regions`` cuts whole bricks (core plus a one-voxel apron) out of a
+  level with ``sg_brick_regions``;
 * ``BrickSource`` holds the pyramids of every (timepoint, channel) and
-  answers the cache's request list with ``sg_cache_put`` calls.
+  answers the cache's request list with ``sg_cache_put`` calls;
+* ``HostBrickStore`` keeps every brick in page-locked host memory (the CPU
+  tier) and answers requests with ``sg_cache_put_scattered``.
 
-Arrays are numpy (host) or torch tensors (device); all arithmetic is
-integer, so host and device pyramids agree exactly.
+Arrays are torch tensors [z, y, x] of 8- or 16-bit voxels; numpy inputs are
+moved to the current device first.
 """
 from __future__ import annotations
 
@@ -26,56 +27,43 @@ import numpy as np
 from . import sg
 
 
-def _next_level(a):
-    """One pyramid step of a [z, y, x] array (numpy or torch)."""
-    if isinstance(a, np.ndarray):
-        w = a.astype(np.uint32)
-        pad = [(0, s % 2) for s in w.shape]
-        w = np.pad(w, pad, mode="edge")
-        z, y, x = (s // 2 for s in w.shape)
-        s = w.reshape(z, 2, y, 2, x, 2).sum(axis=(1, 3, 5))
-        return ((s + 4) >> 3).astype(a.dtype)
+def _on_device(a):
+    """A contiguous device tensor holding a (numpy or torch) voxel array."""
     import torch
-    u16 = a.dtype == torch.uint16  # few device kernels take uint16: go through int16 bits
-    w = (a.view(torch.int16).to(torch.int32) & 0xFFFF) if u16 else a.to(torch.int32)
-    pz, py, px = (s % 2 for s in w.shape)
-    if pz or py or px:
-        w = torch.nn.functional.pad(w[None, None].float(), (0, px, 0, py, 0, pz),
-                                    mode="replicate")[0, 0].to(torch.int32)
-    z, y, x = (s // 2 for s in w.shape)
-    s = w.reshape(z, 2, y, 2, x, 2).sum(dim=(1, 3, 5))
-    m = (s + 4) >> 3
-    return m.to(torch.int16).view(torch.uint16) if u16 else m.to(a.dtype)
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint16:  # moved as int16 bits: the copy kernels take either
+            return torch.from_numpy(a.view(np.int16)).cuda().view(torch.uint16)
+        return torch.from_numpy(a).cuda()
+    if not a.is_cuda:
+        if a.dtype == torch.uint16:
+            return a.view(torch.int16).contiguous().cuda().view(torch.uint16)
+        return a.contiguous().cuda()
+    return a.contiguous()
 
 
-def build_levels(vol0, levels: int):
-    """[level-0, level-1, ...] arrays of the pyramid."""
-    out = [vol0]
+def build_levels(vol0, levels: int, stream=None):
+    """[level-0, level-1, ...] device tensors of the pyramid of vol0."""
+    import torch
+    out = [_on_device(vol0)]
     for _ in range(1, levels):
-        out.append(_next_level(out[-1]))
+        src = out[-1]
+        dst = torch.empty([-(-int(n) // 2) for n in src.shape], dtype=src.dtype,
+                          device=src.device)
+        sg.sg_pyramid_level(src, dst, stream=stream)
+        out.append(dst)
     return out
 
 
-def brick_regions(level, brick: int, coords):
-    """Regions [n, B+2, B+2, B+2] of the bricks coords [n, 3] = (bx, by, bz):
-    voxels B*b - 1 .. B*b + B per axis, clamped to the level."""
-    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 3)
-    B = int(brick)
-    nz, ny, nx = level.shape
-    r = np.arange(-1, B + 1)
-    ix = np.clip(coords[:, 0:1] * B + r[None, :], 0, nx - 1)
-    iy = np.clip(coords[:, 1:2] * B + r[None, :], 0, ny - 1)
-    iz = np.clip(coords[:, 2:3] * B + r[None, :], 0, nz - 1)
-    if isinstance(level, np.ndarray):
-        return np.ascontiguousarray(level[iz[:, :, None, None], iy[:, None, :, None],
-                                          ix[:, None, None, :]])
+def brick_regions(level, brick: int, coords, stream=None):
+    """Device tensor [n, B+2, B+2, B+2] of the bricks coords [n, 3] =
+    (bx, by, bz) of a level (a device tensor [z, y, x])."""
     import torch
-    dev = level.device
-    tz, ty, tx = (torch.from_numpy(a).to(dev) for a in (iz, iy, ix))
-    # gathers do not take uint16 on the device: index the same bits as int16
-    src = level.view(torch.int16) if level.dtype == torch.uint16 else level
-    out = src[tz[:, :, None, None], ty[:, None, :, None], tx[:, None, None, :]].contiguous()
-    return out.view(torch.uint16) if level.dtype == torch.uint16 else out
+    coords = np.asarray(coords, dtype=np.int32).reshape(-1, 3)
+    S = int(brick) + 2
+    out = torch.empty((len(coords), S, S, S), dtype=level.dtype, device=level.device)
+    sg.sg_brick_regions(level, brick, coords, out, stream=stream)
+    return out
 
 
 def decode_ids(ids):
@@ -214,8 +202,6 @@ class HostBrickStore:
             while i < len(coords):
                 chunk, first, m = self._slots(min(batch, len(coords) - i))
                 reg = brick_regions(arr, self.B, coords[i:i + m])
-                if isinstance(reg, np.ndarray):
-                    reg = torch.from_numpy(reg)
                 off = first * self.region_bytes
                 dst = chunk[off:off + m * self.region_bytes].view(dt).view(m, S, S, S)
                 dst.copy_(reg)

@@ -93,8 +93,13 @@ extern "C" sg_status sg_composite_over(const sg_view* view, int32_t n_parts,
   if (st != SG_OK) return st;
   const int64_t npix = (int64_t)V.W * V.H;
   const int64_t blocks = std::min<int64_t>((npix + 255) / 256, 65536);
-  hipLaunchKernelGGL(composite_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     (hipStream_t)hip_stream, V, P, reinterpret_cast<float4*>(out_rgba));
-  SG_HIP(hipGetLastError());
+  // the caller's current device, selected explicitly for this thread
+  int dev = 0;
+  SG_HIP(hipGetDevice(&dev));
+  SG_HIP(hipSetDevice(dev));
+  float4* out = reinterpret_cast<float4*>(out_rgba);
+  void* pa[] = {&V, &P, &out};
+  SG_HIP(hipLaunchKernel(reinterpret_cast<const void*>(composite_kernel), dim3((unsigned)blocks),
+                         dim3(256), pa, 0, (hipStream_t)hip_stream));
   return SG_OK;
 }

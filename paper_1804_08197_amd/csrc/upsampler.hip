@@ -229,58 +229,51 @@ __device__ bool empty_neighbourhood(const bf16* x0, int n, int H, int W, int y, 
   return true;
 }
 
-// Inference epilogue: full-resolution rgba and predicted squared error; the
-// per-image sum of the prediction accumulates in mse_sum[n] (doubles).
+// Inference epilogue: full-resolution rgba and predicted squared error.
+// Grid: x = 256-pixel chunks of one image, y = images (strided). With
+// partials, each workgroup writes its chunk's sum of the prediction to
+// partials[image * gridDim.x + chunk] (a fixed-order tree sum: the result
+// does not depend on scheduling); tile_sum_kernel adds them per image.
 __global__ __launch_bounds__(256) void shuffle_kernel(const float* o, const bf16* x0, int N, int H,
                                                       int W, float4* out, float* err,
-                                                      double* mse_sum) {
-  const int64_t P = (int64_t)N * H * W;
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  float zsum = 0.f;
-  int n = 0;
-  if (p < P) {
-    n = (int)(p / ((int64_t)H * W));
-    const int r = (int)(p - (int64_t)n * H * W), y = r / W, x = r - y * W;
-    const float* op = o + p * kCh;
-    const bool empty = empty_neighbourhood(x0, n, H, W, y, x);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int sy = s >> 1, sx = s & 1;
-      const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
-      if (empty) {  // background, and no predicted error
-        out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (err) err[q] = 0.f;
-        continue;
-      }
-      const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
-      out[q] = make_float4(b.x + op[5 * s], b.y + op[5 * s + 1], b.z + op[5 * s + 2],
-                           b.w + op[5 * s + 3]);
-      const float z = op[5 * s + 4];
-      if (err) err[q] = z * z;
-      zsum += z * z;
-    }
-  }
-  if (!mse_sum) return;
-  // block sums for the block's first image and the next one; other images
-  // (tiny images) add per thread
+                                                      double* partials) {
+  __shared__ double red[256];
   const int64_t HW = (int64_t)H * W;
-  const int nf = (int)(((int64_t)blockIdx.x * blockDim.x) / HW);
-  __shared__ double r0[256], r1[256];
-  const bool in = p < P;
-  r0[threadIdx.x] = in && n == nf ? (double)zsum : 0.0;
-  r1[threadIdx.x] = in && n == nf + 1 ? (double)zsum : 0.0;
-  if (in && n > nf + 1) atomicAdd(mse_sum + n, (double)zsum);
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      r0[threadIdx.x] += r0[threadIdx.x + s];
-      r1[threadIdx.x] += r1[threadIdx.x + s];
+  for (int n = blockIdx.y; n < N; n += gridDim.y) {
+    const int64_t r0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    float zsum = 0.f;
+    if (r0 < HW) {
+      const int r = (int)r0, y = r / W, x = r - y * W;
+      const int64_t p = (int64_t)n * HW + r;
+      const float* op = o + p * kCh;
+      const bool empty = empty_neighbourhood(x0, n, H, W, y, x);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int sy = s >> 1, sx = s & 1;
+        const int64_t q = ((int64_t)n * 2 * H + 2 * y + sy) * (2 * W) + 2 * x + sx;
+        if (empty) {  // background, and no predicted error
+          out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (err) err[q] = 0.f;
+          continue;
+        }
+        const float4 b = base_rgba(x0, n, H, W, y, x, sy, sx);
+        out[q] = make_float4(b.x + op[5 * s], b.y + op[5 * s + 1], b.z + op[5 * s + 2],
+                             b.w + op[5 * s + 3]);
+        const float z = op[5 * s + 4];
+        if (err) err[q] = z * z;
+        zsum += z * z;
+      }
     }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (nf < N) atomicAdd(mse_sum + nf, r0[0]);
-    if (nf + 1 < N) atomicAdd(mse_sum + nf + 1, r1[0]);
+    if (partials) {  // uniform across the workgroup
+      red[threadIdx.x] = (double)zsum;
+      __syncthreads();
+      for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) partials[(int64_t)n * gridDim.x + blockIdx.x] = red[0];
+      __syncthreads();
+    }
   }
 }
 
@@ -456,14 +449,14 @@ __device__ __forceinline__ void fused_layer(const bf16* __restrict__ sin, void* 
 // one partial per workgroup (no atomics: device-wide atomics on one address
 // serialise across the XCDs); tile_sum_kernel then adds each image's
 // partials in a fixed order (deterministic), and takes the fallback
-// decision if asked. The layer-by-layer path adds into zeroed sums directly
-// and finish_kernel copies them out.
+// decision if asked. The layer-by-layer path's epilogue writes one partial
+// per 256-pixel chunk of an image and is summed the same way.
 struct SumArgs {
-  double* sum;        // fused: [workgroups] partials; layered: [N] sums
+  double* sum;        // [images][tiles] partials (fused: tiles; layered: 256-pixel chunks)
   double* result;     // [N] per-image sums of this launch
   int32_t* fallback;  // NULL, or the frame's decision (predicted PSNR < threshold)
   int32_t images;     // N
-  int32_t tiles;      // fused: workgroups per image
+  int32_t tiles;      // partials per image
   double pixels;      // full-resolution pixels per image
   double threshold_db;
 };
@@ -850,22 +843,6 @@ __global__ void reduce_kernel(const float* part, int blocks, int64_t n, float* g
   }
 }
 
-// x[0 .. n) = 0 (a kernel rather than a memset: safe inside captured graphs)
-__global__ void zero_kernel(double* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = 0.0;
-}
-
-// The layer-by-layer path's end of a launch (one workgroup, after the
-// epilogue has added the sums): the results and the decision.
-__global__ void finish_kernel(SumArgs a) {
-  for (int i = threadIdx.x; i < a.images; i += blockDim.x) a.result[i] = a.sum[i];
-  __syncthreads();
-  if (threadIdx.x == 0 && a.fallback)
-    *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
-}
-
 // Adam on the FP32 master weights.
 __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
                             float c1, float c2) {
@@ -1040,8 +1017,8 @@ sg_status gradients(sg_upsampler* u, int n, int h, int w, const float* rgba, con
 
 // Inference into out_rgba / out_err; with sums, the per-image sums of the
 // predicted squared error end up in acc[1 + max_pixels ..] (and, with a
-// fallback flag, the frame's decision in *fallback), the sums themselves
-// cleared again for the next launch.
+// fallback flag, the frame's decision in *fallback), added in a fixed order
+// from per-workgroup partials that every launch overwrites.
 sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
                 const float* depth, double depth_scale, float* out_rgba, float* out_err,
                 bool sums, int32_t* fallback, double threshold_db, hipStream_t s) {
@@ -1053,7 +1030,7 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
   if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
   SumArgs sa{};
   if (sums) {
-    sa.sum = up->acc + 1;  // per-workgroup partials (fused) or per-image sums (layered)
+    sa.sum = up->acc + 1;  // per-workgroup partials
     sa.result = up->acc + 1 + up->max_pixels;
     sa.fallback = fallback;
     sa.images = n;
@@ -1082,12 +1059,14 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
     SG_HIP(hipGetLastError());
   } else {
     if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
-    const int64_t P = (int64_t)n * h * w;
-    if (sums)
-      hipLaunchKernelGGL(zero_kernel, dim3(blocks_of(n)), dim3(256), 0, s, sa.sum, (int64_t)n);
-    hipLaunchKernelGGL(shuffle_kernel, dim3(blocks_of(P)), dim3(256), 0, s, up->o, up->x0, n, h,
-                       w, reinterpret_cast<float4*>(out_rgba), out_err, sa.sum);
-    if (sums) hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, sa);
+    // chunks of 256 pixels per image: n * chunks <= n * h * w <= max_pixels
+    // partial slots
+    const int64_t chunks = ((int64_t)h * w + 255) / 256;
+    sa.tiles = (int32_t)chunks;
+    const dim3 grid((unsigned)chunks, (unsigned)std::min<int32_t>(n, 65535));
+    hipLaunchKernelGGL(shuffle_kernel, grid, dim3(256), 0, s, up->o, up->x0, n, h, w,
+                       reinterpret_cast<float4*>(out_rgba), out_err, sums ? sa.sum : nullptr);
+    if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sa);
     SG_HIP(hipGetLastError());
   }
   return SG_OK;

@@ -26,7 +26,7 @@ SG_LOD, SG_SKIP_EMPTY, SG_GATHER = 1, 2, 4
 SG_MODEL_EMISSION_ABSORPTION, SG_MODEL_EMISSION_ONLY, SG_MODEL_MAX_INTENSITY = 0, 1, 2
 MODELS = {"ea": SG_MODEL_EMISSION_ABSORPTION, "eo": SG_MODEL_EMISSION_ONLY,
           "mip": SG_MODEL_MAX_INTENSITY}
-SG_ABI_VERSION = 2
+SG_ABI_VERSION = 3
 
 
 class SgError(RuntimeError):
@@ -75,6 +75,13 @@ class sg_launch_config(C.Structure):
 if not os.path.exists(LIB_PATH):
     raise ImportError("libsg.so is not built (run __graft_entry__.build()); there is no "
                       "fallback implementation")
+# torch ships its own HIP runtime (libamdhip64.so, found through its RPATH).
+# It must be loaded before libsg.so: the library then binds to that same
+# runtime (same soname) and shares torch's devices, streams and memory.
+# Loaded the other way round, the process would hold two HIP runtimes and
+# the library would receive pointers and streams it cannot use.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _lib.sg_volume_create.argtypes = [C.POINTER(sg_volume_desc), C.POINTER(_P)]
@@ -121,6 +128,9 @@ _lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int3
 _lib.sg_cache_get_info.argtypes = [_P, C.POINTER(sg_cache_info)]
 _lib.sg_cache_resident.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32)]
+_lib.sg_pyramid_level.argtypes = [C.c_int32, C.POINTER(C.c_int32), _P, _P, _P]
+_lib.sg_brick_regions.argtypes = [C.c_int32, C.POINTER(C.c_int32), _P, C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_int32), _P, _P]
 _lib.sg_status_string.argtypes = [C.c_int]
 _lib.sg_status_string.restype = C.c_char_p
 _lib.sg_last_error.restype = C.c_char_p
@@ -132,7 +142,7 @@ for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_buil
            "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
            "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy",
            "sg_cache_put", "sg_cache_put_scattered", "sg_cache_requests", "sg_cache_get_info",
-           "sg_cache_resident", "sg_render_views_if"):
+           "sg_cache_resident", "sg_render_views_if", "sg_pyramid_level", "sg_brick_regions"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -508,6 +518,44 @@ def sg_cache_requests(vol, stream=None):
                                   _stream(stream)), "sg_cache_requests")
     return ids[:n.value], tps[:n.value]
 
+
+
+# ------------------------------------------------------- out-of-core import
+def _voxel_dtype(t) -> int:
+    if t.element_size() == 1:
+        return SG_U8
+    if t.element_size() == 2:
+        return SG_U16
+    raise ValueError("voxel arrays are 8- or 16-bit")
+
+
+def sg_pyramid_level(src, dst, stream=None):
+    """One coarser pyramid level: src and dst are contiguous device tensors
+    [z, y, x] of 8- or 16-bit voxels, dst of shape ceil(src.shape / 2)."""
+    want = tuple(-(-int(n) // 2) for n in src.shape)
+    if tuple(dst.shape) != want or dst.element_size() != src.element_size():
+        raise ValueError("dst must have shape %s and src's voxel size" % (want,))
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous")
+    dims = (C.c_int32 * 3)(*[int(n) for n in src.shape[::-1]])
+    _check(_lib.sg_pyramid_level(_voxel_dtype(src), dims, _ptr(src), _ptr(dst),
+                                 _stream(stream)), "sg_pyramid_level")
+
+
+def sg_brick_regions(level, brick, coords, out, stream=None):
+    """Whole bricks (core plus one-voxel apron, clamped) of the device level
+    tensor [z, y, x] at coords [n, 3] = (bx, by, bz) into the device tensor
+    out [n, B+2, B+2, B+2]."""
+    coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
+    S = int(brick) + 2
+    if tuple(out.shape) != (len(coords), S, S, S) or out.element_size() != level.element_size():
+        raise ValueError("out must be [n, B+2, B+2, B+2] of the level's voxel size")
+    if not (level.is_contiguous() and out.is_contiguous()):
+        raise ValueError("level and out must be contiguous")
+    dims = (C.c_int32 * 3)(*[int(n) for n in level.shape[::-1]])
+    _check(_lib.sg_brick_regions(_voxel_dtype(level), dims, _ptr(level), int(brick), len(coords),
+                                 coords.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(out),
+                                 _stream(stream)), "sg_brick_regions")
 
 def sg_cache_get_info(vol) -> dict:
     o = sg_cache_info()

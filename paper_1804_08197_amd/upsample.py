@@ -60,6 +60,8 @@ class Trainer:
     def __init__(self, vol, model: "up.Upsampler", depth_scale: float, base_params: dict,
                  crop=256, batch=16, lod=False):
         import torch
+        if int(crop) < 2 or int(crop) % 2:
+            raise ValueError("the crop must be even: the network upsamples by exactly 2")
         self.vol, self.model = vol, model
         self.depth_scale = float(depth_scale)
         self.p_full, self.p_half = render_params(base_params, lod)
@@ -75,6 +77,8 @@ class Trainer:
         vf, vh = [], []
         for i in range(self.batch):
             v = poses[int(rng.integers(len(poses)))]
+            if v["width"] < self.crop or v["height"] < self.crop:
+                raise ValueError("a training pose is smaller than the crop")
             x0 = 2 * int(rng.integers(0, (v["width"] - self.crop) // 2 + 1))
             y0 = 2 * int(rng.integers(0, (v["height"] - self.crop) // 2 + 1))
             vf.append(crop_view(v, x0, y0, self.crop, self.crop))
@@ -95,6 +99,9 @@ class UpsampledPath:
                  width: int, height: int, n_views: int = 2, threshold_db: float = 40.0,
                  lod=False):
         import torch
+        if int(width) < 2 or int(height) < 2 or int(width) % 2 or int(height) % 2:
+            raise ValueError("width and height must be even: the network writes rows of "
+                             "2 x (width // 2) pixels")
         self.vol, self.model = vol, model
         self.depth_scale = float(depth_scale)
         self.p_full, self.p_half = render_params(base_params, lod)
@@ -103,11 +110,18 @@ class UpsampledPath:
         self.rgba_lo = torch.empty(n_views, h2, w2, 4, device="cuda")
         self.depth_lo = torch.empty(n_views, h2, w2, device="cuda")
         self.out = torch.empty(n_views, height, width, 4, device="cuda")
+        self.size = (int(width), int(height), int(n_views))
         self._structs = None
+
+    def _check(self, views):
+        w, h, n = self.size
+        if len(views) != n or any(v["width"] != w or v["height"] != h for v in views):
+            raise ValueError("this path renders %d views of %d x %d pixels" % (n, w, h))
 
     def predicted_psnr(self, views):
         """Half-resolution render and network pass; returns the predicted
         PSNR of the frame (all views together)."""
+        self._check(views)
         sg.sg_render_views(self.vol, [half_view(v) for v in views], self.p_half,
                            list(self.rgba_lo), list(self.depth_lo))
         mse = self.model.forward(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
@@ -127,6 +141,7 @@ class UpsampledPath:
         """The same frame with the decision taken on the device, without a
         host round trip: flag (one-element int32 device tensor) receives 1
         when the frame fell back. Asynchronous; returns the images."""
+        self._check(views)
         if self._structs is None:  # built once: the per-frame calls only pack views
             self._structs = (sg.make_params(self.p_half), sg.make_params(self.p_full),
                              list(self.rgba_lo), list(self.depth_lo), list(self.out))

@@ -92,7 +92,7 @@ int main(void) {
 
 
 def test_version_and_status_strings(sg):
-    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 2
+    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 3
     for code, name in [(0, "SG_OK"), (-1, "SG_ERR_INVALID_ARG"), (-2, "SG_ERR_OUT_OF_MEMORY"),
                        (-3, "SG_ERR_DEVICE"), (-4, "SG_ERR_STATE"), (-5, "SG_ERR_UNSUPPORTED")]:
         assert sg.sg_status_string(code) == name
@@ -182,3 +182,38 @@ def test_composite_argument_checks_need_no_device(sg):
     assert call(2, [[0, 0, 0, 16, 32, 32], [16, 0, np.nan, 32, 32, 32]]) == sg.SG_ERR_INVALID_ARG
     assert call(2, good, arr=(C.c_void_p * 2)(base, base + 4)) == sg.SG_ERR_INVALID_ARG
     assert call(2, good, o=C.c_void_p(base + 8)) == sg.SG_ERR_INVALID_ARG
+
+
+def test_import_calls_check_arguments_without_a_device(sg):
+    """sg_pyramid_level and sg_brick_regions reject bad dtypes, dims, bricks
+    and coordinates before any device work; n = 0 is a no-op."""
+    lib = sg.lib()
+    dims = (C.c_int32 * 3)(11, 10, 9)
+    p = C.c_void_p(4096)
+    cz = (C.c_int32 * 3)(0, 0, 0)
+    assert lib.sg_pyramid_level(3, dims, p, C.c_void_p(1 << 20), None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_pyramid_level(1, None, p, p, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_pyramid_level(1, (C.c_int32 * 3)(0, 1, 1), p, p, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_pyramid_level(2, dims, None, p, None) == sg.SG_ERR_INVALID_ARG
+    # overlapping source and destination
+    assert lib.sg_pyramid_level(1, dims, p, C.c_void_p(4096 + 100), None) == \
+        sg.SG_ERR_INVALID_ARG
+    assert lib.sg_brick_regions(1, dims, p, 3, 1, cz, p, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_brick_regions(1, dims, p, 4, -1, cz, p, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_brick_regions(1, dims, p, 4, 1, (C.c_int32 * 3)(3, 0, 0), p, None) == \
+        sg.SG_ERR_INVALID_ARG
+    assert lib.sg_brick_regions(1, dims, p, 4, 1, cz, None, None) == sg.SG_ERR_INVALID_ARG
+    assert lib.sg_brick_regions(2, dims, p, 4, 0, None, None, None) == sg.SG_OK
+
+
+def test_binding_shares_torch_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must not load a second HIP
+    runtime: the library would then hold its own runtime and receive
+    torch's pointers and streams from another one."""
+    code = ("from paper_1804_08197_amd import sg\n"
+            "import torch, re\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len(set(re.findall(r'\\S*libamdhip64\\S*', m))))\n")
+    out = subprocess.run(["python", "-c", code], capture_output=True, text=True, cwd=ROOT,
+                         check=True).stdout.split()
+    assert out[-1] == "1"

@@ -292,11 +292,12 @@ def test_scattered_puts_from_the_host_tier_pageable_and_device_memory():
         for c in range(C):
             for L, arr in enumerate(build_levels(vols[0][c], LEVELS)):
                 coords = grid_coords(grids[L])
-                regs = brick_regions(arr, B, coords)
+                regs = brick_regions(arr, B, coords)  # on the device
+                host = regs.view(torch.int16).cpu().numpy().view(np.uint16)
                 # one separate buffer per brick, in reverse order of address
-                bufs = [np.ascontiguousarray(r) for r in regs[::-1]][::-1]
+                bufs = [np.ascontiguousarray(r) for r in host[::-1]][::-1]
                 if c == 1:
-                    bufs = [torch.from_numpy(r).cuda() for r in bufs]
+                    bufs = [regs[i].clone() for i in range(len(regs) - 1, -1, -1)][::-1]
                     addrs = [b.data_ptr() for b in bufs]
                 else:
                     addrs = [b.ctypes.data for b in bufs]

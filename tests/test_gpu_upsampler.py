@@ -142,6 +142,33 @@ def test_fused_inference_equals_the_layered_path(shape):
         u.close()
 
 
+
+def test_layered_predicted_error_is_deterministic():
+    """The layer-by-layer path adds the predicted error in a fixed order
+    (per-chunk partials, then a fixed-order sum): repeated launches give the
+    same per-image sums bit for bit, and the fallback flag agrees with
+    them."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    n, h, w = 3, 61, 77
+    rng = np.random.default_rng(44)
+    rgba = rng.uniform(0, 1, size=(n, h, w, 4)).astype(np.float32)
+    rgba[..., :3] *= rgba[..., 3:4]
+    depth = rng.uniform(0, 300, size=(n, h, w)).astype(np.float32)
+    trgba, tdepth = torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+    u = up.Upsampler(n * h * w)
+    try:
+        u.set_weights(up.pack(bf16_params(rng, 0.5)))
+        u.set_fused(False)
+        out = torch.empty((n, 2 * h, 2 * w, 4), device="cuda")
+        sums = [u.forward(trgba, tdepth, SCALE, out, predict=True) for _ in range(4)]
+        for m in sums[1:]:
+            assert np.array_equal(m, sums[0])
+        assert np.all(sums[0] > 0)
+    finally:
+        u.close()
+
 def test_gradients_match_reference():
     import torch
 
