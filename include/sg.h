@@ -258,6 +258,30 @@ sg_status sg_render_views_if(sg_volume *vol, int32_t n_views, const sg_view *vie
                              float *const *out_depth, const int32_t *enable,
                              void *hip_stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sg_render_views
+ * with every piece of per-render scratch -- the view table, the persistent
+ * grid's tile queues and the per-view cut maps -- in a static device array
+ * of 4 MiB that each GPU the library runs on holds until the process ends.
+ * The call makes no hipMalloc, hipFree or other allocating call; it enqueues
+ * the same kernels as sg_render_views and renders the same image bit for
+ * bit. Limits and requirements:
+ *   - n_views in [1, 4];
+ *   - n_views x (level-0 brick grid cells) x 4 bytes <= 4 MiB - 8 KiB (e.g.
+ *     a 2048^3 volume in 64^3 bricks: 32^3 cells, 128 KiB per view);
+ *     larger requests fail with SG_ERR_INVALID_ARG;
+ *   - the volume must be committed (sg_volume_commit after uploads, pyramid
+ *     builds or transfer-function changes), else SG_ERR_STATE;
+ *   - kernel timing (sg_set_kernel_timing) does not record these renders.
+ * Every call on one GPU uses that GPU's single scratch array, which keeps
+ * the last call's contents (each call rewrites what it reads): calls whose
+ * device work may overlap on one GPU -- on different streams without
+ * ordering between them -- race, and must be serialised by the caller.
+ * Other errors as sg_render_views. Asynchronous on hip_stream. */
+sg_status sg_render_views_noalloc(sg_volume *vol, int32_t n_views, const sg_view *views,
+                                  const sg_render_params *params, float *const *out_rgba,
+                                  float *const *out_depth, void *hip_stream);
+
 /* Sort-last compositing of one view's part images (Sec 5.1: the over
  * operator is associative, so renders of disjoint parts of the volume
  * combine): parts[k] is the premultiplied RGBA image (float4 per pixel,

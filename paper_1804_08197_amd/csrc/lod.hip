@@ -185,6 +185,20 @@ sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int
   return SG_OK;
 }
 
+sg_status cutmap_run(const Volume* v, const ViewDev* dviews, int n_views, int bias, bool lod,
+                     int timepoint, int32_t* cutmap, const InlineViews& iv, hipStream_t s) {
+  CutGeom g = cut_geom(v, bias, lod, timepoint);
+  const int64_t blocks = std::min<int64_t>((g.cells + 255) / 256, 4096);
+  ViewDev* dv = const_cast<ViewDev*>(dviews);
+  InlineViews ivc = iv;
+  void* pa[] = {&g, &dv, &cutmap, &ivc};
+  SG_HIP(hipLaunchKernel(reinterpret_cast<const void*>(cutmap_kernel),
+                         dim3((unsigned)std::max<int64_t>(blocks, 1),
+                              (unsigned)std::max(n_views, 1)),
+                         dim3(256), pa, 0, s));
+  return SG_OK;
+}
+
 sg_status launch_cutmap(Volume* v, const ViewDev* dviews, int n_views, int bias,
                         bool lod, int timepoint, hipStream_t s, const int32_t* enable) {
   Launch l;

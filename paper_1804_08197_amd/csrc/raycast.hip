@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "sg_internal.h"
@@ -160,7 +161,7 @@ Launch queue_reset_launch(uint32_t* q) {
 
 }  // namespace
 
-sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out) {
+sg_status raycast_plan(Volume* v, RenderArgs& a, bool stats, RaycastPlan* out) {
   const bool gather = a.gather != 0;
   const bool loop = a.persistent || a.wave_tiles > 1;
   const int C = v->d.channels;
@@ -197,6 +198,17 @@ sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out) {
   out->grid = dim3((unsigned)grid);
   out->block = dim3((unsigned)threads);
   out->lds = lds;
+  return SG_OK;
+}
+
+sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out) {
+  RaycastPlan pl;
+  sg_status st = raycast_plan(v, a, stats, &pl);
+  if (st != SG_OK) return st;
+  out->func = pl.func;
+  out->grid = pl.grid;
+  out->block = pl.block;
+  out->lds = pl.lds;
   out->arg.clear();
   out->push(a);
   return SG_OK;
@@ -242,10 +254,20 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       int64_t* total_blocks) {
   if (n_views < 1 || n_views > 4096 || !views || !p)
     return fail(SG_ERR_INVALID_ARG, "views: n_views must be in [1, 4096]");
+  out->assign(n_views, ViewDev{});
+  return build_views_into(v, n_views, views, p, rgba, depth, nsamp, bt_log, out->data(),
+                          total_blocks);
+}
+
+sg_status build_views_into(const Volume* v, int n_views, const sg_view* views,
+                           const sg_render_params* p, float* const* rgba, float* const* depth,
+                           int32_t* const* nsamp, int bt_log, ViewDev* hv,
+                           int64_t* total_blocks) {
+  if (n_views < 1 || n_views > 4096 || !views || !p)
+    return fail(SG_ERR_INVALID_ARG, "views: n_views must be in [1, 4096]");
   sg_status st = check_params(v, p);
   if (st != SG_OK) return st;
-  std::vector<ViewDev>& hv = *out;
-  hv.assign(n_views, ViewDev{});
+  for (int i = 0; i < n_views; ++i) hv[i] = ViewDev{};
   int64_t blocks = 0;
   const int64_t cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
   const int bpx = 8 << bt_log;  // block edge in pixels
@@ -733,5 +755,118 @@ extern "C" sg_status sg_render_graph_destroy(sg_render_graph* g) {
   DeviceGuard guard(g->v->d.device);
   hipDeviceSynchronize();
   graph_free(g);
+  return SG_OK;
+}
+
+// ---------------------------------------------------- allocation-free render
+// sg_render_views_noalloc keeps its per-render scratch -- the view table,
+// the persistent grid's eight tile queues and the cut maps -- in one
+// file-scope device array, of which every GPU the library runs on holds its
+// own copy until the process ends. Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+namespace sg {
+namespace {
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr size_t kScratchQueue = 4096;  // view table [0, 4096), queues from here
+constexpr size_t kScratchCut = 8192;    // cut maps [8192, kScratchBytes)
+static_assert(kInlineViews * sizeof(ViewDev) <= kScratchQueue, "view table exceeds its room");
+constexpr int kMaxDevices = 64;
+}  // namespace
+}  // namespace sg
+
+static __device__ __align__(256) uint8_t scratch[sg::kScratchBytes];
+
+namespace sg {
+namespace {
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// The device address of this device's scratch (dev must be current).
+sg_status scratch_base(int dev, uint8_t** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SG_ERR_UNSUPPORTED, "sg_render_views_noalloc: device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SG_ERR_DEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch[dev] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch[dev];
+  return SG_OK;
+}
+
+}  // namespace
+}  // namespace sg
+
+extern "C" sg_status sg_render_views_noalloc(sg_volume* vol, int32_t n_views,
+                                             const sg_view* views,
+                                             const sg_render_params* params,
+                                             float* const* out_rgba, float* const* out_depth,
+                                             void* hip_stream) {
+  if (!vol) return fail(SG_ERR_INVALID_ARG, "sg_render_views_noalloc: NULL volume");
+  Volume* v = &vol->v;
+  if (!views || !params || !out_rgba)
+    return fail(SG_ERR_INVALID_ARG, "sg_render_views_noalloc: NULL views, params or out_rgba");
+  if (n_views < 1 || n_views > kInlineViews)
+    return fail(SG_ERR_INVALID_ARG, "sg_render_views_noalloc: n_views must be in [1, 4]");
+  sg_status st = check_volume_ready(v);
+  if (st != SG_OK) return st;
+  // committing (aprons, ranges, table upload) may allocate: it must be done
+  bool pending = v->empty_dirty || v->tf_dirty;
+  for (uint8_t p : v->pending) pending = pending || p != 0;
+  if (pending)
+    return fail(SG_ERR_STATE, "sg_render_views_noalloc: uploads or transfer-function changes "
+                              "are not committed (call sg_volume_commit first)");
+  const LaunchConfig cfg = effective_config(v, params);
+  if ((st = check_config(v, cfg)) != SG_OK) return st;
+  const int64_t cells = (int64_t)v->grid[0][0] * v->grid[0][1] * v->grid[0][2];
+  const int64_t cut_bytes = (int64_t)n_views * cells * (int64_t)sizeof(int32_t);
+  if (cut_bytes > (int64_t)(kScratchBytes - kScratchCut))
+    return fail(SG_ERR_INVALID_ARG,
+                "sg_render_views_noalloc: the cut maps (views x level-0 bricks x 4 bytes = " +
+                    std::to_string(cut_bytes) + ") exceed the " +
+                    std::to_string(kScratchBytes - kScratchCut) + "-byte scratch");
+  ViewDev hv[kInlineViews];
+  int64_t blocks = 0;
+  if ((st = build_views_into(v, n_views, views, params, out_rgba, out_depth, nullptr,
+                             cfg.bt_log, hv, &blocks)) != SG_OK)
+    return st;
+  if (!top_level_resident(v, params->timepoint))
+    return fail(SG_ERR_STATE, "a top-level node is not in the cache at this timepoint");
+  DeviceGuard guard(v->d.device);
+  if (!guard.ok) return fail(SG_ERR_DEVICE, "cannot select device");
+  uint8_t* base = nullptr;
+  if ((st = scratch_base(v->d.device, &base)) != SG_OK) return st;
+  ViewDev* dviews = reinterpret_cast<ViewDev*>(base);
+  uint32_t* queue = reinterpret_cast<uint32_t*>(base + kScratchQueue);
+  int32_t* cutmap = reinterpret_cast<int32_t*>(base + kScratchCut);
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the view records ride in the cut-map kernel's arguments; its first
+  // workgroup writes them to the scratch view table (every call rewrites
+  // the table, the cut maps and, for the persistent grid, the queues)
+  InlineViews iv{};
+  iv.n = n_views;
+  for (int i = 0; i < n_views; ++i) iv.v[i] = hv[i];
+  ++v->frame;
+  if ((st = cutmap_run(v, dviews, n_views, params->lod_bias, (params->flags & SG_LOD) != 0,
+                       params->timepoint, cutmap, iv, s)) != SG_OK)
+    return st;
+  if (cfg.persistent) {
+    void* qa[] = {&queue};
+    SG_HIP(hipLaunchKernel(reinterpret_cast<const void*>(reset_queue_kernel), dim3(1), dim3(64),
+                           qa, 0, s));
+  }
+  RenderArgs a;
+  fill_args(v, params, n_views, dviews, cutmap, blocks, cfg, &a);
+  a.queue = queue;
+  RaycastPlan pl;
+  if ((st = raycast_plan(v, a, false, &pl)) != SG_OK) return st;
+  void* args[1] = {&a};
+  SG_HIP(hipLaunchKernel(pl.func, pl.grid, pl.block, args, pl.lds, s));
   return SG_OK;
 }

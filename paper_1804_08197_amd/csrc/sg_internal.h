@@ -248,12 +248,21 @@ sg_status build_views(const Volume* v, int n_views, const sg_view* views,
                       const sg_render_params* p, float* const* rgba, float* const* depth,
                       int32_t* const* nsamp, int bt_log, std::vector<ViewDev>* hv,
                       int64_t* total_blocks);
+// The same into a caller-provided array of n_views records.
+sg_status build_views_into(const Volume* v, int n_views, const sg_view* views,
+                           const sg_render_params* p, float* const* rgba, float* const* depth,
+                           int32_t* const* nsamp, int bt_log, ViewDev* hv,
+                           int64_t* total_blocks);
 // The cut-map kernel for views already on the device, writing `cutmap`.
 // enable: NULL, or a device flag read by the kernel (0: it does nothing).
 // iv: NULL or n == 0, or the views to use and to write to dviews.
 sg_status cutmap_launch(const Volume* v, const ViewDev* dviews, int n_views, int bias,
                         bool lod, int timepoint, int32_t* cutmap, Launch* out,
                         const int32_t* enable = nullptr, const InlineViews* iv = nullptr);
+// The same cut-map kernel enqueued on `s` at once, with its arguments on
+// the stack (no host or device allocation).
+sg_status cutmap_run(const Volume* v, const ViewDev* dviews, int n_views, int bias, bool lod,
+                     int timepoint, int32_t* cutmap, const InlineViews& iv, hipStream_t s);
 
 struct RenderArgs {
   const uint8_t* pool;
@@ -305,6 +314,12 @@ struct RenderArgs {
 
 // The ray-casting launch (kernel, grid, LDS) for arguments `a`; a.grid is
 // set to the grid chosen.
+struct RaycastPlan {
+  const void* func = nullptr;
+  dim3 grid{1, 1, 1}, block{1, 1, 1};
+  size_t lds = 0;
+};
+sg_status raycast_plan(Volume* v, RenderArgs& a, bool stats, RaycastPlan* out);
 sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out);
 // Kernel instances per optical model (one translation unit each).
 const void* raycast_kernel_absorption(int bpv, int channels, bool stats, bool gather,

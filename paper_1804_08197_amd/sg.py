@@ -128,6 +128,9 @@ _lib.sg_cache_requests.argtypes = [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int3
 _lib.sg_cache_get_info.argtypes = [_P, C.POINTER(sg_cache_info)]
 _lib.sg_cache_resident.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32)]
+_lib.sg_render_views_noalloc.argtypes = [_P, C.c_int32, C.POINTER(sg_view),
+                                         C.POINTER(sg_render_params), C.POINTER(_P),
+                                         C.POINTER(_P), _P]
 _lib.sg_pyramid_level.argtypes = [C.c_int32, C.POINTER(C.c_int32), _P, _P, _P]
 _lib.sg_brick_regions.argtypes = [C.c_int32, C.POINTER(C.c_int32), _P, C.c_int32, C.c_int32,
                                   C.POINTER(C.c_int32), _P, _P]
@@ -142,7 +145,8 @@ for _f in ("sg_volume_create", "sg_volume_destroy", "sg_upload_bricks", "sg_buil
            "sg_get_launch_config", "sg_autotune", "sg_render_graph_create",
            "sg_render_graph_set_views", "sg_render_graph_launch", "sg_render_graph_destroy",
            "sg_cache_put", "sg_cache_put_scattered", "sg_cache_requests", "sg_cache_get_info",
-           "sg_cache_resident", "sg_render_views_if", "sg_pyramid_level", "sg_brick_regions"):
+           "sg_cache_resident", "sg_render_views_if", "sg_pyramid_level", "sg_brick_regions",
+           "sg_render_views_noalloc"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -313,6 +317,19 @@ def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
     _check(_lib.sg_render_views(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
            "sg_render_views")
 
+
+def sg_render_views_noalloc(vol, views, params, out_rgba, out_depth=None, stream=None):
+    """sg_render_views with its per-render scratch in the library's static
+    device array (no allocation; at most 4 views, committed volume)."""
+    n = len(views)
+    varr = _views(views)
+    p = params if isinstance(params, sg_render_params) else make_params(params)
+    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
+    dep = None
+    if out_depth is not None:
+        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    _check(_lib.sg_render_views_noalloc(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
+           "sg_render_views_noalloc")
 
 def sg_render_views_if(vol, views, params, out_rgba, enable, out_depth=None, stream=None):
     """sg_render_views carried out only if the device int32 `enable` (a
