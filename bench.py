@@ -236,7 +236,18 @@ def main():
            "step_ms_p90": float(np.percentile(step_ms, 90)),
            "microblocks_per_frame": mb, "brick_bytes_per_frame": brick_bytes,
            "cut_nonempty_nodes": len(cut), "roofline": roof, "roofline_other": other,
-           "launch": launch, "setup_ms": setup}
+           "launch": launch, "setup_ms": setup,
+           # instrumented pass of the same frame (staged kernel only)
+           "kernel_stats": {
+               "node_visits": stats["node_visits"], "slabs": stats["slabs"],
+               "staged_bytes": stats["staged_bytes"],
+               "lanes_in_node": (stats["node_lanes"] / (64.0 * stats["node_visits"])
+                                 if stats["node_visits"] else None),
+               "lanes_in_flight": (stats["alive_lanes"] / (64.0 * stats["node_visits"])
+                                   if stats["node_visits"] else None),
+               "loop_lane_utilisation": (samples / (64.0 * stats["loop_iterations"])
+                                         if stats["loop_iterations"] else None),
+               "pool_samples": stats["pool_samples"], "slab_retries": stats["slab_retries"]}}
 
     if want_cpu:
         out["cpu_baseline"] = cpu_baseline(host, tf, views, samples, npix, args.cpu_seconds)

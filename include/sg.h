@@ -165,6 +165,21 @@ typedef struct {
                               or (ray, node) segments sampled (gather)       */
   uint64_t slabs;          /* out: LDS staging passes (staged kernel)        */
   uint64_t staged_bytes;   /* out: bytes copied from the pool into LDS       */
+  uint64_t node_lanes;     /* out: staged kernel: sum over (wave, node) visits
+                              of the lanes whose ray is in that node         */
+  uint64_t loop_iterations; /* out: staged kernel: wave iterations of the
+                              sample loops (LDS and pool reads); the lane
+                              utilisation of the loops is
+                              total_samples / (64 * loop_iterations)        */
+  uint64_t pool_samples;   /* out: staged kernel: samples whose stencils read
+                              the pool, not LDS (the node's rays share no
+                              dominant direction, or one layer of the slab
+                              does not fit the staging space)               */
+  uint64_t slab_retries;   /* out: staged kernel: slab sizes tried beyond the
+                              first (the region did not fit)               */
+  uint64_t alive_lanes;    /* out: staged kernel: sum over (wave, node) visits
+                              of the lanes whose ray is still in flight (in
+                              that node or in another)                      */
 } sg_render_stats;
 
 /* Create a volume on desc->device (Sec 4.2: the GPU-side store of volume

@@ -64,7 +64,7 @@ LaunchConfig effective_config(const Volume* v, const sg_render_params* p) {
 int wg_log_of(const LaunchConfig& c) { return std::min(2, 2 * c.tile_log); }
 
 size_t lds_bytes(const Volume* v, const LaunchConfig& c) {
-  size_t tf = (size_t)v->d.channels * (v->tf_n + 1) * 16;
+  size_t tf = (size_t)v->d.channels * v->tf_n * 32;  // value and difference per entry
   return c.gather ? tf : tf + ((size_t)1 << wg_log_of(c)) * (size_t)c.stage_bytes;
 }
 
@@ -411,10 +411,10 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
         return fail(SG_ERR_OUT_OF_MEMORY, "micro-block bitmap allocation failed");
       v->mb_words = words;
     }
-    if (!v->counters && hipMalloc((void**)&v->counters, 64) != hipSuccess)
+    if (!v->counters && hipMalloc((void**)&v->counters, 128) != hipSuccess)
       return fail(SG_ERR_OUT_OF_MEMORY, "counter allocation failed");
     SG_HIP(hipMemsetAsync(v->mb_bits, 0, (size_t)words * 4, s));
-    SG_HIP(hipMemsetAsync(v->counters, 0, 64, s));
+    SG_HIP(hipMemsetAsync(v->counters, 0, 128, s));
     a.mb_bits = v->mb_bits;
     a.counters = v->counters;
     for (int i = 0; i < kMaxChannels * kMaxLevels; ++i) a.level_mb_off[i] = offs[i];
@@ -422,9 +422,9 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
     if ((st = raycast_launch(v, a, true, &l)) != SG_OK) return st;
     if ((st = l.run(s)) != SG_OK) return st;
     std::vector<uint32_t> hb((size_t)words);
-    uint64_t cnt[8];
+    uint64_t cnt[16];
     SG_HIP(hipMemcpyAsync(hb.data(), v->mb_bits, (size_t)words * 4, hipMemcpyDeviceToHost, s));
-    SG_HIP(hipMemcpyAsync(cnt, v->counters, 64, hipMemcpyDeviceToHost, s));
+    SG_HIP(hipMemcpyAsync(cnt, v->counters, 128, hipMemcpyDeviceToHost, s));
     SG_HIP(hipStreamSynchronize(s));
     uint64_t pop = 0;
     for (uint32_t x : hb) pop += (uint64_t)__builtin_popcount(x);
@@ -433,6 +433,11 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
     stats->node_visits = cnt[1];
     stats->slabs = cnt[2];
     stats->staged_bytes = cnt[3];
+    stats->node_lanes = cnt[4];
+    stats->loop_iterations = cnt[5];
+    stats->pool_samples = cnt[6];
+    stats->slab_retries = cnt[7];
+    stats->alive_lanes = cnt[8];
     return SG_OK;
   }
   Launch l;

@@ -172,7 +172,7 @@ struct Volume {
   int stage_next = 0;
   uint32_t* mb_bits = nullptr;  // micro-block bitmap (stats only)
   int64_t mb_words = 0;
-  uint64_t* counters = nullptr;  // device counters (stats only)
+  uint64_t* counters = nullptr;  // device counters (stats only), 16 of them
   uint64_t bytes = 0;
   // out-of-core mode (cache_slots > 0)
   bool cache = false;

@@ -59,7 +59,9 @@ class sg_render_params(C.Structure):
 class sg_render_stats(C.Structure):
     _fields_ = [("samples", C.POINTER(C.c_void_p)), ("total_samples", C.c_uint64),
                 ("microblocks", C.c_uint64), ("node_visits", C.c_uint64), ("slabs", C.c_uint64),
-                ("staged_bytes", C.c_uint64)]
+                ("staged_bytes", C.c_uint64), ("node_lanes", C.c_uint64),
+                ("loop_iterations", C.c_uint64), ("pool_samples", C.c_uint64),
+                ("slab_retries", C.c_uint64), ("alive_lanes", C.c_uint64)]
 
 
 class sg_cache_info(C.Structure):
@@ -379,7 +381,9 @@ def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samp
                                       _stream(stream)), "sg_render_views_stats")
     return {"total_samples": int(st.total_samples), "microblocks": int(st.microblocks),
             "node_visits": int(st.node_visits), "slabs": int(st.slabs),
-            "staged_bytes": int(st.staged_bytes)}
+            "staged_bytes": int(st.staged_bytes), "node_lanes": int(st.node_lanes),
+            "loop_iterations": int(st.loop_iterations), "pool_samples": int(st.pool_samples),
+            "slab_retries": int(st.slab_retries), "alive_lanes": int(st.alive_lanes)}
 
 
 def sg_get_lod_cut(vol, view, params, capacity=1 << 20, stream=None):
