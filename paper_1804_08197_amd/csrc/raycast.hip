@@ -17,6 +17,13 @@ namespace {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// Do all views have one size (so one block grid)?
+bool same_size(int n_views, const sg_view* views) {
+  for (int i = 1; i < n_views; ++i)
+    if (views[i].width != views[0].width || views[i].height != views[0].height) return false;
+  return true;
+}
+
 // Zero the 8 per-XCD tile queues of the persistent grid (a kernel, not a
 // memset, so that graphs replay it reliably).
 __global__ void reset_queue_kernel(uint32_t* q) {
@@ -88,7 +95,7 @@ int log2i(int x) {
 // Arguments shared by the stream path and the graph path.
 void fill_args(const Volume* v, const sg_render_params* params, int n_views,
                const ViewDev* dviews, const int32_t* cutmap, int64_t blocks,
-               const LaunchConfig& cfg, RenderArgs* out) {
+               const LaunchConfig& cfg, bool same_size, RenderArgs* out) {
   RenderArgs& a = *out;
   std::memset(&a, 0, sizeof(a));
   const int C = v->d.channels;
@@ -119,6 +126,16 @@ void fill_args(const Volume* v, const sg_render_params* params, int n_views,
   a.key_levels = key_levels;
   a.n_views = n_views;
   a.total_blocks = (int32_t)blocks;
+  if (same_size && n_views > 1) {
+    // the views' blocks at one screen position go to one XCD in turn
+    a.pair_views = n_views;
+    a.view_blocks = (int32_t)(blocks / n_views);
+    a.dealt_blocks = 8 * n_views * ((a.view_blocks + 7) / 8);
+  } else {
+    a.pair_views = 0;
+    a.view_blocks = 0;
+    a.dealt_blocks = (int32_t)(((blocks + 7) / 8) * 8);
+  }
   a.tf_n = v->tf_n;
   a.tile_log = cfg.tile_log;
   a.wg_log = wg_log_of(cfg);
@@ -188,8 +205,7 @@ sg_status raycast_plan(Volume* v, RenderArgs& a, bool stats, RaycastPlan* out) {
     SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, threads, lds));
     grid = std::max(8, ((cus * std::max(per_cu, 1)) / 8) * 8);
   } else {
-    const int64_t g = ((int64_t)(a.total_blocks + 7) / 8) * 8
-                      << (2 * (a.bt_log - a.tile_log));
+    const int64_t g = (int64_t)a.dealt_blocks << (2 * (a.bt_log - a.tile_log));
     if (g > 0x7fffffff) return fail(SG_ERR_INVALID_ARG, "too many pixels in one call");
     grid = (int)g;
   }
@@ -388,7 +404,7 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
   if (timed && (st = timing_mark(v, s)) != SG_OK) return st;
 
   RenderArgs a;
-  fill_args(v, params, n_views, dv, v->cutmap, blocks, cfg, &a);
+  fill_args(v, params, n_views, dv, v->cutmap, blocks, cfg, same_size(n_views, views), &a);
   a.enable = enable;
   const int C = v->d.channels;
   if (stats) {
@@ -701,7 +717,8 @@ extern "C" sg_status sg_render_graph_create(sg_volume* vol, int32_t n_views,
                           &cut)) != SG_OK)
     return bail(st);
   RenderArgs a;
-  fill_args(v, params, n_views, g->dviews, g->cutmap, blocks, cfg, &a);
+  fill_args(v, params, n_views, g->dviews, g->cutmap, blocks, cfg, same_size(n_views, views),
+            &a);
   a.queue = g->queue;
   if ((st = raycast_launch(v, a, false, &ray)) != SG_OK) return bail(st);
   if (hipGraphCreate(&g->graph, 0) != hipSuccess)
@@ -867,7 +884,7 @@ extern "C" sg_status sg_render_views_noalloc(sg_volume* vol, int32_t n_views,
                            qa, 0, s));
   }
   RenderArgs a;
-  fill_args(v, params, n_views, dviews, cutmap, blocks, cfg, &a);
+  fill_args(v, params, n_views, dviews, cutmap, blocks, cfg, same_size(n_views, views), &a);
   a.queue = queue;
   RaycastPlan pl;
   if ((st = raycast_plan(v, a, false, &pl)) != SG_OK) return st;

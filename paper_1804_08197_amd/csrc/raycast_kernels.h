@@ -388,8 +388,8 @@ __device__ __forceinline__ float sample_tau(const Ray& r, int k) {
 // fma(w, t[k+1] - t[k], t[k]): the same operations, in the same FP32
 // rounding, as lerpf(t[k], t[k+1], w).
 __device__ __forceinline__ float4 tf_lookup(const RenderArgs& a, const float4* s_tf, int ch,
-                                            float val) {
-  float u = fmaf(val, a.tf_scale[ch], a.tf_bias[ch]);
+                                            float val, float scale, float bias) {
+  float u = fmaf(val, scale, bias);
   u = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(a.tf_n - 1));  // clamp (u is finite)
   const int k0 = (int)u;
   const float wt = __builtin_amdgcn_fractf(u);  // = u - k0 exactly, u >= 0
@@ -397,6 +397,32 @@ __device__ __forceinline__ float4 tf_lookup(const RenderArgs& a, const float4* s
   const float4 d = s_tf[2 * (ch * a.tf_n + k0) + 1];
   return make_float4(fmaf(wt, d.x, t.x), fmaf(wt, d.y, t.y), fmaf(wt, d.z, t.z),
                      fmaf(wt, d.w, t.w));
+}
+
+__device__ __forceinline__ float4 tf_lookup(const RenderArgs& a, const float4* s_tf, int ch,
+                                            float val) {
+  return tf_lookup(a, s_tf, ch, val, a.tf_scale[ch], a.tf_bias[ch]);
+}
+
+// The transfer-table windows of a run of samples, the offsets held in
+// vector registers: the kernel arguments sit in scalar registers, and an FMA
+// reads at most one of those, so an offset left there costs a move per
+// sample.
+template <int CH>
+struct TfWin {
+  float scale[CH], bias[CH];
+};
+template <int CH>
+__device__ __forceinline__ TfWin<CH> tf_win(const RenderArgs& a) {
+  TfWin<CH> w;
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    float b = a.tf_bias[ch];
+    asm volatile("" : "+v"(b));  // (a register move, no memory access)
+    w.scale[ch] = a.tf_scale[ch];
+    w.bias[ch] = b;
+  }
+  return w;
 }
 
 // Statistics: mark the distinct 4^3 blocks of the level read by the stencil
@@ -441,7 +467,8 @@ struct Shade {
 };
 template <int CH, bool STATS, bool CLAMP, typename F>
 __device__ __forceinline__ Shade shade_ea(const Ray& r, const RenderArgs& a, const float4* s_tf,
-                                          F&& fetch, float tau, int (*mb_key)[3]) {
+                                          const TfWin<CH>& w, F&& fetch, float tau,
+                                          int (*mb_key)[3]) {
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
@@ -460,7 +487,7 @@ __device__ __forceinline__ Shade shade_ea(const Ray& r, const RenderArgs& a, con
   for (int ch = 0; ch < CH; ++ch) {
     const float val = fetch(ch, ix, iy, iz, fx, fy, fz);
     if (STATS) mark_microblocks(r, a, ch, ix, iy, iz, mb_key[ch]);
-    const float4 c = tf_lookup(a, s_tf, ch, val);
+    const float4 c = tf_lookup(a, s_tf, ch, val, w.scale[ch], w.bias[ch]);
     if (CH == 1) {
       z = Shade{c.w, c.x, c.y, c.z};
     } else {
@@ -479,16 +506,20 @@ __device__ __forceinline__ Shade shade_ea(const Ray& r, const RenderArgs& a, con
   return z;
 }
 
-// Over-compositing of one emission-absorption sample of length s at ray
-// parameter tau, in transmittance form: the sample's opacity is
-// 1 - exp(-rho s) and its weight (1 - A) times that, i.e. T - T exp(-rho s)
-// with T = 1 - A (the same recurrence; exp(-rho s) = 2^(-rho s log2 e)).
-// Returns false once the ray has terminated. DEPTH false: the view asks for
-// no depth, so the depth bookkeeping is left out.
+// -log2(e): exp(-x) = 2^(x * kNegLog2e)
+constexpr float kNegLog2e = -1.44269504f;
+
+// Over-compositing of one emission-absorption sample at ray parameter tau,
+// in transmittance form: the sample's opacity is 1 - exp(-rho s) and its
+// weight (1 - A) times that, i.e. T - T exp(-rho s) with T = 1 - A (the same
+// recurrence). sc = s * kNegLog2e, so exp(-rho s) = 2^(rho sc). Returns
+// whether the ray goes on: false once A >= ert, the early termination
+// (the caller clears `alive`; 1 - T then reproduces A exactly). DEPTH false:
+// the view asks for no depth, so the depth bookkeeping is left out.
 template <bool DEPTH>
 __device__ __forceinline__ bool composite_ea(Ray& r, const RenderArgs& a, const Shade& z,
-                                             float s, float tau) {
-  const float tn = r.T * __builtin_amdgcn_exp2f((z.rho * s) * -1.44269504f);
+                                             float sc, float tau) {
+  const float tn = r.T * __builtin_amdgcn_exp2f(z.rho * sc);
   const float wgt = r.T - tn;
   r.Cr = fmaf(wgt, z.er, r.Cr);
   r.Cg = fmaf(wgt, z.eg, r.Cg);
@@ -499,29 +530,35 @@ __device__ __forceinline__ bool composite_ea(Ray& r, const RenderArgs& a, const 
   // reached the threshold has the smallest tau (the depth itself, t0 + tau in FP64,
   // is formed once per segment by finish_depth)
   if (DEPTH) r.dtau = (A >= a.depth_alpha && tau < r.dtau) ? tau : r.dtau;
-  if (A >= a.ert) {
-    r.alive = false;
-    return false;
-  }
-  return true;
+  return !(A >= a.ert);
 }
 
+// Has the ray terminated early (emission-absorption)? The same test, on the
+// same value, as composite_ea's.
+__device__ __forceinline__ bool terminated(const Ray& r, const RenderArgs& a) {
+  return 1.0f - r.T >= a.ert;
+}
+
+// Which step a sample_step takes: a full one, the segment's last (partial)
+// one, or either, decided per sample.
+enum StepKind { kFullStep = 0, kLastStep = 1, kAnyStep = 2 };
+
 // Take sample r.k of the current segment under optical model MODEL (see
-// shade_ea for `fetch`); the segment's last step is the partial one.
-// Returns false once the ray has terminated (emission-absorption only).
-template <int MODEL, int CH, bool STATS, bool CLAMP, bool DEPTH, typename F>
+// shade_ea for `fetch`). Returns whether the ray goes on (false only when
+// an emission-absorption ray terminates; the caller clears `alive`).
+template <int MODEL, int CH, bool STATS, bool CLAMP, bool DEPTH, int KIND, typename F>
 __device__ __forceinline__ bool sample_step(Ray& r, const RenderArgs& a, const float4* s_tf,
-                                            F&& fetch, int (*mb_key)[3]) {
+                                            const TfWin<CH>& w, F&& fetch, int (*mb_key)[3]) {
   const int k = r.k;
-  const bool last = k == r.n - 1;
+  const bool last = KIND == kLastStep || (KIND == kAnyStep && k == r.n - 1);
   const float s = last ? r.s_last : r.Df;
   const float tau = last ? r.tau_last : r.tau;  // = sample_tau(r, k)
   if (MODEL != kModelEmission && MODEL != kModelMip) {
-    const Shade z = shade_ea<CH, STATS, CLAMP>(r, a, s_tf, fetch, tau, mb_key);
+    const Shade z = shade_ea<CH, STATS, CLAMP>(r, a, s_tf, w, fetch, tau, mb_key);
     r.k = k + 1;
     r.tau += r.Df;
     if (STATS) ++r.nsamp;
-    return composite_ea<DEPTH>(r, a, z, s, tau);
+    return composite_ea<DEPTH>(r, a, z, s * kNegLog2e, tau);
   }
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
@@ -540,7 +577,7 @@ __device__ __forceinline__ bool sample_step(Ray& r, const RenderArgs& a, const f
       r.vmax[ch] = fmaxf(r.vmax[ch], val);
       continue;
     }
-    const float4 c = tf_lookup(a, s_tf, ch, val);
+    const float4 c = tf_lookup(a, s_tf, ch, val, w.scale[ch], w.bias[ch]);
     er += c.x;
     eg += c.y;
     eb += c.z;
@@ -560,12 +597,33 @@ __device__ __forceinline__ bool sample_step(Ray& r, const RenderArgs& a, const f
 }
 
 // Samples r.k .. kb (kb <= n - 1) of the current segment, stopping when the
-// ray terminates.
+// ray terminates: the full steps in a loop whose step length does not
+// change, then the segment's partial last step if kb is the last sample.
 template <int MODEL, int CH, bool STATS, bool CLAMP = true, bool DEPTH = true, typename F>
 __device__ __forceinline__ void sample_run(Ray& r, const RenderArgs& a, const float4* s_tf,
                                            F&& fetch, int kb, int (*mb_key)[3]) {
-  while (r.k <= kb && sample_step<MODEL, CH, STATS, CLAMP, DEPTH>(r, a, s_tf, fetch, mb_key)) {
+  constexpr bool kEA = MODEL != kModelEmission && MODEL != kModelMip;
+  const TfWin<CH> w = tf_win<CH>(a);
+  if (CH > 1) {
+    // several channels: one loop (a second copy of the larger body costs
+    // more registers than the per-sample choice of step saves)
+    bool go = r.k <= kb;
+    while (go)
+      go = sample_step<MODEL, CH, STATS, CLAMP, DEPTH, kAnyStep>(r, a, s_tf, w, fetch, mb_key) &&
+           r.k <= kb;
+  } else {
+    const int kf = min(kb, r.n - 2);
+    bool go = r.k <= kf;
+    while (go)
+      go = sample_step<MODEL, CH, STATS, CLAMP, DEPTH, kFullStep>(r, a, s_tf, w, fetch,
+                                                                  mb_key) &&
+           r.k <= kf;
+    // here r.k <= kb only when r.k = n - 1 = kb
+    const bool live = !(kEA && terminated(r, a));
+    if (live && r.k <= kb)
+      sample_step<MODEL, CH, STATS, CLAMP, DEPTH, kLastStep>(r, a, s_tf, w, fetch, mb_key);
   }
+  if (kEA && terminated(r, a)) r.alive = false;
 }
 
 // Pool slot pointers of a node, one per channel. Cache volumes stamp the
@@ -652,15 +710,27 @@ __device__ __forceinline__ TileLane tile_at(const RenderArgs& a, int block, int 
   out.view = 0;
   out.px = out.py = 0;
   out.in_image = false;
-  out.tile_valid = block < a.total_blocks;
+  out.tile_valid = block < a.dealt_blocks;
   if (!out.tile_valid) return out;
-  int lo = 0, hi = a.n_views - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.views[mid].block_begin <= block) lo = mid; else hi = mid - 1;
+  int lo = 0, lb;
+  if (a.pair_views) {
+    // views of one size: the block at one screen position in every view
+    const int s = block >> 3;
+    lo = s % a.pair_views;
+    lb = (block & 7) + 8 * (s / a.pair_views);
+    out.tile_valid = lb < a.view_blocks;
+    if (!out.tile_valid) return out;
+  } else {
+    out.tile_valid = block < a.total_blocks;
+    if (!out.tile_valid) return out;
+    int hi = a.n_views - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.views[mid].block_begin <= block) lo = mid; else hi = mid - 1;
+    }
+    lb = block - a.views[lo].block_begin;
   }
   const ViewDev& V = a.views[lo];
-  const int lb = block - V.block_begin;
   const int bx = lb % V.blocks_x, by = lb / V.blocks_x;
   const int per_row_log = a.bt_log - a.tile_log;  // workgroup tiles per block row (log2)
   const int gx = t & ((1 << per_row_log) - 1), gy = t >> per_row_log;
@@ -695,7 +765,7 @@ __device__ __forceinline__ bool next_tile(const RenderArgs& a, TileLane& tl) {
   item = (uint32_t)__builtin_amdgcn_readlane((int)item, 0);
   const int per_block_log = 2 * a.bt_log;          // wave tiles per block (log2)
   const int block = (int)((item >> per_block_log) << 3) + x;
-  if (block >= a.total_blocks) return false;
+  if (block >= a.dealt_blocks) return false;
   const int k = (int)(item & ((1u << per_block_log) - 1));
   const int wt_log = 2 * a.tile_log;               // wave tiles per workgroup tile (log2)
   tl = tile_at(a, block, k >> wt_log, k & ((1 << wt_log) - 1), lane);

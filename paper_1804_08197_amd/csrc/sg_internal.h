@@ -286,7 +286,16 @@ struct RenderArgs {
   int32_t dims[3];
   int32_t grid0[3];
   int32_t n_views;
-  int32_t total_blocks;  // 4x4-tile blocks over all views
+  int32_t total_blocks;  // screen blocks over all views
+  // Dealing of blocks to the XCDs. Dealt block g runs on XCD g % 8. With
+  // pair_views = 0, g is the block's index over all views (view by view).
+  // With pair_views = P > 1 (every view has the same size, e.g. the two
+  // eyes), g = 8 s + x holds the block at screen position
+  // x + 8 (s / P) of view s % P: the blocks at one position in all views
+  // share an XCD and its L2, and follow one another.
+  int32_t pair_views;
+  int32_t view_blocks;   // blocks per view (pair_views > 0)
+  int32_t dealt_blocks;  // dealt block indices (a multiple of 8)
   int32_t grid;          // workgroups launched
   int32_t tf_n;
   int32_t tile_log;     // log2 edge of a workgroup tile in 8x8 wave tiles
