@@ -1000,6 +1000,13 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     const int node = uniform(__builtin_amdgcn_readlane(r.node, first));
     const T* slot[CH];
     slot_ptrs<T, CH>(a, node, slot, lane == 0);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {  // the same for every lane: scalar registers
+      const uint64_t p = reinterpret_cast<uint64_t>(slot[ch]);
+      slot[ch] = reinterpret_cast<const T*>(
+          (uint64_t)(uint32_t)uniform((int)(uint32_t)p) |
+          ((uint64_t)(uint32_t)uniform((int)(uint32_t)(p >> 32)) << 32));
+    }
     if (STATS) {
       const uint64_t alive = __ballot(r.alive);
       if (lane == 0) {
@@ -1133,35 +1140,73 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
       if (STATS && lane == 0 && ntries > 1)
         atomicAdd((unsigned long long*)a.counters + 7, (unsigned long long)(ntries - 1));
       const int k_slab = r.k;
-      if (fits) {
-        // --- stage the region of every channel: pass p moves chunks
-        // p .. p+63 of the region (row-major, cpr chunks per row) straight
-        // from the pool into LDS (global_load_lds: lane i writes chunk i
-        // after the LDS base of the pass)
-        // Chunk i of the region is row = i / cpr, plane rz = row / wd[1];
-        // in the slot it sits at base + i + row * skip_row + rz * skip_plane
-        // (the chunks a row or a plane of the slot has beyond the region's).
-        // The quotients come from (x + 1/2) * (1/d) in FP32: its relative
-        // error is below 2^-23 and (x + 1/2) / d lies at least 1/(2d) from
-        // an integer, so the floor is exact for every x < 2^22.
-        const int cpr = wd[0] / align, P = Sx / align;
-        const int rows = wd[1] * wd[2];
-        const int total = cpr * rows;
-        const float inv_cpr = 1.0f / (float)cpr, inv_wy = 1.0f / (float)wd[1];
-        const int base = ((o[2] * S + o[1]) * Sx + o[0]) / align;
-        const int skip_row = P - cpr, skip_plane = (S - wd[1]) * P;
-        for (int p0 = 0; p0 < total; p0 += 64) {
-          const int i = p0 + lane;
-          if (i < total) {
-            const int row = (int)(((float)i + 0.5f) * inv_cpr);
-            const int rz = (int)(((float)row + 0.5f) * inv_wy);
-            const int g = base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane);
 #pragma unroll
-            for (int ch = 0; ch < CH; ++ch)
-              __builtin_amdgcn_global_load_lds(
-                  reinterpret_cast<const uint8_t*>(slot[ch]) + (size_t)g * kRowAlignBytes,
-                  reinterpret_cast<uint8_t*>(stage + ch * cap) + p0 * kRowAlignBytes,
-                  kRowAlignBytes, 0, 0);
+      for (int i = 0; i < 3; ++i) {  // the same for every lane: scalar registers
+        o[i] = uniform(o[i]);
+        wd[i] = uniform(wd[i]);
+      }
+      if (fits) {
+        // --- stage the region of every channel straight from the pool into
+        // LDS (global_load_lds: lane i of an instruction writes chunk i after
+        // the instruction's LDS base). The region is wd[1] * wd[2] rows of
+        // cpr chunks, row-major in LDS. The quotients below come from
+        // (x + 1/2) * (1/d) in FP32: its relative error is below 2^-23 and
+        // (x + 1/2) / d lies at least 1/(2d) from an integer, so the floor
+        // is exact for every x < 2^22.
+        const int cpr = wd[0] / align, P = Sx / align;
+        const int wy = wd[1], rows = wd[1] * wd[2];
+        const int total = cpr * rows;
+        const float inv_cpr = 1.0f / (float)cpr, inv_wy = 1.0f / (float)wy;
+        constexpr int cb = kRowAlignBytes;
+        if (cpr <= 64) {
+          // a pass moves R = 64 / cpr whole rows: lane rr * cpr + c takes
+          // chunk c of row rr of the pass (lanes past R * cpr rest). Each
+          // lane keeps the byte offset in the slot of its chunk and its
+          // row's position within its plane, and steps both by R rows per
+          // pass (dz planes and dy rows, with one carry)
+          const int R = uniform((int)(64.5f * inv_cpr));
+          const int dz = uniform((int)(((float)R + 0.5f) * inv_wy)), dy = R - dz * wy;
+          const int rr = (int)(((float)lane + 0.5f) * inv_cpr), col = lane - rr * cpr;
+          const int pz = (int)(((float)rr + 0.5f) * inv_wy);
+          int yy = rr - pz * wy;
+          int gb = ((((o[2] + pz) * S + o[1] + yy) * Sx + o[0]) / align + col) * cb;
+          // slot bytes per pass, without and with the carry into the next plane
+          int step = (dz * S + dy) * P * cb, step_c = step + (S - wy) * P * cb;
+          // as they are (one select per pass, no factoring of the common
+          // multiplier into the loop)
+          asm volatile("" : "+v"(step), "+v"(step_c));
+          const int lim = rr < R ? rows - rr : 0;  // the lane's rows: r0 + rr < rows
+          for (int r0 = 0; r0 < rows; r0 += R) {
+            if (r0 < lim) {
+#pragma unroll
+              for (int ch = 0; ch < CH; ++ch)
+                __builtin_amdgcn_global_load_lds(
+                    reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)gb,
+                    reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
+            }
+            yy += dy;
+            const bool c = yy >= wy;
+            yy -= c ? wy : 0;
+            gb += c ? step_c : step;
+          }
+        } else {
+          // rows wider than a pass (bricks of 128 or more): pass p moves
+          // chunks p .. p+63 of the region; chunk i is row = i / cpr, plane
+          // rz = row / wy, at base + i + row * skip_row + rz * skip_plane
+          const int base = ((o[2] * S + o[1]) * Sx + o[0]) / align;
+          const int skip_row = P - cpr, skip_plane = (S - wy) * P;
+          for (int p0 = 0; p0 < total; p0 += 64) {
+            const int i = p0 + lane;
+            if (i < total) {
+              const int row = (int)(((float)i + 0.5f) * inv_cpr);
+              const int rz = (int)(((float)row + 0.5f) * inv_wy);
+              const int g = base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane);
+#pragma unroll
+              for (int ch = 0; ch < CH; ++ch)
+                __builtin_amdgcn_global_load_lds(
+                    reinterpret_cast<const uint8_t*>(slot[ch]) + (size_t)g * cb,
+                    reinterpret_cast<uint8_t*>(stage + ch * cap) + p0 * cb, cb, 0, 0);
+            }
           }
         }
         __builtin_amdgcn_s_waitcnt(0);  // the LDS writes of the loads have landed
@@ -1225,8 +1270,10 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
   load_tf<CH>(a, s_tf);
+  // the wave's staging space (the wave index is the same for all its lanes:
+  // scalar registers)
   T* stage = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem + 2 * CH * a.tf_n) +
-                                  (threadIdx.x >> 6) * a.stage_bytes);
+                                  uniform((int)(threadIdx.x >> 6)) * a.stage_bytes);
   // no workgroup barrier follows: the waves work independently from here
   if (!LOOP) {
     const TileLane tl = tile_lane(a, 0);
