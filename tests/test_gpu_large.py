@@ -6,10 +6,10 @@
   launch for all channels, stereo 1440x1600 per eye.
 * batched uneven views of the 128^3 blobs volume in one launch.
 
-The oracle renders random pixels plus a centre crop of each eye (with the
-early-termination bracket); cuts and empty flags are compared in full.
+The oracle renders random pixels plus a centre crop of each eye (tubes:
+also every 16th row of both eyes), with the early-termination bracket;
+cuts and empty flags are compared in full.
 """
-import math
 import sys
 
 import numpy as np
@@ -110,10 +110,16 @@ def test_tubes_2048_stereo_parity(gpu):
             assert np.array_equal(ids, cut), "eye %d: LOD cut differs" % i
             emp = sc.empty(cut)
             assert np.array_equal(emp_gpu, emp), "eye %d: empty flags differ" % i
-            pix = sample_pixels(v, 2500, 100 + i)
+            # every 16th row of the eye (offset per eye, so the rows cut the
+            # 8-pixel wave tiles and 32-pixel blocks at different heights),
+            # plus random pixels and the centre crop: about 6% of the frame
+            rows = np.arange(3 + 8 * i, v["height"], 16)
+            yy, xx = np.meshgrid(rows, np.arange(v["width"]), indexing="ij")
+            pix = np.concatenate([np.stack([xx.ravel(), yy.ravel()], 1).astype(np.int32),
+                                  sample_pixels(v, 2500, 100 + i)])
             err, needed, _ = compare_pixels(sc, v, params, rgba[i], ns[i], pix, cut, emp)
-            log("tubes eye %d: cut %d nodes, %d px, max err %.3g, bracket used %d" % (
-                i, len(cut), len(pix), err, needed))
+            log("tubes eye %d: cut %d nodes, %d px (%d rows), max err %.3g, bracket used %d" % (
+                i, len(cut), len(pix), len(rows), err, needed))
         # the frame is non-trivial
         assert st["total_samples"] > 1e8
         assert max(float(r[..., 3].max()) for r in rgba) > 0.99
@@ -173,8 +179,9 @@ def test_batched_uneven_views_parity(gpu):
     try:
         upload_volume(h, vol, 32)
         sg.sg_set_transfer_function(h, 0, tf, 0, 255)
-        views = gen.orbit_views((64, 64, 64), (1.5 * 221.7, 4 * 221.7), 16, 1004, (512, 2048),
-                                (512, 2048), tan_top=math.tan(math.radians(30)))
+        import bench
+        views = bench.batched_views()  # all 64 views of the batched workload
+        assert len(views) == 64
         params = {"ert": ERT, "tau": 1.0}
         outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
         sg.sg_render_views(h, views, params, outs)
@@ -182,7 +189,7 @@ def test_batched_uneven_views_parity(gpu):
         sc = oracle.Scene([vol], 32, 3, [as_f64_tf(tf)], [(0, 255)])
         for i, v in enumerate(views):
             got = outs[i].cpu().numpy()
-            pix = sample_pixels(v, 400, 300 + i, crop=16)
+            pix = sample_pixels(v, 300, 300 + i, crop=16)
             refs = [sc.render(v, dict(params, ert=e), pixels=pix)
                     for e in (ERT, ERT - 1e-5, ERT + 1e-5)]
             best, _ = bracket_error(got[pix[:, 1], pix[:, 0]].astype(np.float64), refs)
