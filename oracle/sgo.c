@@ -818,12 +818,14 @@ int64_t sgo_render(const sgo_scene *sc, const sgo_view *v, const sgo_params *pr,
       }
     }
   }
+  /* the thread count of this call only (the process-wide default stays) */
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  const int team = nthreads > 0 ? (int)nthreads : omp_get_max_threads();
 #else
+  const int team = 1;
   (void)nthreads;
 #endif
-#pragma omp parallel reduction(+ : sum)
+#pragma omp parallel num_threads(team) reduction(+ : sum)
   {
     seg_t *segs = (seg_t *)malloc(sizeof(seg_t) * (size_t)(ncut > 0 ? ncut : 1));
 #pragma omp for schedule(dynamic, 16)
