@@ -28,7 +28,8 @@
  *
  * Conventions as in sg.h: every call returns an sg_status; device pointers
  * are read or written in hip_stream order; the upsampler owns its weights,
- * optimiser state and scratch; it is not thread-safe.
+ * optimiser state and scratch; it is not thread-safe, and calls on one
+ * upsampler that overlap on different streams race on its scratch.
  */
 #ifndef SG_UPSAMPLER_H
 #define SG_UPSAMPLER_H
@@ -59,15 +60,25 @@ sg_status sg_up_get_weights(sg_upsampler *up, float *params, int64_t n);
 /* Inference on n low-resolution images of h x w:
  *   rgba  device float [n][h][w][4] (a render's premultiplied output)
  *   depth device float [n][h][w]    (its first-hit depth, +inf = none)
+ *   content NULL, or device uint8 [n][(h + 7) / 8][(w + 7) / 8]: the
+ *         input's content mask as sg_render_views fills sg_view.tile_any
+ *         (one byte per 8 x 8-pixel block, nonzero if a pixel of the block
+ *         has a nonzero rgba component or a finite depth); the images'
+ *         masks back to back. With NULL the call builds the same mask from
+ *         rgba and depth. A mask byte of 0 where the block has content
+ *         gives wrong output there; extra nonzero bytes only cost time.
  *   out_rgba device float [n][2h][2w][4]
  *   out_err  NULL or device float [n][2h][2w] (predicted squared error)
  *   mse_pred NULL or host double [n]: mean predicted squared error per
  *            image (synchronises hip_stream when given)
- * n * h * w <= max_pixels. */
+ * n * h * w <= max_pixels. The fused network (the default) runs only on the
+ * 16 x 16 tiles whose input region (the tile and the 4-pixel reach of the
+ * four layers) meets a nonzero block of the mask; every other tile is
+ * background, written without a look at the input. */
 sg_status sg_up_forward(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
-                        const float *rgba, const float *depth, double depth_scale,
-                        float *out_rgba, float *out_err, double *mse_pred,
-                        void *hip_stream);
+                        const float *rgba, const float *depth, const uint8_t *content,
+                        double depth_scale, float *out_rgba, float *out_err,
+                        double *mse_pred, void *hip_stream);
 
 /* Inference as sg_up_forward, and the fallback decision taken on the device
  * without a host round trip: *fallback (device int32) = 1 when the frame's
@@ -76,9 +87,9 @@ sg_status sg_up_forward(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
  * the flag to sg_render_views_if to render the frame at full resolution
  * only when the prediction fails. Asynchronous. */
 sg_status sg_up_forward_flag(sg_upsampler *up, int32_t n, int32_t h, int32_t w,
-                             const float *rgba, const float *depth, double depth_scale,
-                             float *out_rgba, float *out_err, double threshold_db,
-                             int32_t *fallback, void *hip_stream);
+                             const float *rgba, const float *depth, const uint8_t *content,
+                             double depth_scale, float *out_rgba, float *out_err,
+                             double threshold_db, int32_t *fallback, void *hip_stream);
 
 /* Gradients of the training loss (mean squared RGBA error against target,
  * plus err_weight times the mean squared error of the error head against

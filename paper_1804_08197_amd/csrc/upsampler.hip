@@ -459,6 +459,7 @@ struct SumArgs {
   int32_t tiles;      // partials per image
   double pixels;      // full-resolution pixels per image
   double threshold_db;
+  int32_t* reset;     // NULL, or the tile-list counters, cleared for the next launch
 };
 
 // fallback = 1 when 10 log10(1 / m) < threshold, m the mean over the
@@ -473,38 +474,53 @@ __device__ __forceinline__ int32_t decide(const double* result, int n, double pi
 }
 
 // One workgroup of kSumThreads: result[i] = the partials of image i added
-// in a fixed order (deterministic): thread t adds partials t, t + kSumThreads,
-// ... (loaded four at a time so the loads are in flight together), then the
-// 64 lanes of each wave fold by xor-shuffles and wave 0 adds the waves' sums.
+// in a fixed order (deterministic). The 16 waves are split into groups of
+// wpi waves, one group per image (a stereo pair: 8 waves each), so that
+// the images' loads are in flight together; thread u of a group adds
+// partials u, u + 64 wpi, ... (four loads in flight), the 64 lanes of each
+// wave fold by xor-shuffles, and the group's waves' sums are added in wave
+// order. More images than waves take several rounds.
 constexpr int kSumThreads = 1024;
+constexpr int kSumWaves = kSumThreads / 64;
 __global__ __launch_bounds__(kSumThreads) void tile_sum_kernel(SumArgs a) {
-  __shared__ double red[kSumThreads / 64];
+  __shared__ double red[kSumWaves];
   const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int i = 0; i < a.images; ++i) {
-    const double* p = a.sum + (int64_t)i * a.tiles;
+  const int wpi = a.images >= kSumWaves ? 1 : kSumWaves / max(a.images, 1);
+  const int ipr = kSumWaves / wpi;  // images per round
+  const int g = wave / wpi;         // this wave's group (idle when g >= ipr)
+  const int stride = wpi * 64, u = (wave - g * wpi) * 64 + lane;
+  for (int r0 = 0; r0 < a.images; r0 += ipr) {
+    const int i = r0 + g;
     double v = 0.0;
-    for (int base = 0; base < a.tiles; base += 4 * kSumThreads) {
-      double x[4];
+    if (g < ipr && i < a.images) {
+      const double* p = a.sum + (int64_t)i * a.tiles;
+      for (int base = 0; base < a.tiles; base += 4 * stride) {
+        double x[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = base + j * kSumThreads + t;
-        x[j] = k < a.tiles ? p[k] : 0.0;
+        for (int j = 0; j < 4; ++j) {
+          const int k = base + j * stride + u;
+          x[j] = k < a.tiles ? p[k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v += x[j];
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v += x[j];
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    if (t == 0) {
+    if (t < ipr && r0 + t < a.images) {
       double r = 0.0;
-      for (int w = 0; w < kSumThreads / 64; ++w) r += red[w];
-      a.result[i] = r;
+      for (int w = 0; w < wpi; ++w) r += red[t * wpi + w];
+      a.result[r0 + t] = r;
     }
     __syncthreads();
   }
   if (t == 0 && a.fallback) *a.fallback = decide(a.result, a.images, a.pixels, a.threshold_db);
+  if (t == 0 && a.reset) {
+    a.reset[0] = 0;
+    a.reset[1] = 0;
+  }
 }
 
 // the workgroup's share of the predicted error, into its partial slot
@@ -687,33 +703,137 @@ __device__ __forceinline__ FusedLds fused_lds(float4* smem) {
 }
 static_assert(kE0 * kE0 + kE0 * kTile <= 256 * 8, "flags fit the scratch");
 
-// One workgroup per 16 x 16 tile (grid: tiles x, tiles y, images).
+// The tiles of one launch in two lists that share one array: the tiles
+// with content in reach from list[0] on, the empty tiles from
+// list[tiles - 1] down. A tile is numbered (image, tile row, tile column)
+// row-major, which is also its partial-sum slot.
+struct TileList {
+  int32_t* list;   // [tiles]
+  int32_t* count;  // [0]: tiles with content, [1]: empty tiles (zero before the launch)
+  int32_t tiles;
+  int32_t tiles_x, tiles_y;
+};
+
+// The content mask of an input without one, in the layout of the render's
+// tile_any mask: one byte per 8 x 8-pixel block, 1 if any of its pixels has
+// a nonzero rgba component or a finite depth (a superset of the pixels
+// whose x0 is nonzero). One wave per block, four blocks per workgroup.
+__global__ __launch_bounds__(256) void content_mask_kernel(const float4* __restrict__ rgba,
+                                                           const float* __restrict__ depth, int H,
+                                                           int W, int64_t blocks, int mh, int mw,
+                                                           uint8_t* __restrict__ mask) {
+  const int lane = threadIdx.x & 63;
+  const int64_t per = (int64_t)mh * mw;
+  // the same trip count for every lane of a wave
+  for (int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); blk < blocks;
+       blk += (int64_t)gridDim.x * 4) {
+    const int64_t n = blk / per;
+    const int r = (int)(blk - n * per);
+    const int y = (r / mw) * 8 + (lane >> 3), x = (r % mw) * 8 + (lane & 7);
+    bool nz = false;
+    if (y < H && x < W) {
+      const int64_t q = (n * H + y) * W + x;
+      const float4 c = rgba[q];
+      nz = c.x != 0.f || c.y != 0.f || c.z != 0.f || c.w != 0.f || depth[q] < INFINITY;
+    }
+    const uint64_t m = __ballot(nz);
+    if (lane == 0) mask[blk] = m != 0 ? 1 : 0;
+  }
+}
+
+static_assert(kTile == 16 && kReach <= 8, "a tile's input region meets at most 4 x 4 blocks");
+
+// One thread per 16 x 16 tile: the tile has content in reach when a block
+// of the mask that meets its input region (the tile and a kReach-pixel
+// ring, clamped to the image) is nonzero; the tile then joins the first
+// list, else the second (with a zero partial sum). A wave appends with one
+// atomic per list; the order within a list does not matter, since every
+// tile writes only its own pixels and its own partial-sum slot.
+__global__ __launch_bounds__(256) void tile_list_kernel(const uint8_t* __restrict__ mask, int H,
+                                                        int W, TileList tl, double* sum) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int per = tl.tiles_x * tl.tiles_y;
+  const int mh = (H + 7) >> 3, mw = (W + 7) >> 3;
+  // the same trip count for every lane of a wave
+  for (int base = (int)blockIdx.x * 256; base < tl.tiles; base += (int)gridDim.x * 256) {
+    const int t = base + (int)threadIdx.x;
+    const bool valid = t < tl.tiles;
+    bool any = false;
+    if (valid) {
+      const int n = t / per, r = t - n * per, ty = r / tl.tiles_x, tx = r - ty * tl.tiles_x;
+      const int y0 = max(ty * kTile - kReach, 0) >> 3;
+      const int y1 = min(ty * kTile + kTile - 1 + kReach, H - 1) >> 3;
+      const int x0 = max(tx * kTile - kReach, 0) >> 3;
+      const int x1 = min(tx * kTile + kTile - 1 + kReach, W - 1) >> 3;
+      const uint8_t* m = mask + (int64_t)n * mh * mw;
+      // at most 4 x 4 blocks (rows 16 ty - kReach .. 16 ty + 15 + kReach
+      // meet blocks 2 ty - 1 .. 2 ty + 2 when kReach <= 8): read as a fixed
+      // 4 x 4 with indices clamped into the range
+      // (repeats do not change the result), so every load is in flight at once
+      uint8_t v[4][4];
+#pragma unroll
+      for (int dy = 0; dy < 4; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 4; ++dx)
+          v[dy][dx] = m[min(y0 + dy, y1) * mw + min(x0 + dx, x1)];
+#pragma unroll
+      for (int dy = 0; dy < 4; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 4; ++dx) any |= v[dy][dx] != 0;
+      if (!any && sum) sum[t] = 0.0;
+    }
+    const uint64_t hv = __ballot(valid && any), ev = __ballot(valid && !any);
+    int hb = 0, eb = 0;
+    if (lane == 0) {
+      if (hv) hb = atomicAdd(&tl.count[0], __popcll(hv));
+      if (ev) eb = atomicAdd(&tl.count[1], __popcll(ev));
+    }
+    hb = __shfl(hb, 0);
+    eb = __shfl(eb, 0);
+    if (valid && any) tl.list[hb + __popcll(hv & below)] = t;
+    if (valid && !any) tl.list[tl.tiles - 1 - (eb + __popcll(ev & below))] = t;
+  }
+}
+
+// One workgroup per list entry (grid: tiles). The lists partition the
+// array, so entry b < count[0] is a tile with content and every later entry
+// an empty tile. Workgroups are dispatched in grid order, so the tiles that
+// run the network start first and the empty tiles, whose only work is
+// storing background without a look at the input, stream through the
+// remaining slots beside them. A tile of the first list whose exact input
+// region turns out empty (the mask is per 8 x 8 block) is cleared as well:
+// every tile's output is what a test of its own input region gives.
 __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 fused_forward_kernel(
-    const float4* __restrict__ rgba, const float* __restrict__ depth, int N, int H, int W,
+    const float4* __restrict__ rgba, const float* __restrict__ depth, int H, int W,
     float inv_scale, const bf16x8* __restrict__ w0, const bf16x8* __restrict__ w1,
     const bf16x8* __restrict__ w2, const bf16x8* __restrict__ w3, const float* __restrict__ b0,
     const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
-    float4* __restrict__ out, float* __restrict__ err, SumArgs sums) {
+    float4* __restrict__ out, float* __restrict__ err, SumArgs sums, TileList tl) {
+  const int b = (int)blockIdx.x;
+  const int t = tl.list[b];
+  const int per = tl.tiles_x * tl.tiles_y;
+  const int n = t / per, r = t - n * per;
+  const int ty0 = (r / tl.tiles_x) * kTile, tx0 = (r % tl.tiles_x) * kTile;
+  if (b >= tl.count[0]) {  // empty tile (its partial sum is already zero)
+    clear_tile(n, H, W, ty0, tx0, out, err);
+    return;
+  }
   const FusedLds l = fused_lds(fused_smem);
-  const int n = blockIdx.z;
-  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
-  const int64_t slot = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
   load_weights<8>(w0, wa);
   const bool any_nz = prep_region(rgba, depth, H, W, inv_scale, n, ty0, tx0, l.sV, l.nzf, l.sX);
-  const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
-  const int y = ty0 + qy, x = tx0 + qx;
   if (!__syncthreads_or(any_nz)) {
-    // the whole region is empty: every pixel of the tile is background, and
-    // the tile's partial sum is zero
     clear_tile(n, H, W, ty0, tx0, out, err);
-    if (sums.sum && threadIdx.x == 0) sums.sum[slot] = 0.0;
+    if (sums.sum && threadIdx.x == 0) sums.sum[t] = 0.0;
     return;
   }
+  const int qy = threadIdx.x / kTile, qx = threadIdx.x % kTile;
+  const int y = ty0 + qy, x = tx0 + qx;
   const float zsum = fused_tile(l.sU, l.sV, l.sX, l.nzf, l.rowany, wa, wb, wc, w1, w2, w3, b0,
                                 b1, b2, b3, n, H, W, ty0, tx0, qy, qx, y, x, out, err);
-  if (sums.sum) tile_partial(sums, l.red, zsum, slot);
+  if (sums.sum) tile_partial(sums, l.red, zsum, t);
 }
 
 
@@ -902,6 +1022,8 @@ struct sg_upsampler {
   int part_blocks = 0;
   double* acc = nullptr;    // device doubles: loss, partials or sums, per-image results
   int64_t acc_n = 0;
+  int32_t* tl = nullptr;    // tile-list counters [4] (zero between launches), list [max_pixels]
+  uint8_t* mask = nullptr;  // content mask built from an input without one [max_pixels]
   bool packed = false;
   bool fused = true;        // inference through fused_forward_kernel
 };
@@ -909,7 +1031,8 @@ struct sg_upsampler {
 namespace {
 
 void up_free(sg_upsampler* u) {
-  void* ptrs[] = {u->params, u->grads, u->m, u->v, u->x0, u->o, u->ga, u->gb, u->part, u->acc};
+  void* ptrs[] = {u->params, u->grads, u->m,    u->v,   u->x0, u->o,
+                  u->ga,     u->gb,    u->part, u->acc, u->tl, u->mask};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int l = 0; l < kLayers; ++l) {
@@ -1020,8 +1143,9 @@ sg_status gradients(sg_upsampler* u, int n, int h, int w, const float* rgba, con
 // fallback flag, the frame's decision in *fallback), added in a fixed order
 // from per-workgroup partials that every launch overwrites.
 sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
-                const float* depth, double depth_scale, float* out_rgba, float* out_err,
-                bool sums, int32_t* fallback, double threshold_db, hipStream_t s) {
+                const float* depth, const uint8_t* content, double depth_scale,
+                float* out_rgba, float* out_err, bool sums, int32_t* fallback,
+                double threshold_db, hipStream_t s) {
   sg_status st = check_batch(up, n, h, w, rgba, depth);
   if (st != SG_OK) return st;
   if (!out_rgba || !(std::isfinite(depth_scale) && depth_scale > 0.0))
@@ -1037,13 +1161,28 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
     sa.pixels = 4.0 * (double)h * w;
     sa.threshold_db = threshold_db;
   }
-  if (up->fused && n <= 65535) {
+  if (up->fused) {
     if (!up->packed && (st = pack_weights(up, s)) != SG_OK) return st;
     const float* b = up->params;
-    const dim3 grid((unsigned)((w + kTile - 1) / kTile), (unsigned)((h + kTile - 1) / kTile),
-                    (unsigned)n);
-    sa.tiles = (int32_t)(grid.x * grid.y);
+    // tiles <= n h w <= max_pixels: one list entry and one partial slot each
+    TileList tl;
+    tl.tiles_x = (w + kTile - 1) / kTile;
+    tl.tiles_y = (h + kTile - 1) / kTile;
+    tl.tiles = (int32_t)((int64_t)n * tl.tiles_x * tl.tiles_y);
+    tl.count = up->tl;
+    tl.list = up->tl + 4;
+    sa.tiles = tl.tiles_x * tl.tiles_y;
+    sa.reset = up->tl;
     const float4* in4 = reinterpret_cast<const float4*>(rgba);
+    if (!content) {
+      const int mh = (h + 7) / 8, mw = (w + 7) / 8;
+      const int64_t blocks = (int64_t)n * mh * mw;  // <= max_pixels
+      hipLaunchKernelGGL(content_mask_kernel, dim3(blocks_of(blocks, 4)), dim3(256), 0, s, in4,
+                         depth, h, w, blocks, mh, mw, up->mask);
+      content = up->mask;
+    }
+    hipLaunchKernelGGL(tile_list_kernel, dim3(blocks_of(tl.tiles)), dim3(256), 0, s, content, h,
+                       w, tl, sums ? sa.sum : nullptr);
     const bf16x8* fw0 = reinterpret_cast<const bf16x8*>(up->fw[0]);
     const bf16x8* fw1 = reinterpret_cast<const bf16x8*>(up->fw[1]);
     const bf16x8* fw2 = reinterpret_cast<const bf16x8*>(up->fw[2]);
@@ -1052,10 +1191,12 @@ sg_status infer(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* 
                 *b2 = b + layer_off(2) + 9 * 32 * kCh, *b3 = b + layer_off(3) + 9 * 32 * kCh;
     SG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fused_forward_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds));
-    hipLaunchKernelGGL(fused_forward_kernel, grid, dim3(256), kFusedLds, s, in4, depth, n, h, w,
-                       (float)(1.0 / depth_scale), fw0, fw1, fw2, fw3, b0, b1, b2, b3,
-                       reinterpret_cast<float4*>(out_rgba), out_err, sa);
-    if (sums) hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sa);
+    hipLaunchKernelGGL(fused_forward_kernel, dim3((unsigned)tl.tiles), dim3(256), kFusedLds, s, in4,
+                       depth, h, w, (float)(1.0 / depth_scale), fw0, fw1, fw2, fw3, b0, b1, b2,
+                       b3, reinterpret_cast<float4*>(out_rgba), out_err, sa, tl);
+    // per-image sums and the decision when asked; always the counters' reset
+    if (!sums) sa.images = 0;
+    hipLaunchKernelGGL(tile_sum_kernel, dim3(1), dim3(kSumThreads), 0, s, sa);
     SG_HIP(hipGetLastError());
   } else {
     if ((st = forward(up, n, h, w, rgba, depth, depth_scale, s)) != SG_OK) return st;
@@ -1110,6 +1251,8 @@ sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler** out) {
   al((void**)&u->gb, max_pixels * kCh * 2);
   al((void**)&u->part, (int64_t)u->part_blocks * (9 * 32 * kCh + kCh) * 4);
   al((void**)&u->acc, u->acc_n * 8);
+  al((void**)&u->tl, (4 + max_pixels) * 4);
+  al((void**)&u->mask, max_pixels);
   if (!ok) {
     up_free(u);
     (void)hipGetLastError();
@@ -1119,6 +1262,7 @@ sg_status sg_up_create(int32_t device, int64_t max_pixels, sg_upsampler** out) {
       hipMemset(u->m, 0, kParams * 4) != hipSuccess ||
       hipMemset(u->v, 0, kParams * 4) != hipSuccess ||
       hipMemset(u->acc, 0, (size_t)u->acc_n * 8) != hipSuccess ||
+      hipMemset(u->tl, 0, 16) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     up_free(u);
     return fail(SG_ERR_DEVICE, "sg_up_create: initialisation failed");
@@ -1159,10 +1303,10 @@ sg_status sg_up_get_weights(sg_upsampler* up, float* params, int64_t n) {
 }
 
 sg_status sg_up_forward(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const float* rgba,
-                        const float* depth, double depth_scale, float* out_rgba, float* out_err,
-                        double* mse_pred, void* hip_stream) {
+                        const float* depth, const uint8_t* content, double depth_scale,
+                        float* out_rgba, float* out_err, double* mse_pred, void* hip_stream) {
   hipStream_t s = (hipStream_t)hip_stream;
-  sg_status st = infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err,
+  sg_status st = infer(up, n, h, w, rgba, depth, content, depth_scale, out_rgba, out_err,
                        mse_pred != nullptr, nullptr, 0.0, s);
   if (st != SG_OK) return st;
   if (mse_pred) {
@@ -1176,12 +1320,12 @@ sg_status sg_up_forward(sg_upsampler* up, int32_t n, int32_t h, int32_t w, const
 }
 
 sg_status sg_up_forward_flag(sg_upsampler* up, int32_t n, int32_t h, int32_t w,
-                             const float* rgba, const float* depth, double depth_scale,
-                             float* out_rgba, float* out_err, double threshold_db,
-                             int32_t* fallback, void* hip_stream) {
+                             const float* rgba, const float* depth, const uint8_t* content,
+                             double depth_scale, float* out_rgba, float* out_err,
+                             double threshold_db, int32_t* fallback, void* hip_stream) {
   if (!fallback || std::isnan(threshold_db))
     return fail(SG_ERR_INVALID_ARG, "sg_up_forward_flag: NULL flag or NaN threshold");
-  return infer(up, n, h, w, rgba, depth, depth_scale, out_rgba, out_err, true, fallback,
+  return infer(up, n, h, w, rgba, depth, content, depth_scale, out_rgba, out_err, true, fallback,
                threshold_db, (hipStream_t)hip_stream);
 }
 

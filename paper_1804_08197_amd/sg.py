@@ -26,7 +26,7 @@ SG_LOD, SG_SKIP_EMPTY, SG_GATHER = 1, 2, 4
 SG_MODEL_EMISSION_ABSORPTION, SG_MODEL_EMISSION_ONLY, SG_MODEL_MAX_INTENSITY = 0, 1, 2
 MODELS = {"ea": SG_MODEL_EMISSION_ABSORPTION, "eo": SG_MODEL_EMISSION_ONLY,
           "mip": SG_MODEL_MAX_INTENSITY}
-SG_ABI_VERSION = 3
+SG_ABI_VERSION = 4
 
 
 class SgError(RuntimeError):

@@ -97,7 +97,11 @@ class UpsampledPath:
 
     def __init__(self, vol, model: "up.Upsampler", depth_scale: float, base_params: dict,
                  width: int, height: int, n_views: int = 2, threshold_db: float = 40.0,
-                 lod=False):
+                 lod=False, launch_half=None, launch_full=None):
+        """launch_half / launch_full: None, or the launch configuration
+        (sg_set_launch_config) for the half-resolution render and for the
+        full-resolution fallback render; the images are the same under any
+        configuration, only their speed differs."""
         import torch
         if int(width) < 2 or int(height) < 2 or int(width) % 2 or int(height) % 2:
             raise ValueError("width and height must be even: the network writes rows of "
@@ -110,8 +114,20 @@ class UpsampledPath:
         self.rgba_lo = torch.empty(n_views, h2, w2, 4, device="cuda")
         self.depth_lo = torch.empty(n_views, h2, w2, device="cuda")
         self.out = torch.empty(n_views, height, width, 4, device="cuda")
+        # the half-resolution render's content mask (tile_any), which tells
+        # the network which tiles hold anything but background
+        self.content = torch.empty(n_views, (h2 + 7) // 8, (w2 + 7) // 8, dtype=torch.uint8,
+                                   device="cuda")
         self.size = (int(width), int(height), int(n_views))
+        self.launch_half, self.launch_full = launch_half, launch_full
         self._structs = None
+
+    def _launch(self, cfg):
+        if cfg is not None:
+            sg.sg_set_launch_config(self.vol, cfg)
+
+    def _half_views(self, views):
+        return [dict(half_view(v), tile_any=self.content[i]) for i, v in enumerate(views)]
 
     def _check(self, views):
         w, h, n = self.size
@@ -122,10 +138,11 @@ class UpsampledPath:
         """Half-resolution render and network pass; returns the predicted
         PSNR of the frame (all views together)."""
         self._check(views)
-        sg.sg_render_views(self.vol, [half_view(v) for v in views], self.p_half,
+        self._launch(self.launch_half)
+        sg.sg_render_views(self.vol, self._half_views(views), self.p_half,
                            list(self.rgba_lo), list(self.depth_lo))
         mse = self.model.forward(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
-                                 predict=True)
+                                 predict=True, content=self.content)
         m = float(np.mean(mse))
         return math.inf if m <= 0 else 10.0 * math.log10(1.0 / m)
 
@@ -134,6 +151,7 @@ class UpsampledPath:
         the prediction falls below the threshold. Returns (images, fell_back)."""
         fell_back = self.predicted_psnr(views) < self.threshold_db
         if fell_back:
+            self._launch(self.launch_full)
             sg.sg_render_views(self.vol, views, self.p_full, list(self.out))
         return self.out, fell_back
 
@@ -146,9 +164,11 @@ class UpsampledPath:
             self._structs = (sg.make_params(self.p_half), sg.make_params(self.p_full),
                              list(self.rgba_lo), list(self.depth_lo), list(self.out))
         ph, pf, lo, dlo, out = self._structs
-        sg.sg_render_views(self.vol, [half_view(v) for v in views], ph, lo, dlo)
+        self._launch(self.launch_half)
+        sg.sg_render_views(self.vol, self._half_views(views), ph, lo, dlo)
         self.model.forward_flag(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
-                                self.threshold_db, flag)
+                                self.threshold_db, flag, content=self.content)
+        self._launch(self.launch_full)
         sg.sg_render_views_if(self.vol, views, pf, out, flag)
         return self.out
 

@@ -18,16 +18,16 @@ _lib.sg_up_create.argtypes = [C.c_int32, C.c_int64, C.POINTER(_P)]
 _lib.sg_up_destroy.argtypes = [_P]
 _lib.sg_up_set_weights.argtypes = [_P, C.POINTER(C.c_float), C.c_int64]
 _lib.sg_up_get_weights.argtypes = [_P, C.POINTER(C.c_float), C.c_int64]
-_lib.sg_up_forward.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P, _P,
-                               C.POINTER(C.c_double), _P]
+_lib.sg_up_forward.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_double, _P,
+                               _P, C.POINTER(C.c_double), _P]
 _lib.sg_up_gradients.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P,
                                  C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_double), _P]
 _lib.sg_up_train_step.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P,
                                   C.c_double, C.c_double, C.POINTER(C.c_double), _P]
 _lib.sg_up_read_buffer.argtypes = [_P, C.c_int32, _P, C.c_int64]
 _lib.sg_up_set_fused.argtypes = [_P, C.c_int32]
-_lib.sg_up_forward_flag.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, C.c_double, _P,
-                                    _P, C.c_double, _P, _P]
+_lib.sg_up_forward_flag.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_double,
+                                    _P, _P, C.c_double, _P, _P]
 for _f in ("sg_up_create", "sg_up_destroy", "sg_up_set_weights", "sg_up_get_weights",
            "sg_up_forward", "sg_up_gradients", "sg_up_train_step", "sg_up_read_buffer",
            "sg_up_set_fused", "sg_up_forward_flag"):
@@ -87,21 +87,23 @@ class Upsampler:
         return v
 
     def forward(self, rgba, depth, depth_scale, out_rgba, out_err=None, predict=False,
-                stream=None):
+                stream=None, content=None):
+        """content: None, or the input's content mask (uint8 device tensor
+        [n][(h + 7) // 8][(w + 7) // 8], as the render fills tile_any)."""
         n, h, w = rgba.shape[:3]
         mse = (C.c_double * n)() if predict else None
-        sg._check(_lib.sg_up_forward(self.h, n, h, w, _dp(rgba), _dp(depth), float(depth_scale),
-                                     _dp(out_rgba), _dp(out_err), mse, sg._stream(stream)),
-                  "sg_up_forward")
+        sg._check(_lib.sg_up_forward(self.h, n, h, w, _dp(rgba), _dp(depth), _dp(content),
+                                     float(depth_scale), _dp(out_rgba), _dp(out_err), mse,
+                                     sg._stream(stream)), "sg_up_forward")
         return np.array(mse[:]) if predict else None
 
     def forward_flag(self, rgba, depth, depth_scale, out_rgba, threshold_db, fallback,
-                     out_err=None, stream=None):
+                     out_err=None, stream=None, content=None):
         """Inference and the fallback decision on the device: fallback (a
         one-element int32 device tensor) = 1 when the predicted PSNR of the
         batch is below threshold_db. Asynchronous."""
         n, h, w = rgba.shape[:3]
-        sg._check(_lib.sg_up_forward_flag(self.h, n, h, w, _dp(rgba), _dp(depth),
+        sg._check(_lib.sg_up_forward_flag(self.h, n, h, w, _dp(rgba), _dp(depth), _dp(content),
                                           float(depth_scale), _dp(out_rgba), _dp(out_err),
                                           float(threshold_db), _dp(fallback),
                                           sg._stream(stream)), "sg_up_forward_flag")

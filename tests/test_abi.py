@@ -92,7 +92,7 @@ int main(void) {
 
 
 def test_version_and_status_strings(sg):
-    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 3
+    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 4
     for code, name in [(0, "SG_OK"), (-1, "SG_ERR_INVALID_ARG"), (-2, "SG_ERR_OUT_OF_MEMORY"),
                        (-3, "SG_ERR_DEVICE"), (-4, "SG_ERR_STATE"), (-5, "SG_ERR_UNSUPPORTED")]:
         assert sg.sg_status_string(code) == name
@@ -131,8 +131,10 @@ def test_null_arguments_are_invalid(sg):
         sg.SG_ERR_INVALID_ARG
     assert lib.sg_composite_over(None, 1, None, None, None, None) == sg.SG_ERR_INVALID_ARG
     from paper_1804_08197_amd import upsampler as up
-    assert up._lib.sg_up_forward_flag(None, 1, 1, 1, None, None, 1.0, None, None, 40.0, None,
-                                      None) == sg.SG_ERR_INVALID_ARG
+    assert up._lib.sg_up_forward_flag(None, 1, 1, 1, None, None, None, 1.0, None, None, 40.0,
+                                      None, None) == sg.SG_ERR_INVALID_ARG
+    assert up._lib.sg_up_forward(None, 1, 1, 1, None, None, None, 1.0, None, None, None,
+                                 None) == sg.SG_ERR_INVALID_ARG
     assert up._lib.sg_up_set_fused(None, 1) == sg.SG_ERR_INVALID_ARG
 
 

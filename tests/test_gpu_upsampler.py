@@ -391,6 +391,111 @@ def test_empty_neighbourhoods_yield_background(shape):
         u.close()
 
 
+def block_mask(rgba, depth):
+    """Per 8 x 8-pixel block: any pixel with a nonzero rgba component or a
+    finite depth (the render's tile_any rule)."""
+    n, h, w = depth.shape
+    nz = (rgba != 0).any(-1) | np.isfinite(depth)
+    mh, mw = (h + 7) // 8, (w + 7) // 8
+    pad = np.zeros((n, mh * 8, mw * 8), bool)
+    pad[:, :h, :w] = nz
+    return pad.reshape(n, mh, 8, mw, 8).any(axis=(2, 4)).astype(np.uint8)
+
+
+def test_content_mask_drives_the_same_frame():
+    """The fused network runs only on tiles the content mask marks (dilated
+    by the layers' reach); all others are background without a look at the
+    input. Every source of the mask (built by the call, computed here, all
+    ones) gives the layered path's output bit for bit, over two calls in a
+    row with different inputs and sizes (the tile lists' counters start at
+    zero on each call), on sparse and dense inputs."""
+    import torch
+
+    from paper_1804_08197_amd import upsampler as up
+    rng = np.random.default_rng(77)
+    params = bf16_params(rng, 0.5)
+    u = up.Upsampler(2 * 96 * 130)
+    try:
+        u.set_weights(up.pack(params))
+        for (n, h, w), sparse in (((2, 96, 130), True), ((1, 37, 53), False),
+                                  ((2, 61, 45), True)):
+            rgba = np.zeros((n, h, w, 4), np.float32)
+            depth = np.full((n, h, w), np.inf, np.float32)
+            if sparse:
+                for i in range(n):
+                    for _ in range(4):
+                        y0, x0_ = rng.integers(0, h), rng.integers(0, w)
+                        sl = (i, slice(y0, min(h, y0 + 2)), slice(x0_, min(w, x0_ + 3)))
+                        a = rng.uniform(0.2, 1.0, size=rgba[sl].shape[:-1] + (1,))
+                        rgba[sl] = np.concatenate([rng.uniform(0, 1, a.shape[:-1] + (3,)) * a, a],
+                                                  -1).astype(np.float32)
+                        depth[sl] = rng.uniform(10, 300, size=depth[sl].shape)
+            else:
+                rgba[:] = rng.uniform(0, 1, size=rgba.shape)
+                depth[:] = rng.uniform(0, 300, size=depth.shape)
+            trgba, tdepth = torch.from_numpy(rgba).cuda(), torch.from_numpy(depth).cuda()
+            mask = block_mask(rgba, depth)
+            masks = {"built": None, "given": torch.from_numpy(mask).cuda(),
+                     "ones": torch.ones(mask.shape, dtype=torch.uint8, device="cuda")}
+            u.set_fused(False)
+            ref = torch.full((n, 2 * h, 2 * w, 4), float("nan"), device="cuda")
+            ref_err = torch.full((n, 2 * h, 2 * w), float("nan"), device="cuda")
+            m_ref = u.forward(trgba, tdepth, SCALE, ref, ref_err, predict=True)
+            u.set_fused(True)
+            for name, m in masks.items():
+                out = torch.full_like(ref, float("nan"))
+                err = torch.full_like(ref_err, float("nan"))
+                mse = u.forward(trgba, tdepth, SCALE, out, err, predict=True, content=m)
+                assert torch.equal(out, ref), (n, h, w, name)
+                assert torch.equal(err, ref_err), (n, h, w, name)
+                assert np.allclose(mse, m_ref, rtol=1e-12, atol=0), (n, h, w, name)
+            log("%s sparse=%s: %d of %d blocks with content, all masks == layered" % (
+                (n, h, w), sparse, int(mask.sum()), mask.size))
+    finally:
+        u.close()
+
+
+def test_render_tile_mask_feeds_the_network():
+    """The half-resolution render's own tile_any mask, handed to the network,
+    gives the frame the network gives when it builds the mask itself (and
+    the mask equals the 8 x 8-block rule applied to the render's output)."""
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg
+    from paper_1804_08197_amd import upsampler as up
+    from tests.helpers import gpu_volume
+    vol = gen.random_volume((48, 40, 56), 33, dtype=np.uint8)
+    h = gpu_volume([vol], 16, 3, [gen.tf_identity()], [(0, 255)])
+    W2, H2 = 150, 94
+    vs = gen.stereo(np.array([150.0, -90.0, 80.0]), np.array([28.0, 20.0, 24.0]), 4.0, W2, H2,
+                    0.5, 0.5 * W2 / H2)
+    n, hh, ww = 2, H2 // 2, W2 // 2
+    u = up.Upsampler(n * hh * ww)
+    try:
+        u.set_weights(up.pack(bf16_params(np.random.default_rng(18))))
+        rgba = torch.empty(n, hh, ww, 4, device="cuda")
+        depth = torch.empty(n, hh, ww, device="cuda")
+        tiles = torch.full((n, (hh + 7) // 8, (ww + 7) // 8), 7, dtype=torch.uint8, device="cuda")
+        half = [dict(v, width=ww, height=hh, tile_any=tiles[i]) for i, v in enumerate(vs)]
+        sg.sg_render_views(h, half, {"ert": 0.99, "skip_empty": 1, "lod": 0, "bias": 1,
+                                     "depth_alpha": 0.5}, list(rgba), list(depth))
+        torch.cuda.synchronize()
+        want_mask = block_mask(rgba.cpu().numpy(), depth.cpu().numpy())
+        assert np.array_equal(tiles.cpu().numpy(), want_mask)
+        assert want_mask.any() and not want_mask.all()
+        outs = []
+        for m in (None, tiles):
+            out = torch.full((n, 2 * hh, 2 * ww, 4), float("nan"), device="cuda")
+            mse = u.forward(rgba, depth, 100.0, out, predict=True, content=m)
+            outs.append((out, mse))
+        assert torch.equal(outs[0][0], outs[1][0])
+        assert np.array_equal(outs[0][1], outs[1][1])
+    finally:
+        u.close()
+        sg.sg_volume_destroy(h)
+
+
 def test_full_size_stereo_input_sampled_parity():
     """The benchmark's network input (two eyes of 720 x 800, sparse content
     as in the blob scene): fused inference equals the layered path bit for
