@@ -92,6 +92,24 @@ int log2i(int x) {
   return l;
 }
 
+// The early-termination test on the transmittance: the largest float t with
+// fl(1 - t) >= ert. fl(1 - t) never rises as t rises, so for every float T
+// the test T <= t decides exactly as 1 - T >= ert does, one subtraction
+// fewer per sample. NaN stays NaN (no ray terminates, as before).
+float ert_transmittance(float ert) {
+  if (std::isnan(ert)) return ert;
+  const float one = 1.0f;
+  float t = (float)(1.0 - (double)ert);
+  for (int i = 0; i < 64 && !(one - t >= ert); ++i) t = std::nextafter(t, -INFINITY);
+  for (int i = 0; i < 64; ++i) {
+    const float u = std::nextafter(t, INFINITY);
+    if (!(one - u >= ert)) break;
+    t = u;
+  }
+  return t;
+}
+
+
 // Arguments shared by the stream path and the graph path.
 void fill_args(const Volume* v, const sg_render_params* params, int n_views,
                const ViewDev* dviews, const int32_t* cutmap, int64_t blocks,
@@ -153,6 +171,7 @@ void fill_args(const Volume* v, const sg_render_params* params, int n_views,
   a.stage_bytes = cfg.stage_bytes;
   a.step = params->step_voxels;
   a.ert = (float)params->ert_alpha;
+  a.t_ert = ert_transmittance(a.ert);
   a.depth_alpha = (float)params->depth_alpha;
   a.model = params->model;
   a.n_planes = params->n_planes;

@@ -525,18 +525,18 @@ __device__ __forceinline__ bool composite_ea(Ray& r, const RenderArgs& a, const 
   r.Cg = fmaf(wgt, z.eg, r.Cg);
   r.Cb = fmaf(wgt, z.eb, r.Cb);
   r.T = tn;
-  const float A = 1.0f - tn;
   // depth: tau rises along the segment, so the first sample whose alpha
   // reached the threshold has the smallest tau (the depth itself, t0 + tau in FP64,
   // is formed once per segment by finish_depth)
-  if (DEPTH) r.dtau = (A >= a.depth_alpha && tau < r.dtau) ? tau : r.dtau;
-  return !(A >= a.ert);
+  if (DEPTH) r.dtau = (1.0f - tn >= a.depth_alpha && tau < r.dtau) ? tau : r.dtau;
+  // A = 1 - T >= ert, decided on T itself (t_ert: the exact FP32 bound)
+  return !(tn <= a.t_ert);
 }
 
 // Has the ray terminated early (emission-absorption)? The same test, on the
 // same value, as composite_ea's.
 __device__ __forceinline__ bool terminated(const Ray& r, const RenderArgs& a) {
-  return 1.0f - r.T >= a.ert;
+  return r.T <= a.t_ert;
 }
 
 // Which step a sample_step takes: a full one, the segment's last (partial)
@@ -1223,10 +1223,12 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           const char* sb = reinterpret_cast<const char*>(stage - base_off);
           const int syb = sy_l * (int)sizeof(T), szb = sy_l * wy * (int)sizeof(T);
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            // stencil corner in bytes: every term below 2^23 (24-bit products)
-            const int off = __mul24(iz, szb) + __mul24(iy, syb) + ix * (int)sizeof(T);
-            return trilinear_bytes<T>(sb + ch * cap * (int)sizeof(T) + off, syb, szb, fx, fy,
-                                      fz);
+            // stencil corner: x step, then the row and plane steps as 24-bit
+            // multiply-adds (every term below 2^23)
+            const char* p = sb + ch * cap * (int)sizeof(T) + ix * (int)sizeof(T);
+            p += __mul24(iy, syb);
+            p += __mul24(iz, szb);
+            return trilinear_bytes<T>(p, syb, szb, fx, fy, fz);
           };
           if (depth_on)
             sample_run<MODEL, CH, STATS, false, true>(r, a, s_tf, fetch, kb, mb_key);

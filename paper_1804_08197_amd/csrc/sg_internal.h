@@ -312,6 +312,7 @@ struct RenderArgs {
   int32_t stage_bytes;  // LDS staging bytes per wave
   double step;
   float ert;
+  float t_ert;          // the largest float T with fl(1 - T) >= ert: T <= t_ert terminates
   float depth_alpha;
   int32_t model;        // kModel*
   int32_t n_planes;     // cut planes in use (0..4)
