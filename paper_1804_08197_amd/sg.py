@@ -189,15 +189,13 @@ def make_view(v) -> sg_view:
     if isinstance(v, sg_view):
         return v
     o = sg_view()
-    m = np.asarray(v["cam_to_world"], dtype=np.float64).reshape(16)
-    for i in range(16):
-        o.cam_to_world[i] = float(m[i])
+    o.cam_to_world[:] = np.asarray(v["cam_to_world"], dtype=np.float64).reshape(16).tolist()
     o.tan_left, o.tan_right = float(v["tan_left"]), float(v["tan_right"])
     o.tan_bottom, o.tan_top = float(v["tan_bottom"]), float(v["tan_top"])
     o.width, o.height = int(v["width"]), int(v["height"])
-    lens = v.get("lens") or (0.0, 0.0, 0.0, 0.0)
-    for i in range(4):
-        o.lens[i] = float(lens[i])
+    lens = v.get("lens")
+    if lens:
+        o.lens[:] = [float(x) for x in lens]
     lim = _ptr(v.get("ray_limit"))
     o.ray_limit = lim.value if lim is not None else None
     ta = _ptr(v.get("tile_any"))
@@ -303,8 +301,31 @@ def sg_set_transfer_function(vol, channel, rgba, domain_lo, domain_hi):
 
 
 def _views(views):
-    arr = (sg_view * len(views))(*[make_view(v) for v in views])
-    return arr
+    """An sg_view array from view dicts (or the prebuilt array itself)."""
+    if isinstance(views, C.Array):
+        return views
+    return (sg_view * len(views))(*[make_view(v) for v in views])
+
+
+def _ptrs(tensors):
+    """A device-pointer array from tensors (None entries stay NULL), or the
+    prebuilt array itself."""
+    if isinstance(tensors, C.Array):
+        return tensors
+    return (C.c_void_p * len(tensors))(*[(t.data_ptr() if t is not None else None)
+                                         for t in tensors])
+
+
+def views_array(views):
+    """Pack view dicts once into an sg_view array that the render calls
+    accept as they are (for callers that render the same views more than
+    once, or derive one set of views from another)."""
+    return _views(views)
+
+
+def pointer_array(tensors):
+    """Pack the device addresses of output tensors once (see views_array)."""
+    return _ptrs(tensors)
 
 
 def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
@@ -312,10 +333,8 @@ def sg_render_views(vol, views, params, out_rgba, out_depth=None, stream=None):
     n = len(views)
     varr = _views(views)
     p = params if isinstance(params, sg_render_params) else make_params(params)
-    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
-    dep = None
-    if out_depth is not None:
-        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    rgba = _ptrs(out_rgba)
+    dep = _ptrs(out_depth) if out_depth is not None else None
     _check(_lib.sg_render_views(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
            "sg_render_views")
 
@@ -326,10 +345,8 @@ def sg_render_views_noalloc(vol, views, params, out_rgba, out_depth=None, stream
     n = len(views)
     varr = _views(views)
     p = params if isinstance(params, sg_render_params) else make_params(params)
-    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
-    dep = None
-    if out_depth is not None:
-        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    rgba = _ptrs(out_rgba)
+    dep = _ptrs(out_depth) if out_depth is not None else None
     _check(_lib.sg_render_views_noalloc(vol, n, varr, C.byref(p), rgba, dep, _stream(stream)),
            "sg_render_views_noalloc")
 
@@ -339,10 +356,8 @@ def sg_render_views_if(vol, views, params, out_rgba, enable, out_depth=None, str
     n = len(views)
     varr = _views(views)
     p = params if isinstance(params, sg_render_params) else make_params(params)
-    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
-    dep = None
-    if out_depth is not None:
-        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    rgba = _ptrs(out_rgba)
+    dep = _ptrs(out_depth) if out_depth is not None else None
     if enable is None:
         raise ValueError("sg_render_views_if needs a device flag")
     _check(_lib.sg_render_views_if(vol, n, varr, C.byref(p), rgba, dep,
@@ -369,10 +384,8 @@ def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samp
     n = len(views)
     varr = _views(views)
     p = make_params(params)
-    rgba = (C.c_void_p * n)(*[o.data_ptr() for o in out_rgba])
-    dep = None
-    if out_depth is not None:
-        dep = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_depth])
+    rgba = _ptrs(out_rgba)
+    dep = _ptrs(out_depth) if out_depth is not None else None
     st = sg_render_stats()
     if out_samples is not None:
         smp = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in out_samples])
@@ -430,14 +443,20 @@ def _launch_struct(cfg) -> sg_launch_config:
     return o
 
 
+def launch_config_struct(cfg) -> sg_launch_config:
+    """A launch configuration dict packed once (sg_set_launch_config takes it
+    as it is)."""
+    return _launch_struct(cfg)
+
+
 def _launch_dict(o: sg_launch_config) -> dict:
     return {k: int(getattr(o, k)) for k in LAUNCH_FIELDS}
 
 
 def sg_set_launch_config(vol, cfg=None):
-    """cfg: dict with kernel / tile / block / stage_bytes / persistent, or
-    None for the default."""
-    c = _launch_struct(cfg) if cfg is not None else None
+    """cfg: dict with kernel / tile / block / stage_bytes / persistent, a
+    prebuilt sg_launch_config, or None for the default."""
+    c = cfg if isinstance(cfg, sg_launch_config) or cfg is None else _launch_struct(cfg)
     _check(_lib.sg_set_launch_config(vol, C.byref(c) if c is not None else None),
            "sg_set_launch_config")
 

@@ -16,6 +16,7 @@ Orchestration only: every render, network pass and update runs in libsg.
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
 
 import numpy as np
@@ -160,16 +161,33 @@ class UpsampledPath:
         host round trip: flag (one-element int32 device tensor) receives 1
         when the frame fell back. Asynchronous; returns the images."""
         self._check(views)
-        if self._structs is None:  # built once: the per-frame calls only pack views
-            self._structs = (sg.make_params(self.p_half), sg.make_params(self.p_full),
-                             list(self.rgba_lo), list(self.depth_lo), list(self.out))
-        ph, pf, lo, dlo, out = self._structs
-        self._launch(self.launch_half)
-        sg.sg_render_views(self.vol, self._half_views(views), ph, lo, dlo)
+        key = (id(self.launch_half), id(self.launch_full))
+        if self._structs is None or self._structs[0] != key:
+            # built once: per frame only the views are packed, once for
+            # both renders (the half-resolution ones are a patched copy)
+            lh = None if self.launch_half is None else sg.launch_config_struct(self.launch_half)
+            lf = None if self.launch_full is None else sg.launch_config_struct(self.launch_full)
+            self._structs = (key, sg.make_params(self.p_half), sg.make_params(self.p_full),
+                             sg.pointer_array(list(self.rgba_lo)),
+                             sg.pointer_array(list(self.depth_lo)),
+                             sg.pointer_array(list(self.out)), lh, lf,
+                             [self.content[i].data_ptr() for i in range(self.size[2])])
+        _, ph, pf, lo, dlo, out, lh, lf, masks = self._structs
+        full = sg.views_array(views)
+        half = (sg.sg_view * len(full))()
+        C.memmove(half, full, C.sizeof(full))
+        for i in range(len(full)):
+            half[i].width = full[i].width // 2
+            half[i].height = full[i].height // 2
+            half[i].tile_any = masks[i]
+        if lh is not None:
+            sg.sg_set_launch_config(self.vol, lh)
+        sg.sg_render_views(self.vol, half, ph, lo, dlo)
         self.model.forward_flag(self.rgba_lo, self.depth_lo, self.depth_scale, self.out,
                                 self.threshold_db, flag, content=self.content)
-        self._launch(self.launch_full)
-        sg.sg_render_views_if(self.vol, views, pf, out, flag)
+        if lf is not None:
+            sg.sg_set_launch_config(self.vol, lf)
+        sg.sg_render_views_if(self.vol, full, pf, out, flag)
         return self.out
 
 
