@@ -72,8 +72,11 @@ def main():
                     help="explicit launch configuration kernel,tile,block,stage_bytes,persistent "
                          "(no autotuning); profiles use the one the benchmark chose")
     ap.add_argument("--workload", default="tubes",
-                    choices=("tubes", "batched64", "upsampler", "stream", "hmd", "octants"),
+                    choices=("tubes", "batched64", "upsampler", "stream", "hmd", "octants",
+                             "blobs256", "cells"),
                     help="tubes: the bricked stereo frame (default, the headline); "
+                         "blobs256: the plain 256x256 frame of the 128^3 blob volume; "
+                         "cells: one resident timepoint of the 3-channel cell series; "
                          "batched64: 64 uneven views of the 128^3 blob volume in one call; "
                          "upsampler: learned-upsampler path vs plain path on the blob scene; "
                          "stream: the 3-channel cell time series played through the "
@@ -90,6 +93,9 @@ def main():
     ap.add_argument("--scene", default="blobs", choices=("blobs", "tubes"),
                     help="upsampler: the 128^3 blob scene (default) or the 2048^3 tube "
                          "volume with the screen-space LOD")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="tubes: leave out the upsampler, blobs256 and cells figures that the "
+                         "default run adds to its line")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
@@ -116,6 +122,14 @@ def main():
         return
     if args.workload == "octants":
         bench_octants(args)
+        return
+    if args.workload == "blobs256":
+        print(json.dumps(run_blobs256(args, args.cpu_seconds > 0)), flush=True)
+        return
+    if args.workload == "cells":
+        r = run_cells(args, args.cpu_seconds > 0 and not args.render_only)
+        if r is not None:
+            print(json.dumps(r), flush=True)
         return
 
     import gen
@@ -250,9 +264,216 @@ def main():
                "pool_samples": stats["pool_samples"], "slab_retries": stats["slab_retries"]}}
 
     if want_cpu:
-        out["cpu_baseline"] = cpu_baseline(host, tf, views, samples, npix, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(host, tf, views, npix, args.cpu_seconds)
     sg.sg_volume_destroy(h)
+    del host, tv, outs
+    if not args.no_extras:
+        out.update(extras(args))
     print(json.dumps(out), flush=True)
+
+
+def extras(args):
+    """The default run's further figures, each on its own volume: the
+    learned-upsampler path against the plain path (blob scene), the plain
+    256x256 blob frame, and one resident timepoint of the cell series. A
+    figure that fails is reported as its error; the headline stands."""
+    import gc
+
+    import torch
+    res = {}
+    for key, fn in (("upsampler", lambda: upsampler_summary(run_upsampler(args))),
+                    ("blobs256", lambda: run_blobs256(args, args.cpu_seconds > 0)),
+                    ("cells_timepoint", lambda: run_cells(args, args.cpu_seconds > 0))):
+        t0 = time.time()
+        try:
+            res[key] = fn()
+        except Exception as e:  # noqa: BLE001 -- reported in the line
+            res[key] = {"error": "%s: %s" % (type(e).__name__, e)}
+        gc.collect()
+        torch.cuda.empty_cache()
+        log("%s done in %.1fs" % (key, time.time() - t0))
+    return res
+
+
+def upsampler_summary(r):
+    """The upsampler path's keys for the headline line."""
+    return {"workload": r["config"]["workload"], "plain_ms": r["plain_ms"],
+            "up_ms": r["upsampler_path_ms"], "speedup": r["speedup_vs_plain"],
+            "psnr_mean": r["psnr_upsampled_mean"], "psnr_min": r["psnr_upsampled_min"],
+            "bilinear_psnr": r["psnr_bilinear_mean"], "fallback_rate": r["fallback_rate"],
+            "frames": r["config"]["eval_frames"], "timed_frames": r["steps"],
+            "timed_fallbacks": r["timed_fallbacks"], "delivered_min_psnr": r["delivered_min_psnr"],
+            "fallback_threshold_db": r["fallback_threshold_db"], "network_ms": r["network_ms"],
+            "network_flag_ms": r["network_flag_ms"],
+            "network_mask_built_ms": r["network_mask_built_ms"],
+            "train_pairs": r["config"]["train_pairs"],
+            "train_seconds": r["train_seconds"], "roofline": r["roofline"]}
+
+
+def timed_events(fn, steps, warmup):
+    """Mean milliseconds of fn over steps calls after warmup calls, from HIP
+    events on torch's current stream (the stream the renders run on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        fn()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / steps
+
+
+def rooflines(samples, flop, bytes_alg, kernel_s):
+    """(dominant, other) of the FP32 ALU and HBM rooflines of one launch."""
+    alu = {"bound": "alu", "achieved": samples * flop / kernel_s / 1e12,
+           "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "traffic": None}
+    hbm = {"bound": "hbm", "achieved": bytes_alg / kernel_s / 1e9, "peak": HBM_PEAK / 1e9,
+           "unit": "GB/s", "traffic": None}
+    for r in (alu, hbm):
+        r["frac"] = r["achieved"] / r["peak"]
+    return (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+
+
+def run_blobs256(args, want_cpu):
+    """The plain unbricked frame: the 128^3 uint8 blob volume as one brick
+    and one level, one 256x256 view (60 degree field of view, eye 2.5
+    volume diagonals from the centre), identity ramp over [0, 255], step
+    0.5 voxel, early termination at 0.99. A frame is tens of microseconds
+    of ray casting, so the figure is launch-bound; it is timed eager and as
+    a replayed render graph, and the oracle renders the whole frame."""
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg, upload_volume
+    vol = gen.blobs128()
+    h = sg.sg_volume_create((128, 128, 128), dtype=sg.SG_U8, brick=128, levels=1)
+    upload_volume(h, torch.from_numpy(vol).cuda(), 128)
+    tf = gen.tf_identity()
+    sg.sg_set_transfer_function(h, 0, tf, 0, 255)
+    sg.sg_volume_commit(h)
+    views = [gen.blobs128_view()]
+    params = {"step": 0.5, "ert": 0.99, "lod": 0, "bias": 0, "skip_empty": 1}
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    npix = sum(v["width"] * v["height"] for v in views)
+    launch, _ = sg.sg_autotune(h, views, params, outs, repeats=3)
+    stats = sg.sg_render_views_stats(h, views, params, outs)
+    samples, mb = stats["total_samples"], stats["microblocks"]
+    R = 500
+    eager_ms = timed_events(lambda: sg.sg_render_views(h, views, params, outs), R, 20)
+    g = sg.RenderGraph(h, views, params, outs)
+    graph_ms = timed_events(g.launch, R, 20)
+    g.destroy()
+    sg.sg_set_kernel_timing(h, True)
+    for _ in range(R):
+        sg.sg_render_views(h, views, params, outs)
+    n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+    sg.sg_set_kernel_timing(h, False)
+    ray_s = ray_ms / n_k * 1e-3
+    best_ms = min(eager_ms, graph_ms)
+    roof, other = rooflines(samples, FLOP_PER_SAMPLE, mb * 64 + npix * 16, ray_s)
+    out = {"metric": "frames/s of the plain 256x256 blob frame", "value": 1e3 / best_ms,
+           "unit": "frames/s", "n_gpus": 1, "steps": R, "warmup": 20, "ms_per_step": best_ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "blobs128_u8_mono_256x256", "brick": 128, "levels": 1,
+                      "step_voxels": 0.5, "ert": 0.99},
+           "samples_per_frame": samples, "samples_per_s": samples / (best_ms * 1e-3),
+           "eager_ms": eager_ms, "graph_replay_ms": graph_ms,
+           "raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
+           "microblocks_per_frame": mb, "launch": launch, "roofline": roof,
+           "roofline_other": other}
+    sg.sg_volume_destroy(h)
+    if want_cpu:
+        import oracle
+        sc = oracle.Scene([vol], 128, 1, [np.asarray(tf, np.float64)], [(0, 255)])
+        out["cpu_baseline"] = oracle_whole_frame(sc, views, params, "frames/s")
+    return out
+
+
+def run_cells(args, want_cpu):
+    """One timepoint of the 3-channel cell series resident in HBM: 3 x
+    1024x1024x512 uint16 (timepoint 0), bricked 64^3 with a one-voxel
+    apron, 5 levels, each channel with its own tinted table, additive
+    channel blending, stereo 1440x1600 per eye, step 0.5 voxel of the
+    selected level, screen-space LOD at 1 pixel, early termination 0.99,
+    empty skipping. One step = one sg_render_views call for both eyes."""
+    import torch
+
+    import gen
+    from gen.large import CellVolume, upload_generated
+    from paper_1804_08197_amd import sg
+    dims, B, L, C = gen.CELLS_DIMS, gen.CELLS_BRICK, gen.CELLS_LEVELS, 3
+    h = sg.sg_volume_create(dims, channels=C, timepoints=1, dtype=sg.SG_U16, brick=B, levels=L)
+    hosts = []
+    t0 = time.time()
+    for c in range(C):
+        cv = CellVolume(c, 0).to_device()
+        host = np.empty(dims[::-1], dtype=np.uint16) if want_cpu else None
+        upload_generated(h, cv, B, channel=c, timepoint=0, host_out=host, slab_bricks=4)
+        hosts.append(host)
+        del cv
+    tfs = [gen.tf_tint(tint) for tint in gen.CELL_TINTS]
+    for c in range(C):
+        sg.sg_set_transfer_function(h, c, tfs[c], *gen.CELL_DOMAIN)
+    sg.sg_volume_commit(h)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    views = gen.cells_stereo()
+    params = dict(PARAMS)
+    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+    npix = sum(v["width"] * v["height"] for v in views)
+    if args.launch:
+        launch = dict(zip(sg.LAUNCH_FIELDS, (int(x) for x in args.launch.split(","))))
+        sg.sg_set_launch_config(h, launch)
+    else:
+        launch, _ = sg.sg_autotune(h, views, params, outs, repeats=2)
+    if args.render_only:
+        for _ in range(args.warmup):
+            sg.sg_render_views(h, views, params, outs)
+        torch.cuda.synchronize()
+        sg.sg_set_kernel_timing(h, True)
+        for _ in range(args.steps):
+            sg.sg_render_views(h, views, params, outs)
+        n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+        print(json.dumps({"renders": n_k, "raycast_kernel_ms": ray_ms / n_k,
+                          "cutmap_kernel_ms": cut_ms / n_k}), flush=True)
+        sg.sg_volume_destroy(h)
+        return None
+    stats = sg.sg_render_views_stats(h, views, params, outs)
+    samples, mb = stats["total_samples"], stats["microblocks"]
+    steps = max(args.steps, 10)
+    torch.cuda.synchronize()
+    sg.sg_set_kernel_timing(h, True)
+    ms = timed_events(lambda: sg.sg_render_views(h, views, params, outs), steps, args.warmup)
+    n_k, cut_ms, ray_ms = sg.sg_get_kernel_timing(h)
+    sg.sg_set_kernel_timing(h, False)
+    # the kernel timer also saw the warm-up calls: they render the same frame
+    ray_s = ray_ms / n_k * 1e-3
+    roof, other = rooflines(samples, flop_per_sample(C), mb * 64 * 2 + npix * 16, ray_s)
+    out = {"metric": "stereo frames/s of one resident timepoint of the 3-channel series",
+           "value": 1e3 / ms, "unit": "stereo frames/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "cells_3x1024x1024x512_u16_resident_timepoint_stereo_1440x1600",
+                      "channels": C, "brick": B, "levels": L, "step_voxels": 0.5, "ert": 0.99,
+                      "lod_tau_px": 1.0, "skip_empty": True},
+           "samples_per_frame": samples, "samples_per_s": samples * 1e3 / ms,
+           "raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
+           "microblocks_per_frame": mb, "launch": launch, "roofline": roof,
+           "roofline_other": other, "setup_generate_upload_s": setup_s,
+           "paper_context": "3D movies of up to 2e7 voxels per volume frame play at 25 volume "
+                            "frames/s (Sec 5.4; hardware not stated)"}
+    sg.sg_volume_destroy(h)
+    if want_cpu:
+        import oracle
+        sc = oracle.Scene(hosts, B, L, [np.asarray(t, np.float32).astype(np.float64) for t in tfs],
+                          [gen.CELL_DOMAIN] * C)
+        out["cpu_baseline"] = oracle_pixel_subset(sc, views, params, npix, args.cpu_seconds,
+                                                  "stereo frames/s")
+    return out
 
 
 def batched_views():
@@ -368,6 +589,10 @@ def upsampler_scene(args):
 
 
 def bench_upsampler(args):
+    print(json.dumps(run_upsampler(args)), flush=True)
+
+
+def run_upsampler(args):
     """A scene in stereo at 1440x1600 per eye: the plain full-resolution path
     against the learned-upsampler path (half-resolution render one level
     coarser with depth, network, fallback to the plain render when the
@@ -415,10 +640,19 @@ def bench_upsampler(args):
                                                   stereo_ipd=sc["ipd"])[0], p_full, list(plain),
                                repeats=2)
     log("launch configuration: %s" % launch)
-    # the upsampler path's own launch: the same with workgroup tiles of at
-    # least 16 pixels, so its gated full-resolution render, when skipped,
-    # dispatches few workgroups (images are the same under every launch)
-    launch_up = dict(launch, tile=max(16, launch["tile"]), block=max(launch["block"], 32))
+    # the upsampler path's own launches (set-up, untimed; images are the
+    # same under every launch): the half-resolution render tuned on its own
+    # frame; the gated full-resolution render with 32-pixel workgroup tiles
+    # on a direct grid, whose few workgroups end at once when the frame
+    # needs no fallback (a persistent grid would first reset its tile
+    # queues, one more launch)
+    hv = gen.orbit_views(center, radius, 1, 4005, W, H, tan_t, stereo_ipd=sc["ipd"])[0]
+    launch_half, _ = sg.sg_autotune(h, path._half_views(hv), path.p_half, list(path.rgba_lo),
+                                    repeats=2)
+    launch_full = dict(launch, tile=32, block=max(32, launch["block"]), persistent=0)
+    log("launch configuration: half %s, gated full %s" % (launch_half, launch_full))
+    path.launch_half, path.launch_full = launch_half, launch_full
+    launch_up = {"half": launch_half, "full_gated": launch_full}
 
     def frame_psnr(views):
         sg.sg_render_views(h, views, p_full, list(plain))
@@ -467,19 +701,18 @@ def bench_upsampler(args):
             sg.sg_render_views(h, v, p_full, list(plain))
 
     def run_up_host():
-        sg.sg_set_launch_config(h, launch_up)
         fell = 0
         for v in sub:
             fell += path.render(v)[1]
         return fell
 
     flags = torch.zeros(len(sub), dtype=torch.int32, device="cuda")
+    flag_of = [flags[i:i + 1] for i in range(len(sub))]  # one device flag per frame
 
     def run_up():
         # the product path: the fallback decision stays on the device
-        sg.sg_set_launch_config(h, launch_up)
-        for i, v in enumerate(sub):
-            path.render_device(v, flags[i:i + 1])
+        for v, f in zip(sub, flag_of):
+            path.render_device(v, f)
 
     for fn in (run_plain, run_up_host, run_up):
         fn()
@@ -499,23 +732,17 @@ def bench_upsampler(args):
     torch.cuda.synchronize()
     up_ms = (time.perf_counter() - t) * 1e3 / len(sub)
     fell = int(flags.sum().item())
-    # network alone (no render, no host read-back)
-    ev_net = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev_net[0].record()
-    for _ in range(50):
-        model.forward(path.rgba_lo, path.depth_lo, diag, path.out)
-    ev_net[1].record()
-    torch.cuda.synchronize()
-    net_ms = ev_net[0].elapsed_time(ev_net[1]) / 50
+    # network alone on the last timed frame's input (no render, no host
+    # read-back), driven by that render's content mask as the path runs it,
+    # and with the mask built by the call itself
+    net_ms = timed_events(lambda: model.forward(path.rgba_lo, path.depth_lo, diag, path.out,
+                                                content=path.content), 50, 5)
+    net_nomask_ms = timed_events(lambda: model.forward(path.rgba_lo, path.depth_lo, diag,
+                                                       path.out), 50, 5)
     # the network as the device-decided path runs it, with the fallback decision
     flag1 = torch.zeros(1, dtype=torch.int32, device="cuda")
-    ev_f = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev_f[0].record()
-    for _ in range(50):
-        model.forward_flag(path.rgba_lo, path.depth_lo, diag, path.out, thr, flag1)
-    ev_f[1].record()
-    torch.cuda.synchronize()
-    flag_ms = ev_f[0].elapsed_time(ev_f[1]) / 50
+    flag_ms = timed_events(lambda: model.forward_flag(path.rgba_lo, path.depth_lo, diag, path.out,
+                                                      thr, flag1, content=path.content), 50, 5)
     # the network runs only on 16x16 input tiles with a nonzero input pixel
     # within its 4-pixel reach (empty tiles write background): the
     # algorithmic work counts the pixels of those tiles, at 2 x 9 x 32 x
@@ -524,9 +751,12 @@ def bench_upsampler(args):
     run = torch.nn.functional.max_pool2d(nz.float().unsqueeze(1), 24, 16, 4, ceil_mode=True)
     tiles_run, tiles_all = int(run.sum().item()), run.numel()
     flops = tiles_run * 256 * 2 * 9 * 32 * (8 + 32 + 32 + 32)
-    # HBM: every input pixel's rgba + depth read (20 B), four output pixels'
-    # rgba written (64 B), whether or not its tile runs the network
-    net_bytes = path.rgba_lo.shape[0] * (H // 2) * (W // 2) * (20 + 64)
+    # HBM: the input (rgba + depth, 20 B per pixel) of the tiles that run the
+    # network, four output pixels' rgba (64 B) for every input pixel, and
+    # the content mask (one byte per 8 x 8 block)
+    n_img = path.rgba_lo.shape[0]
+    net_bytes = (tiles_run * 256 * 20 + n_img * (H // 2) * (W // 2) * 64
+                 + path.content.numel())
     mfma = {"bound": "mfma", "achieved": flops / (net_ms * 1e-3) / 1e12, "peak": 2500.0,
             "unit": "TFLOP/s", "traffic": None}
     hbm = {"bound": "hbm", "achieved": net_bytes / (net_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
@@ -548,6 +778,7 @@ def bench_upsampler(args):
            "upsampler_path_host_decision_ms": up_host_ms,
            "timed_fallbacks_host_decision": int(fell_host),
            "network_ms": net_ms, "network_flag_ms": flag_ms,
+           "network_mask_built_ms": net_nomask_ms,
            "network_tiles_run": tiles_run, "network_tiles": tiles_all,
            "network_tflops": flops / (net_ms * 1e-3) / 1e12,
            "roofline": net_roof[0], "roofline_other": net_roof[1],
@@ -562,7 +793,7 @@ def bench_upsampler(args):
            "train_seconds": train_s, "train_loss_first_last": [losses[0], losses[-1]]}
     model.close()
     sg.sg_volume_destroy(h)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_hmd(args):
@@ -935,16 +1166,36 @@ def copy_calibration(nbytes):
           flush=True)
 
 
-def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
-    """The FP64 oracle on a seeded random subset of the frame's pixels."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(host, tf, views, npix, seconds):
+    """The FP64 oracle on a seeded random subset of the tube frame's pixels."""
     import gen
     import oracle
     t0 = time.time()
     sc = oracle.Scene([host], gen.TUBES_BRICK, gen.TUBES_LEVELS,
                       [np.asarray(tf, np.float32).astype(np.float64)], [gen.TUBE_DOMAIN])
-    cuts = [sc.cut(v, PARAMS) for v in views]
+    log("oracle setup %.1fs" % (time.time() - t0))
+    return oracle_pixel_subset(sc, views, PARAMS, npix, seconds, "stereo frames/s")
+
+
+def oracle_pixel_subset(sc, views, params, npix, seconds, unit):
+    """The oracle on uniformly random pixels of every view (seeded), on all
+    of this host's threads for about ``seconds``, then on one thread for
+    4,096 further pixels per view; each rate is extrapolated to the frame
+    by pixel count."""
+    import oracle
+    cuts = [sc.cut(v, params) for v in views]
     emps = [sc.empty(c) for c in cuts]
-    log("oracle setup %.1fs (pyramid, cuts %s)" % (time.time() - t0, [len(c) for c in cuts]))
     rng = np.random.default_rng(2024)
     threads = oracle.max_threads()
     done_pix, done_samp, spent, n = 0, 0, 0.0, 64
@@ -952,38 +1203,47 @@ def cpu_baseline(host, tf, views, gpu_samples, npix, seconds):
         for i, v in enumerate(views):
             pix = np.stack([rng.integers(0, v["width"], n), rng.integers(0, v["height"], n)], 1)
             t = time.perf_counter()
-            r = sc.render(v, PARAMS, pixels=pix, cut=cuts[i], empty=emps[i], threads=threads)
+            r = sc.render(v, params, pixels=pix, cut=cuts[i], empty=emps[i], threads=threads)
             spent += time.perf_counter() - t
             done_pix += n
             done_samp += r["total_samples"]
         n = min(n * 2, 8192)
     frame_s = spent / done_pix * npix
-    # the same oracle on one thread, on 4,096 further random pixels per eye
     one_pix, one_samp, one_s = 0, 0, 0.0
     for i, v in enumerate(views):
         pix = np.stack([rng.integers(0, v["width"], 4096), rng.integers(0, v["height"], 4096)], 1)
         t = time.perf_counter()
-        r = sc.render(v, PARAMS, pixels=pix, cut=cuts[i], empty=emps[i], threads=1)
+        r = sc.render(v, params, pixels=pix, cut=cuts[i], empty=emps[i], threads=1)
         one_s += time.perf_counter() - t
         one_pix += len(pix)
         one_samp += r["total_samples"]
-    cpu_model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    cpu_model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": 1.0 / frame_s, "unit": "stereo frames/s", "cores": threads,
+    return {"value": 1.0 / frame_s, "unit": unit, "cores": threads,
             "kind": "oracle", "samples_per_s": done_samp / spent,
-            "cpu_model": cpu_model, "nproc": os.cpu_count(),
-            "single_thread": {"value": one_pix / (one_s * npix), "unit": "stereo frames/s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": one_pix / (one_s * npix), "unit": unit,
                               "samples_per_s": one_samp / one_s, "pixels": one_pix},
-            "sample": "%d uniformly random pixels of both eyes (%.1f%% of the frame's pixel "
+            "sample": "%d uniformly random pixels of %d view(s) (%.1f%% of the frame's pixel "
                       "count), %.1fs of wall time on %d threads, extrapolated to the frame by "
-                      "pixel count" % (done_pix, 100.0 * done_pix / npix, spent, threads)}
+                      "pixel count" % (done_pix, len(views), 100.0 * done_pix / npix, spent,
+                                       threads)}
+
+
+def oracle_whole_frame(sc, views, params, unit):
+    """The oracle rendering every pixel of the frame: on all of this host's
+    threads, then on one thread."""
+    import oracle
+    threads = oracle.max_threads()
+    res = {}
+    for k in (threads, 1):
+        t = time.perf_counter()
+        samp = sum(sc.render(v, params, threads=k, count=True)["total_samples"] for v in views)
+        res[k] = (time.perf_counter() - t, samp)
+    (s_all, n_all), (s_one, n_one) = res[threads], res[1]
+    return {"value": 1.0 / s_all, "unit": unit, "cores": threads, "kind": "oracle",
+            "samples_per_s": n_all / s_all, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": 1.0 / s_one, "unit": unit, "samples_per_s": n_one / s_one},
+            "sample": "the whole frame (%d view(s)), %.2fs on %d threads and %.2fs on one"
+                      % (len(views), s_all, threads, s_one)}
 
 
 if __name__ == "__main__":
