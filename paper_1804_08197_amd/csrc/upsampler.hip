@@ -796,14 +796,20 @@ __global__ __launch_bounds__(256) void tile_list_kernel(const uint8_t* __restric
   }
 }
 
-// One workgroup per list entry (grid: tiles). The lists partition the
-// array, so entry b < count[0] is a tile with content and every later entry
-// an empty tile. Workgroups are dispatched in grid order, so the tiles that
-// run the network start first and the empty tiles, whose only work is
-// storing background without a look at the input, stream through the
-// remaining slots beside them. A tile of the first list whose exact input
-// region turns out empty (the mask is per 8 x 8 block) is cleared as well:
-// every tile's output is what a test of its own input region gives.
+// Grid: tiles workgroups (enough whatever the split). The lists partition
+// the array: entries below c = count[0] are tiles with content, every later
+// entry an empty tile. Workgroup b < c runs the network on tile list[b];
+// workgroup b >= c stores background (without a look at the input) for the
+// kEmptyPerGroup empty entries c + (b - c) kEmptyPerGroup ..., and the
+// workgroups past the last empty entry end at once. Workgroups are
+// dispatched in grid order, so the tiles that run the network start first
+// and the stores stream through the remaining slots beside them, in a
+// handful of workgroups (each holds this kernel's 78 KB of LDS, two per
+// CU, so every workgroup costs a slot). A tile of the first list whose
+// exact input region turns out empty (the mask is per 8 x 8 block) is
+// cleared as well: every tile's output is what a test of its own input
+// region gives.
+constexpr int kEmptyPerGroup = 8;
 __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 fused_forward_kernel(
     const float4* __restrict__ rgba, const float* __restrict__ depth, int H, int W,
@@ -812,14 +818,22 @@ fused_forward_kernel(
     const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ b3,
     float4* __restrict__ out, float* __restrict__ err, SumArgs sums, TileList tl) {
   const int b = (int)blockIdx.x;
-  const int t = tl.list[b];
+  const int c = tl.count[0];
   const int per = tl.tiles_x * tl.tiles_y;
-  const int n = t / per, r = t - n * per;
-  const int ty0 = (r / tl.tiles_x) * kTile, tx0 = (r % tl.tiles_x) * kTile;
-  if (b >= tl.count[0]) {  // empty tile (its partial sum is already zero)
-    clear_tile(n, H, W, ty0, tx0, out, err);
+  if (b >= c) {  // empty tiles (their partial sums are already zero)
+    const int64_t e0 = c + (int64_t)(b - c) * kEmptyPerGroup;
+#pragma unroll
+    for (int j = 0; j < kEmptyPerGroup; ++j) {
+      if (e0 + j >= tl.tiles) break;  // the same for the whole workgroup
+      const int t = tl.list[e0 + j];
+      const int n = t / per, r = t - n * per;
+      clear_tile(n, H, W, (r / tl.tiles_x) * kTile, (r % tl.tiles_x) * kTile, out, err);
+    }
     return;
   }
+  const int t = tl.list[b];
+  const int n = t / per, r = t - n * per;
+  const int ty0 = (r / tl.tiles_x) * kTile, tx0 = (r % tl.tiles_x) * kTile;
   const FusedLds l = fused_lds(fused_smem);
   bf16x8 wa[ksteps(8)], wb[ksteps(32)], wc[ksteps(32)];
   load_weights<8>(w0, wa);
