@@ -219,3 +219,31 @@ def test_binding_shares_torch_hip_runtime_whatever_the_import_order():
     out = subprocess.run(["python", "-c", code], capture_output=True, text=True, cwd=ROOT,
                          check=True).stdout.split()
     assert out[-1] == "1"
+
+
+def test_view_packing_and_prebuilt_arrays(sg):
+    """make_view packs every field of a view dict (checked field by field
+    against the dict); the render calls' helpers pass prebuilt view,
+    pointer and launch structures through untouched."""
+    import math
+
+    import gen
+    rng = np.random.default_rng(5)
+    v = gen.view(gen.look_at(rng.normal(size=3) * 300, (10.0, 20.0, 30.0)), 70, 46,
+                 math.tan(math.radians(25)))
+    v = dict(v, lens=(0.1, -0.2, 0.05, -0.03), ray_limit=123456, tile_any=654321)
+    o = sg.make_view(v)
+    assert list(o.cam_to_world) == [float(x) for x in np.asarray(v["cam_to_world"]).ravel()]
+    assert (o.tan_left, o.tan_right, o.tan_bottom, o.tan_top) == (
+        v["tan_left"], v["tan_right"], v["tan_bottom"], v["tan_top"])
+    assert (o.width, o.height) == (70, 46)
+    assert list(o.lens) == [0.1, -0.2, 0.05, -0.03]
+    assert (o.ray_limit, o.tile_any) == (123456, 654321)
+    plain = sg.make_view(dict(v, lens=None, ray_limit=None, tile_any=None))
+    assert list(plain.lens) == [0.0] * 4 and not plain.ray_limit and not plain.tile_any
+    arr = sg.views_array([v, v])
+    assert sg._views(arr) is arr and bytes(arr[0]) == bytes(o)
+    ptrs = sg.pointer_array([None])
+    assert sg._ptrs(ptrs) is ptrs and ptrs[0] is None
+    cfg = sg.launch_config_struct({"kernel": 1, "tile": 8})
+    assert sg._launch_dict(cfg)["kernel"] == 1 and sg._launch_dict(cfg)["tile"] == 8
