@@ -180,6 +180,9 @@ typedef struct {
   uint64_t alive_lanes;    /* out: staged kernel: sum over (wave, node) visits
                               of the lanes whose ray is still in flight (in
                               that node or in another)                      */
+  uint64_t wide_slabs;     /* out: staged kernel: slabs whose region rows
+                              were wider than one 64-lane copy pass (bricks
+                              of 128 voxels or more), copied chunk by chunk */
 } sg_render_stats;
 
 /* Create a volume on desc->device (Sec 4.2: the GPU-side store of volume

@@ -473,6 +473,7 @@ sg_status render(sg_volume* vol, int32_t n_views, const sg_view* views,
     stats->pool_samples = cnt[6];
     stats->slab_retries = cnt[7];
     stats->alive_lanes = cnt[8];
+    stats->wide_slabs = cnt[9];
     return SG_OK;
   }
   Launch l;

@@ -1128,8 +1128,11 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         const int area = max(1, quot(vox, max(1, wd[m])));
         if (vox <= cap) {
           fits = vox > 0;
-          // next slab's depth from this slab's cross-section
-          D = min(max(quot(cap, area) - 1, 1), 64);
+          // next slab's depth from this slab's cross-section, with 1/8 of it
+          // in reserve: cross-sections grow along the rays, and a slab that
+          // does not fit costs a second search (7/8: 40% fewer retries for
+          // 0.1% more slabs; 3/4 gave 4% more slabs and no gain)
+          D = min(max(quot(cap * 7, area * 8) - 1, 1), 64);
           break;
         }
         if (D == 1) break;
@@ -1193,6 +1196,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           // rows wider than a pass (bricks of 128 or more): pass p moves
           // chunks p .. p+63 of the region; chunk i is row = i / cpr, plane
           // rz = row / wy, at base + i + row * skip_row + rz * skip_plane
+          if (STATS && lane == 0) atomicAdd((unsigned long long*)a.counters + 9, 1ull);
           const int base = ((o[2] * S + o[1]) * Sx + o[0]) / align;
           const int skip_row = P - cpr, skip_plane = (S - wy) * P;
           for (int p0 = 0; p0 < total; p0 += 64) {

@@ -61,7 +61,8 @@ class sg_render_stats(C.Structure):
                 ("microblocks", C.c_uint64), ("node_visits", C.c_uint64), ("slabs", C.c_uint64),
                 ("staged_bytes", C.c_uint64), ("node_lanes", C.c_uint64),
                 ("loop_iterations", C.c_uint64), ("pool_samples", C.c_uint64),
-                ("slab_retries", C.c_uint64), ("alive_lanes", C.c_uint64)]
+                ("slab_retries", C.c_uint64), ("alive_lanes", C.c_uint64),
+                ("wide_slabs", C.c_uint64)]
 
 
 class sg_cache_info(C.Structure):
@@ -396,7 +397,8 @@ def sg_render_views_stats(vol, views, params, out_rgba, out_depth=None, out_samp
             "node_visits": int(st.node_visits), "slabs": int(st.slabs),
             "staged_bytes": int(st.staged_bytes), "node_lanes": int(st.node_lanes),
             "loop_iterations": int(st.loop_iterations), "pool_samples": int(st.pool_samples),
-            "slab_retries": int(st.slab_retries), "alive_lanes": int(st.alive_lanes)}
+            "slab_retries": int(st.slab_retries), "alive_lanes": int(st.alive_lanes),
+            "wide_slabs": int(st.wide_slabs)}
 
 
 def sg_get_lod_cut(vol, view, params, capacity=1 << 20, stream=None):

@@ -95,3 +95,30 @@ def test_ordinary_view_stages_everything_and_retries_slab_sizes():
         assert st["pool_samples"] == 0 and st["slabs"] > 0 and st["slab_retries"] > 0
     finally:
         sg.sg_volume_destroy(h)
+
+
+def test_rows_wider_than_a_copy_pass_are_staged_chunk_by_chunk():
+    """uint16 bricks of 128 voxels: a region row can hold more than 64
+    4-byte chunks (one copy pass), which the staging copies chunk by chunk.
+    One-wave 8x8 views down z, 80-120 voxels above the volume, wide across
+    x (tan 1 to 1.5) and narrow across y (tan 0.02), over a 130-voxel-wide
+    volume with one level: the rays of one wave cross both x edges of the
+    first brick within its first slab, so that slab's rows hold the whole
+    brick width (65 chunks), a few rows and layers deep. The images match
+    the oracle and the gather kernel's bit for bit."""
+    from paper_1804_08197_amd import sg
+    vol = gen.random_volume((40, 140, 130), 29, dtype=np.uint16)  # z, y, x
+    tf = gen.tf_hot(a_start=30)
+    h = gpu_volume([vol], 128, 1, [tf], [(0, 65535)])
+    try:
+        sg.sg_set_launch_config(h, {"kernel": 0, "tile": 16, "block": 32, "stage_bytes": 8192,
+                                    "persistent": 0})
+        sc = oracle_scene([vol], 128, 1, [tf], [(0, 65535)])
+        c = np.array([65.0, 70.0, 20.0])
+        views = [gen.view(gen.look_at(c + np.array([0.0, 0.0, 20.0 + d]), c, up=(0, 1, 0)), 8, 8,
+                          0.02, tr) for d in (80.0, 100.0, 120.0) for tr in (1.0, 1.5)]
+        st = _check(h, sc, views, {"ert": ERT, "tau": 1.0})
+        print("wide rows:", st, flush=True)
+        assert st["wide_slabs"] > 0 and st["slabs"] > 0
+    finally:
+        sg.sg_volume_destroy(h)
