@@ -94,8 +94,9 @@ def main():
                     help="upsampler: the 128^3 blob scene (default) or the 2048^3 tube "
                          "volume with the screen-space LOD")
     ap.add_argument("--no-extras", action="store_true",
-                    help="tubes: leave out the upsampler, blobs256 and cells figures that the "
-                         "default run adds to its line")
+                    help="tubes: leave out the further figures the default run adds to its "
+                         "line (HMD variants, octant share, upsampler, blobs256, cells, "
+                         "batched64, stream)")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
@@ -265,34 +266,88 @@ def main():
 
     if want_cpu:
         out["cpu_baseline"] = cpu_baseline(host, tf, views, npix, args.cpu_seconds)
-    sg.sg_volume_destroy(h)
     del host, tv, outs
+    if not args.no_extras:
+        # the workloads that reuse the resident tube volume, in the same launch
+        short = argparse.Namespace(**dict(vars(args), steps=min(args.steps, 10),
+                                          warmup=min(args.warmup, 2)))
+        for key, fn in (("hmd_variants", lambda: hmd_summary(run_hmd(h, views, launch, short))),
+                        ("octant_share", lambda: octant_summary(run_octants(h, views, launch,
+                                                                           short)))):
+            out[key] = guarded(key, fn)
+    sg.sg_volume_destroy(h)
     if not args.no_extras:
         out.update(extras(args))
     print(json.dumps(out), flush=True)
 
 
-def extras(args):
-    """The default run's further figures, each on its own volume: the
-    learned-upsampler path against the plain path (blob scene), the plain
-    256x256 blob frame, and one resident timepoint of the cell series. A
-    figure that fails is reported as its error; the headline stands."""
+def guarded(key, fn):
+    """fn(), or its error as the figure: the headline line stands."""
     import gc
 
     import torch
-    res = {}
-    for key, fn in (("upsampler", lambda: upsampler_summary(run_upsampler(args))),
-                    ("blobs256", lambda: run_blobs256(args, args.cpu_seconds > 0)),
-                    ("cells_timepoint", lambda: run_cells(args, args.cpu_seconds > 0))):
-        t0 = time.time()
-        try:
-            res[key] = fn()
-        except Exception as e:  # noqa: BLE001 -- reported in the line
-            res[key] = {"error": "%s: %s" % (type(e).__name__, e)}
-        gc.collect()
-        torch.cuda.empty_cache()
-        log("%s done in %.1fs" % (key, time.time() - t0))
-    return res
+    t0 = time.time()
+    try:
+        r = fn()
+    except Exception as e:  # noqa: BLE001 -- reported in the line
+        r = {"error": "%s: %s" % (type(e).__name__, e)}
+    gc.collect()
+    torch.cuda.empty_cache()
+    log("%s done in %.1fs" % (key, time.time() - t0))
+    return r
+
+
+def hmd_summary(r):
+    """The HMD variants' kernel times and samples for the headline line."""
+    return {"workload": r["config"]["workload"], "launch": r["launch"],
+            "variants": {k: {"raycast_kernel_ms": v["raycast_kernel_ms"],
+                             "samples": v["samples"]} for k, v in r["variants"].items()}}
+
+
+def octant_summary(r):
+    """One GPU's octant share for the headline line."""
+    return {"workload": r["config"]["workload"],
+            "stereo_frames_per_s_slowest_octant": r["value"], "slowest": r["config"]["slowest"],
+            "octant_kernel_ms": {k: v["raycast_kernel_ms"] for k, v in r["octants"].items()},
+            "composite_ms_all_parts": r["composite_ms_all_parts"],
+            "composite_max_diff_to_whole": r["composite_max_diff_to_whole"]}
+
+
+def batched_summary(r):
+    """The 64-view batch for the headline line."""
+    keys = ("value", "unit", "ms_per_step", "views_per_s", "samples_per_batch",
+            "default_launch_ms", "autotuned_launch", "autotuned_ms", "graph_replay_ms",
+            "raycast_kernel_ms", "roofline")
+    return dict({"workload": r["config"]["workload"]}, **{k: r[k] for k in keys})
+
+
+def stream_summary(r):
+    """The time series through the brick cache for the headline line."""
+    keys = ("value", "unit", "ms_per_step", "frames_per_timepoint",
+            "stereo_frames_per_s_during_playback", "bricks_uploaded_per_timepoint",
+            "upload_GB_per_s", "core_voxels_streamed_per_s", "host_to_device_copy_GB_per_s",
+            "resident_frame_ms", "resident_samples_per_frame", "evictions")
+    return dict({"workload": r["config"]["workload"],
+                 "timepoints_in_host_tier": r["config"]["timepoints_in_host_tier"]},
+                **{k: r[k] for k in keys})
+
+
+def extras(args):
+    """The default run's further figures, each on its own volume: the
+    learned-upsampler path against the plain path (blob scene), the plain
+    256x256 blob frame, one resident timepoint of the cell series, the
+    64-view batch, and the cell series played through the brick cache (three
+    timepoints in the host tier, ten played). A figure that fails is
+    reported as its error; the headline stands."""
+    short = argparse.Namespace(**dict(vars(args), steps=min(args.steps, 10),
+                                      warmup=min(args.warmup, 2),
+                                      stream_timepoints=min(args.stream_timepoints, 3)))
+    return {key: guarded(key, fn) for key, fn in (
+        ("upsampler", lambda: upsampler_summary(run_upsampler(args))),
+        ("blobs256", lambda: run_blobs256(args, args.cpu_seconds > 0)),
+        ("cells_timepoint", lambda: run_cells(args, args.cpu_seconds > 0)),
+        ("batched64", lambda: batched_summary(run_batched(short))),
+        ("stream", lambda: stream_summary(run_stream(short))))}
 
 
 def upsampler_summary(r):
@@ -487,6 +542,10 @@ def batched_views():
 
 
 def bench_batched(args):
+    print(json.dumps(run_batched(args)), flush=True)
+
+
+def run_batched(args):
     """64 uneven views in one call: default launch, autotuned launch, and the
     autotuned launch replayed as a render graph."""
     import torch
@@ -546,7 +605,7 @@ def bench_batched(args):
            "default_launch_ms": default_ms, "autotuned_launch": cfg, "autotuned_ms": eager_ms,
            "graph_replay_ms": graph_ms, "raycast_kernel_ms": ray_ms / n_k, "roofline": alu}
     sg.sg_volume_destroy(h)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def upsampler_scene(args):
@@ -805,6 +864,17 @@ def bench_hmd(args):
     centre, a region of interest (the central half of every axis), a
     depth-buffer ray limit (a synthetic opaque plane 0.9 m from the head) and
     first-hit depth output. One step = one stereo frame of every variant."""
+    from paper_1804_08197_amd import sg
+    h = tube_volume()
+    views = workload_views()
+    out = run_hmd(h, views, None, args)
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def tube_volume():
+    """The 2048^3 tube volume, resident and committed (set-up of the
+    workloads that reuse the headline volume)."""
     import torch
 
     import gen
@@ -817,10 +887,24 @@ def bench_hmd(args):
     sg.sg_build_lod(h, 0, 0)
     sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
     sg.sg_volume_commit(h)
-    views = workload_views()
+    del tv
+    torch.cuda.synchronize()
+    return h
+
+
+def run_hmd(h, views, launch, args):
+    """The HMD variants on the tube volume h (launch: the plain frame's
+    configuration, or None to tune it here)."""
+    import torch
+
+    import gen
+    from paper_1804_08197_amd import sg
     outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
     depth = [torch.empty(v["height"], v["width"], device="cuda") for v in views]
-    launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+    if launch is None:
+        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+    else:
+        sg.sg_set_launch_config(h, launch)
     # the synthetic depth buffer: distance along each pixel's ray to a plane
     # 0.9 m (1843.2 voxels) in front of the eye, perpendicular to the view axis
     limits = []
@@ -873,8 +957,7 @@ def bench_hmd(args):
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_hmd_variants",
                       "variants": list(res)},
            "variants": res, "launch": launch, "roofline": alu}
-    sg.sg_volume_destroy(h)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_octants(args):
@@ -886,22 +969,28 @@ def bench_octants(args):
     the launch the autotuner picks for the whole frame. With eight GPUs the
     frame takes as long as the slowest octant plus the composite, so the
     headline figure is 1 / (slowest octant). One step = every octant once."""
+    from paper_1804_08197_amd import sg
+    h = tube_volume()
+    views = workload_views()
+    out = run_octants(h, views, None, args)
+    sg.sg_volume_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+def run_octants(h, views, launch, args):
+    """One GPU's octant share on the tube volume h (launch: the plain
+    frame's configuration, or None to tune it here)."""
     import torch
 
     import gen
-    from gen.large import TubeVolume, upload_generated
     from paper_1804_08197_amd import sg
-    dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
-    tv = TubeVolume().to_device()
-    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
-    upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
-    sg.sg_build_lod(h, 0, 0)
-    sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
-    sg.sg_volume_commit(h)
-    views = workload_views()
-    outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
-    launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
-    del outs
+    dims = gen.TUBES_DIMS
+    if launch is None:
+        outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
+        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+        del outs
+    else:
+        sg.sg_set_launch_config(h, launch)
     half = [d // 2 for d in dims]
     res, boxes, parts = {}, [], []
     for o in range(9):
@@ -963,8 +1052,7 @@ def bench_octants(args):
            "octants": res, "samples_octants_sum": sum(v["samples"] for v in octs.values()),
            "composite_ms_all_parts": comp_ms, "composite_max_diff_to_whole": comp_err,
            "launch": launch, "roofline": alu}
-    sg.sg_volume_destroy(h)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def flop_per_sample(channels):
@@ -978,6 +1066,10 @@ def flop_per_sample(channels):
 
 
 def bench_stream(args):
+    print(json.dumps(run_stream(args)), flush=True)
+
+
+def run_stream(args):
     """The 3-channel 1024x1024x512 uint16 cell time series played through the
     out-of-core brick cache (stereo 1440x1600 per eye). The host tier holds
     every brick (core + apron, all levels) of --stream-timepoints timepoints
@@ -1125,7 +1217,7 @@ def bench_stream(args):
            "paper_context": "3D movies of up to 2e7 voxels per volume frame play at 25 volume "
                             "frames/s (Sec 5.4; hardware not stated)"}
     sg.sg_volume_destroy(h)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def measured_traffic():
