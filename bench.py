@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "samples/s and stereo frames/s, plain vs learned-upsampler path at PSNR≥40 dB"
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector (packed FMA)
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # VALU lane operations/s (non-packed)
 FLOP_PER_SAMPLE = 31         # algorithmic FLOP of one single-channel sample (see flop_per_sample)
 
 
@@ -235,6 +236,16 @@ def main():
            "unit": "TFLOP/s", "traffic": traffic}
     alu["frac"] = alu["achieved"] / alu["peak"]
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+    # the VALU lane-operation rate: samples x the measured lane operations
+    # per sample (committed counter passes of this kernel) against 256 CUs x
+    # 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane operations/s
+    rec = profile_record()
+    valu = None
+    if rec and "valu_lane_ops_per_sample" in rec:
+        lane_ops = samples * rec["valu_lane_ops_per_sample"] / ray_avg_s
+        valu = {"bound": "valu", "achieved": lane_ops / 1e12, "peak": VALU_LANE_PEAK / 1e12,
+                "unit": "T lane-ops/s", "frac": lane_ops / VALU_LANE_PEAK,
+                "lane_ops_per_sample": rec["valu_lane_ops_per_sample"]}
 
     out = {"metric": METRIC, "value": fps, "unit": "stereo frames/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -251,6 +262,7 @@ def main():
            "step_ms_p90": float(np.percentile(step_ms, 90)),
            "microblocks_per_frame": mb, "brick_bytes_per_frame": brick_bytes,
            "cut_nonempty_nodes": len(cut), "roofline": roof, "roofline_other": other,
+           "roofline_valu": valu,
            "launch": launch, "setup_ms": setup,
            # instrumented pass of the same frame (staged kernel only)
            "kernel_stats": {
@@ -1220,11 +1232,10 @@ def run_stream(args):
     return out
 
 
-def measured_traffic():
-    """HBM bytes per ray-casting dispatch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes (calibrated against a copy of known
-    size), or None once the kernel source has changed since they were
-    taken."""
+def profile_record():
+    """The committed rocprofv3 record of the ray-casting kernel (byte counters
+    calibrated against a copy of known size, VALU counters), or None once
+    the kernel source has changed since it was taken."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "raycast_tubes2048_stereo.traffic.json")
     try:
@@ -1234,7 +1245,14 @@ def measured_traffic():
         return None
     if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
         return None
-    return rec["traffic_bytes_per_dispatch"]
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per ray-casting dispatch from the committed FETCH_SIZE /
+    WRITE_SIZE passes, or None (see profile_record)."""
+    rec = profile_record()
+    return rec["traffic_bytes_per_dispatch"] if rec else None
 
 
 def copy_calibration(nbytes):
