@@ -864,11 +864,12 @@ __device__ __forceinline__ void wave_sync() {
 // Wave reductions without LDS traffic: within each 16-lane row, DPP lane
 // swaps (quad_perm xor 1, quad_perm xor 2, half-row mirror, row mirror)
 // leave the row's result in every lane; the four row results are then read
-// as scalars. Every lane of the wave must be active at the call (a swap
-// from an inactive lane returns the lane's own value).
+// as scalars. Every lane of the wave must be active at the call: each
+// swap's source lane is then active, so the move has no fallback value to
+// keep (and no register copy to make for one).
 template <int C>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, C, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, C, 0xF, 0xF, false);
 }
 template <typename Op>
 __device__ __forceinline__ int wave_reduce_i(int v, Op op) {
@@ -909,13 +910,37 @@ __device__ __forceinline__ float lane_f(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
-// Component-wise minimum of two 16-bit lanes packed in a word, over the wave.
+// Component-wise minimum of the two 16-bit halves of a word, over the wave,
+// for two words at once (the steps interleaved, so no move waits on the
+// previous step's result); the four row results of each are combined in
+// scalar registers.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t wave_min_u16x2(uint32_t v) {
-  return (uint32_t)wave_reduce_i((int)v, [](int x, int y) {
-    return (int)__builtin_bit_cast(uint32_t, __builtin_elementwise_min(
-        __builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, y)));
-  });
+__device__ __forceinline__ uint32_t min_u16x2(uint32_t x, uint32_t y) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, x),
+                                                                 __builtin_bit_cast(u16x2, y)));
+}
+__device__ __forceinline__ uint32_t rows_min_u16x2(uint32_t v) {
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+  uint32_t l0 = min(a & 0xFFFFu, b & 0xFFFFu), l1 = min(c & 0xFFFFu, d & 0xFFFFu);
+  uint32_t h0 = min(a >> 16, b >> 16), h1 = min(c >> 16, d >> 16);
+  // (kept in scalar registers: a three-way vector minimum would need moves)
+  asm volatile("" : "+s"(l0), "+s"(l1), "+s"(h0), "+s"(h1));
+  return min(l0, l1) | (min(h0, h1) << 16);
+}
+__device__ __forceinline__ void wave_min_u16x2_pair(uint32_t& v, uint32_t& w) {
+  v = min_u16x2(v, (uint32_t)dpp_i<0xB1>((int)v));
+  w = min_u16x2(w, (uint32_t)dpp_i<0xB1>((int)w));
+  v = min_u16x2(v, (uint32_t)dpp_i<0x4E>((int)v));
+  w = min_u16x2(w, (uint32_t)dpp_i<0x4E>((int)w));
+  v = min_u16x2(v, (uint32_t)dpp_i<0x141>((int)v));
+  w = min_u16x2(w, (uint32_t)dpp_i<0x141>((int)w));
+  v = min_u16x2(v, (uint32_t)dpp_i<0x140>((int)v));
+  w = min_u16x2(w, (uint32_t)dpp_i<0x140>((int)w));
+  v = rows_min_u16x2(v);
+  w = rows_min_u16x2(w);
 }
 
 // floor(x / d) for 0 <= x < 2^21, 1 <= d, from a reciprocal: within one of
@@ -1099,10 +1124,9 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
             phi = (uint32_t)(0xFFFF - pick(hi3, ua)) | ((uint32_t)(0xFFFF - pick(hi3, ub)) << 16);
           }
         }
-        const uint32_t rlo = (uint32_t)uniform((int)wave_min_u16x2(plo));
-        const uint32_t rhi = (uint32_t)uniform((int)wave_min_u16x2(phi));
-        const int la = (int)(rlo & 0xFFFF), lb = (int)(rlo >> 16);
-        const int ha = 0xFFFF - (int)(rhi & 0xFFFF), hb = 0xFFFF - (int)(rhi >> 16);
+        wave_min_u16x2_pair(plo, phi);
+        const int la = (int)(plo & 0xFFFF), lb = (int)(plo >> 16);
+        const int ha = 0xFFFF - (int)(phi & 0xFFFF), hb = 0xFFFF - (int)(phi >> 16);
         const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -1111,8 +1135,9 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
             wd[i] = jh - jl + 2;
           } else {
             const int l = i == ua ? la : lb, h = i == ua ? ha : hb;
-            o[i] = l <= h ? l : 0;
-            wd[i] = l <= h ? h - l + 2 : 0;
+            const int e = h - l;  // no lane has samples: l = 0xFFFF, h = 0, e < 0
+            o[i] = e >= 0 ? l : 0;
+            wd[i] = e >= 0 ? e + 2 : 0;
           }
         }
         // chunk-aligned rows: x origin rounded down, width rounded up
@@ -1125,20 +1150,20 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         const int vox = wd[0] * wd[1] * wd[2];
         // (the depth only shapes the slabs, never which samples they hold,
         // so its quotients are taken with reciprocals)
-        const int area = max(1, quot(vox, max(1, wd[m])));
+        const int area = uniform(max(1, quot(vox, max(1, wd[m]))));
         if (vox <= cap) {
           fits = vox > 0;
           // next slab's depth from this slab's cross-section, with 1/8 of it
           // in reserve: cross-sections grow along the rays, and a slab that
           // does not fit costs a second search (7/8: 40% fewer retries for
           // 0.1% more slabs; 3/4 gave 4% more slabs and no gain)
-          D = min(max(quot(cap * 7, area * 8) - 1, 1), 64);
+          D = uniform(min(max(quot(cap * 7, area * 8) - 1, 1), 64));
           break;
         }
         if (D == 1) break;
         // the cross-section of a thinner slab is no larger (its samples are
         // a subset), so this depth fits unless even one layer does not
-        D = max(1, min(D - 1, quot(cap, area) - 1));
+        D = uniform(max(1, min(D - 1, quot(cap, area) - 1)));
       }
       if (STATS && lane == 0 && ntries > 1)
         atomicAdd((unsigned long long*)a.counters + 7, (unsigned long long)(ntries - 1));
@@ -1153,13 +1178,15 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         // LDS (global_load_lds: lane i of an instruction writes chunk i after
         // the instruction's LDS base). The region is wd[1] * wd[2] rows of
         // cpr chunks, row-major in LDS. The quotients below come from
-        // (x + 1/2) * (1/d) in FP32: its relative error is below 2^-23 and
-        // (x + 1/2) / d lies at least 1/(2d) from an integer, so the floor
-        // is exact for every x < 2^22.
+        // (x + 1/2) * rcp(d) in FP32: rcp is within one ulp, so the product's
+        // relative error is below 2^-22, and (x + 1/2) / d lies at least
+        // 1/(2d) from an integer, so the floor is exact for every x < 2^21
+        // (here x < 2^15: the region holds at most the staging capacity).
         const int cpr = wd[0] / align, P = Sx / align;
         const int wy = wd[1], rows = wd[1] * wd[2];
         const int total = cpr * rows;
-        const float inv_cpr = 1.0f / (float)cpr, inv_wy = 1.0f / (float)wy;
+        const float inv_cpr = __builtin_amdgcn_rcpf((float)cpr),
+                    inv_wy = __builtin_amdgcn_rcpf((float)wy);
         constexpr int cb = kRowAlignBytes;
         if (cpr <= 64) {
           // a pass moves R = 64 / cpr whole rows: lane rr * cpr + c takes
