@@ -789,6 +789,90 @@ __device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
 }
 
 // ------------------------------------------------------------ gather kernel
+// The pool stencil of one sample: its eight voxels and fractions, loaded
+// ahead of their use (the same index, clamp and fraction arithmetic as
+// shade_ea's read of the pool).
+struct Stencil {
+  uint32_t v[8];
+  float fx, fy, fz;
+};
+template <typename T>
+__device__ __forceinline__ Stencil stencil_at(const Ray& r, const RenderArgs& a, const T* slot,
+                                              float tau) {
+  const float qx = fmaf(tau, r.dq[0], r.q0[0]);
+  const float qy = fmaf(tau, r.dq[1], r.q0[1]);
+  const float qz = fmaf(tau, r.dq[2], r.q0[2]);
+  const int ix = min(max((int)qx, 0), a.B);
+  const int iy = min(max((int)qy, 0), a.B);
+  const int iz = min(max((int)qz, 0), a.B);
+  Stencil st;
+  st.fx = __builtin_amdgcn_fractf(qx);
+  st.fy = __builtin_amdgcn_fractf(qy);
+  st.fz = __builtin_amdgcn_fractf(qz);
+  const T* p0 = slot + (iz * a.S + iy) * a.Sx + ix;
+  const int sy = a.Sx, sz = a.S * a.Sx;
+  st.v[0] = p0[0];
+  st.v[1] = p0[1];
+  st.v[2] = p0[sy];
+  st.v[3] = p0[sy + 1];
+  st.v[4] = p0[sz];
+  st.v[5] = p0[sz + 1];
+  st.v[6] = p0[sz + sy];
+  st.v[7] = p0[sz + sy + 1];
+  return st;
+}
+// Its trilinear value: trilinear's operations in trilinear's order.
+__device__ __forceinline__ float stencil_value(const Stencil& st) {
+  const float c00 = lerpf((float)st.v[0], (float)st.v[1], st.fx);
+  const float c10 = lerpf((float)st.v[2], (float)st.v[3], st.fx);
+  const float c01 = lerpf((float)st.v[4], (float)st.v[5], st.fx);
+  const float c11 = lerpf((float)st.v[6], (float)st.v[7], st.fx);
+  const float c0 = lerpf(c00, c10, st.fy);
+  const float c1 = lerpf(c01, c11, st.fy);
+  return lerpf(c0, c1, st.fz);
+}
+// A full step of one channel (emission-absorption) from a loaded stencil:
+// sample_step's full step.
+template <bool DEPTH>
+__device__ __forceinline__ bool stencil_step(Ray& r, const RenderArgs& a, const float4* s_tf,
+                                             const TfWin<1>& w, const Stencil& st) {
+  const float4 c = tf_lookup(a, s_tf, 0, stencil_value(st), w.scale[0], w.bias[0]);
+  const float tau = r.tau;
+  r.k += 1;
+  r.tau += r.Df;
+  return composite_ea<DEPTH>(r, a, Shade{c.w, c.x, c.y, c.z}, r.Df * kNegLog2e, tau);
+}
+
+// The gather kernel's samples of the current segment for one channel under
+// emission-absorption: sample_run's samples, with the stencil of each full
+// step's next sample loaded while the current one is shaded, so that a ray
+// waits for memory about once per sample rather than twice (the rays of a
+// sparse frame are few, and a frame then lasts as long as its longest
+// chain of dependent reads). The loads are issued at the top of the loop
+// body and pinned there (no instruction moves across the scheduling
+// barrier); the last full step loads its own stencil again instead of the
+// partial step's.
+template <typename T, bool DEPTH, typename F>
+__device__ __forceinline__ void gather_run(Ray& r, const RenderArgs& a, const float4* s_tf,
+                                           const T* slot, F&& fetch, int (*mb_key)[3]) {
+  const TfWin<1> w = tf_win<1>(a);
+  const int kb = r.n - 1, kf = r.n - 2;
+  if (r.k <= kf) {
+    Stencil cur = stencil_at(r, a, slot, r.tau);
+    bool go = true;
+    while (go) {
+      const Stencil nxt = stencil_at(r, a, slot, r.k < kf ? r.tau + r.Df : r.tau);
+      __builtin_amdgcn_sched_barrier(0);
+      go = stencil_step<DEPTH>(r, a, s_tf, w, cur) && r.k <= kf;
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
+    }
+  }
+  if (!terminated(r, a) && r.k <= kb)
+    sample_step<kModelAbsorption, 1, false, true, DEPTH, kLastStep>(r, a, s_tf, w, fetch, mb_key);
+  if (terminated(r, a)) r.alive = false;
+}
+
 template <typename T, int CH, bool STATS, int MODEL>
 __device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* s_tf,
                                              const TileLane& tl) {
@@ -809,10 +893,16 @@ __device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* 
     auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
       return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
     };
-    if (depth_on)
+    if (CH == 1 && !STATS && MODEL == kModelAbsorption) {
+      if (depth_on)
+        gather_run<T, true>(r, a, s_tf, slot[0], fetch, mb_key);
+      else
+        gather_run<T, false>(r, a, s_tf, slot[0], fetch, mb_key);
+    } else if (depth_on) {
       sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, r.n - 1, mb_key);
-    else
+    } else {
       sample_run<MODEL, CH, STATS, true, false>(r, a, s_tf, fetch, r.n - 1, mb_key);
+    }
     if (!r.alive) break;
     next_segment<MODEL, CH>(r, a, V, false);
   }
