@@ -843,6 +843,14 @@ __device__ __forceinline__ bool stencil_step(Ray& r, const RenderArgs& a, const 
   return composite_ea<DEPTH>(r, a, Shade{c.w, c.x, c.y, c.z}, r.Df * kNegLog2e, tau);
 }
 
+template <bool DEPTH>
+__device__ __forceinline__ bool shade_step(Ray& r, const RenderArgs& a, const float4& c) {
+  const float tau = r.tau;
+  r.k += 1;
+  r.tau += r.Df;
+  return composite_ea<DEPTH>(r, a, Shade{c.w, c.x, c.y, c.z}, r.Df * kNegLog2e, tau);
+}
+
 // The gather kernel's samples of the current segment for one channel under
 // emission-absorption: sample_run's samples, with the stencil of each full
 // step's next sample loaded while the current one is shaded, so that a ray
@@ -858,14 +866,22 @@ __device__ __forceinline__ void gather_run(Ray& r, const RenderArgs& a, const fl
   const TfWin<1> w = tf_win<1>(a);
   const int kb = r.n - 1, kf = r.n - 2;
   if (r.k <= kf) {
-    Stencil cur = stencil_at(r, a, slot, r.tau);
+    Stencil c0 = stencil_at(r, a, slot, r.tau);
+    Stencil c1 = stencil_at(r, a, slot, r.k < kf ? r.tau + r.Df : r.tau);
     bool go = true;
     while (go) {
-      const Stencil nxt = stencil_at(r, a, slot, r.k < kf ? r.tau + r.Df : r.tau);
+      const float t1 = r.k < kf ? r.tau + r.Df : r.tau;
+      const float t2 = r.k + 1 < kf ? t1 + r.Df : t1;
+      const float t3 = r.k + 2 < kf ? t2 + r.Df : t2;
+      const Stencil n0 = stencil_at(r, a, slot, t2), n1 = stencil_at(r, a, slot, t3);
       __builtin_amdgcn_sched_barrier(0);
-      go = stencil_step<DEPTH>(r, a, s_tf, w, cur) && r.k <= kf;
+      const float4 e0 = tf_lookup(a, s_tf, 0, stencil_value(c0), w.scale[0], w.bias[0]);
+      const float4 e1 = tf_lookup(a, s_tf, 0, stencil_value(c1), w.scale[0], w.bias[0]);
+      go = shade_step<DEPTH>(r, a, e0) && r.k <= kf;
+      if (go) go = shade_step<DEPTH>(r, a, e1) && r.k <= kf;
       __builtin_amdgcn_sched_barrier(0);
-      cur = nxt;
+      c0 = n0;
+      c1 = n1;
     }
   }
   if (!terminated(r, a) && r.k <= kb)
