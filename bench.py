@@ -38,6 +38,12 @@ VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # VALU lane operations/s (non-packed)
 FLOP_PER_SAMPLE = 31         # algorithmic FLOP of one single-channel sample (see flop_per_sample)
 
 
+def pool_layout(args):
+    """The sg_layout of the large volumes' slots."""
+    from paper_1804_08197_amd import sg
+    return sg.SG_LAYOUT_MICROBLOCK if args.layout == "microblock" else sg.SG_LAYOUT_LINEAR
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -94,6 +100,10 @@ def main():
     ap.add_argument("--scene", default="blobs", choices=("blobs", "tubes"),
                     help="upsampler: the 128^3 blob scene (default) or the 2048^3 tube "
                          "volume with the screen-space LOD")
+    ap.add_argument("--layout", default="microblock", choices=("microblock", "linear"),
+                    help="pool slot layout of the 2048^3 tube and 3-channel cell volumes "
+                         "(the 128^3 blob volumes keep linear slots, which the gather "
+                         "kernel reads with fewer instructions)")
     ap.add_argument("--no-extras", action="store_true",
                     help="tubes: leave out the further figures the default run adds to its "
                          "line (HMD variants, octant share, upsampler, blobs256, cells, "
@@ -144,7 +154,8 @@ def main():
     t0 = time.time()
     tv = TubeVolume().to_device()
     log("geometry: %d segments in %.1fs" % (tv.n_segments, time.time() - t0))
-    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels,
+                            layout=pool_layout(args))
     host = np.empty(dims[::-1], dtype=np.uint16) if want_cpu else None
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
@@ -253,7 +264,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600",
                       "volume": "2048^3 uint16, 400 branching Gaussian tubes + Poisson(200)",
-                      "brick": B, "levels": levels, "views": 2, "width": 1440, "height": 1600,
+                      "brick": B, "levels": levels, "layout": args.layout, "views": 2,
+                      "width": 1440, "height": 1600,
                       "step_voxels": 0.5, "ert": 0.99, "lod_tau_px": 1.0, "skip_empty": True},
            "samples_per_frame": samples, "samples_per_s": samples * fps,
            "raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
@@ -473,7 +485,8 @@ def run_cells(args, want_cpu):
     from gen.large import CellVolume, upload_generated
     from paper_1804_08197_amd import sg
     dims, B, L, C = gen.CELLS_DIMS, gen.CELLS_BRICK, gen.CELLS_LEVELS, 3
-    h = sg.sg_volume_create(dims, channels=C, timepoints=1, dtype=sg.SG_U16, brick=B, levels=L)
+    h = sg.sg_volume_create(dims, channels=C, timepoints=1, dtype=sg.SG_U16, brick=B, levels=L,
+                            layout=pool_layout(args))
     hosts = []
     t0 = time.time()
     for c in range(C):
@@ -525,8 +538,8 @@ def run_cells(args, want_cpu):
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "cells_3x1024x1024x512_u16_resident_timepoint_stereo_1440x1600",
-                      "channels": C, "brick": B, "levels": L, "step_voxels": 0.5, "ert": 0.99,
-                      "lod_tau_px": 1.0, "skip_empty": True},
+                      "channels": C, "brick": B, "levels": L, "layout": args.layout,
+                      "step_voxels": 0.5, "ert": 0.99, "lod_tau_px": 1.0, "skip_empty": True},
            "samples_per_frame": samples, "samples_per_s": samples * 1e3 / ms,
            "raycast_kernel_ms": ray_ms / n_k, "cutmap_kernel_ms": cut_ms / n_k,
            "microblocks_per_frame": mb, "launch": launch, "roofline": roof,
@@ -647,7 +660,8 @@ def upsampler_scene(args):
     from gen.large import TubeVolume, upload_generated
     dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
     tv = TubeVolume().to_device()
-    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels,
+                            layout=pool_layout(args))
     upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
     sg.sg_build_lod(h, 0, 0)
     sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
@@ -877,14 +891,14 @@ def bench_hmd(args):
     depth-buffer ray limit (a synthetic opaque plane 0.9 m from the head) and
     first-hit depth output. One step = one stereo frame of every variant."""
     from paper_1804_08197_amd import sg
-    h = tube_volume()
+    h = tube_volume(args)
     views = workload_views()
     out = run_hmd(h, views, None, args)
     sg.sg_volume_destroy(h)
     print(json.dumps(out), flush=True)
 
 
-def tube_volume():
+def tube_volume(args):
     """The 2048^3 tube volume, resident and committed (set-up of the
     workloads that reuse the headline volume)."""
     import torch
@@ -894,7 +908,8 @@ def tube_volume():
     from paper_1804_08197_amd import sg
     dims, B, levels = gen.TUBES_DIMS, gen.TUBES_BRICK, gen.TUBES_LEVELS
     tv = TubeVolume().to_device()
-    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels)
+    h = sg.sg_volume_create(dims, channels=1, dtype=sg.SG_U16, brick=B, levels=levels,
+                            layout=pool_layout(args))
     upload_generated(h, tv, B, slab_bricks=2, build_lod=False)
     sg.sg_build_lod(h, 0, 0)
     sg.sg_set_transfer_function(h, 0, gen.tf_hot(), *gen.TUBE_DOMAIN)
@@ -967,7 +982,7 @@ def run_hmd(h, views, launch, args):
            "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_hmd_variants",
-                      "variants": list(res)},
+                      "variants": list(res), "layout": args.layout},
            "variants": res, "launch": launch, "roofline": alu}
     return out
 
@@ -982,7 +997,7 @@ def bench_octants(args):
     frame takes as long as the slowest octant plus the composite, so the
     headline figure is 1 / (slowest octant). One step = every octant once."""
     from paper_1804_08197_amd import sg
-    h = tube_volume()
+    h = tube_volume(args)
     views = workload_views()
     out = run_octants(h, views, None, args)
     sg.sg_volume_destroy(h)
@@ -1060,7 +1075,7 @@ def run_octants(h, views, launch, args):
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "tubes2048_u16_bricked_stereo_1440x1600_octant_share",
-                      "octant": "1024^3", "slowest": slow},
+                      "octant": "1024^3", "slowest": slow, "layout": args.layout},
            "octants": res, "samples_octants_sum": sum(v["samples"] for v in octs.values()),
            "composite_ms_all_parts": comp_ms, "composite_max_diff_to_whole": comp_err,
            "launch": launch, "roofline": alu}
@@ -1104,7 +1119,7 @@ def run_stream(args):
     if T < 3:
         raise SystemExit("bench.py: --stream-timepoints must be at least 3")
     h = sg.sg_volume_create(dims, channels=C, timepoints=T, dtype=sg.SG_U16, brick=B, levels=L,
-                            cache_slots=args.stream_slots)
+                            cache_slots=args.stream_slots, layout=pool_layout(args))
     store = HostBrickStore(h, dims, B, L, 2)
     t0 = time.time()
     for t in range(T):
@@ -1208,6 +1223,7 @@ def run_stream(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "cells_3x1024x1024x512_u16_stream_stereo_1440x1600",
                       "timepoints_in_host_tier": T, "cache_slots": args.stream_slots,
+                      "layout": args.layout,
                       "bricks_per_timepoint": sum(int(np.prod(g)) for g in store.grids) * C,
                       "brick": B, "levels": L, "channels": C, "step_voxels": 0.5, "ert": 0.99,
                       "lod_tau_px": 1.0},

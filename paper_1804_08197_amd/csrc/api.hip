@@ -121,6 +121,8 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
     return fail(SG_ERR_INVALID_ARG, "levels must be in [1, 16]");
   if (d->device < 0) return fail(SG_ERR_INVALID_ARG, "device must be >= 0");
   if (d->cache_slots < 0) return fail(SG_ERR_INVALID_ARG, "cache_slots must be >= 0");
+  if (d->layout != SG_LAYOUT_LINEAR && d->layout != SG_LAYOUT_MICROBLOCK)
+    return fail(SG_ERR_INVALID_ARG, "layout must be SG_LAYOUT_LINEAR or SG_LAYOUT_MICROBLOCK");
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
@@ -153,7 +155,8 @@ sg_status create(const sg_volume_desc* d, sg_volume** out) {
   }
   v->node_off[v->L] = nodes;
   v->nodes = nodes;
-  const int64_t S3 = (int64_t)v->S * v->S * v->Sx;
+  v->M = d->layout == SG_LAYOUT_MICROBLOCK ? (v->S + 3) / 4 : 0;
+  const int64_t S3 = v->M ? (int64_t)v->M * v->M * v->M * 64 : (int64_t)v->S * v->S * v->Sx;
   v->slot_bytes = ((S3 * v->bpv + 64 + 255) / 256) * 256;
   v->entries = (int64_t)d->timepoints * d->channels * nodes;
   if (v->entries > 0x7FFFFFFF) {

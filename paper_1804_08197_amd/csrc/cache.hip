@@ -26,7 +26,7 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(256) void put_kernel(uint8_t* pool, int64_t slot_bytes,
                                                   const int32_t* slots, const T* src, int n,
-                                                  int S, int Sx) {
+                                                  int S, int Sx, int M) {
   const int64_t per = (int64_t)S * S * S;
   const int64_t total = per * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void put_kernel(uint8_t* pool, int64_t slot_by
     const int64_t b = i / per, r = i - b * per;
     const int64_t row = r / S, x = r - row * S;
     T* dst = reinterpret_cast<T*>(pool + (int64_t)slots[b] * slot_bytes);
-    dst[row * Sx + x] = src[i];
+    dst[slot_index((int)x, (int)(row % S), (int)(row / S), S, Sx, M)] = src[i];
   }
 }
 
@@ -50,13 +50,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void range_list_kernel(const uint8_t* pool, int64_t slot_bytes,
                                                          const int32_t* slots,
                                                          const int32_t* entries,
-                                                         uint32_t* range, int S, int Sx) {
+                                                         uint32_t* range, int S, int Sx,
+                                                         int M) {
   const T* p = reinterpret_cast<const T*>(pool + (int64_t)slots[blockIdx.x] * slot_bytes);
   const int32_t n = S * S * S;
   uint32_t lo = 0xFFFFFFFFu, hi = 0;
   for (int32_t i = threadIdx.x; i < n; i += 256) {
     const int32_t row = i / S, x = i - row * S;
-    const uint32_t v = p[row * Sx + x];
+    const uint32_t v = p[slot_index(x, row % S, row / S, S, Sx, M)];
     lo = min(lo, v);
     hi = max(hi, v);
   }
@@ -259,14 +260,14 @@ sg_status put_impl(sg_volume* vol, int32_t channel, int32_t timepoint, int32_t l
   const int blocks = (int)std::min<int64_t>((work + 255) / 256, 65536);
   if (v->bpv == 1) {
     hipLaunchKernelGGL(put_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, v->pool,
-                       v->slot_bytes, d_slot, (const uint8_t*)dsrc, n, v->S, v->Sx);
+                       v->slot_bytes, d_slot, (const uint8_t*)dsrc, n, v->S, v->Sx, v->M);
     hipLaunchKernelGGL(range_list_kernel<uint8_t>, dim3(n), dim3(256), 0, s, v->pool,
-                       v->slot_bytes, d_slot, d_ent, v->range, v->S, v->Sx);
+                       v->slot_bytes, d_slot, d_ent, v->range, v->S, v->Sx, v->M);
   } else {
     hipLaunchKernelGGL(put_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, v->pool,
-                       v->slot_bytes, d_slot, (const uint16_t*)dsrc, n, v->S, v->Sx);
+                       v->slot_bytes, d_slot, (const uint16_t*)dsrc, n, v->S, v->Sx, v->M);
     hipLaunchKernelGGL(range_list_kernel<uint16_t>, dim3(n), dim3(256), 0, s, v->pool,
-                       v->slot_bytes, d_slot, d_ent, v->range, v->S, v->Sx);
+                       v->slot_bytes, d_slot, d_ent, v->range, v->S, v->Sx, v->M);
   }
   hipLaunchKernelGGL(stamp_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v->stamp,
                      d_slot, n, v->frame);

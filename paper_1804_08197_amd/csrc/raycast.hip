@@ -119,6 +119,7 @@ void fill_args(const Volume* v, const sg_render_params* params, int n_views,
   const int C = v->d.channels;
   a.pool = v->pool;
   a.slot_bytes = v->slot_bytes;
+  a.M = v->M;
   a.page = v->page + (int64_t)params->timepoint * C * v->nodes;
   a.empty = v->empty + (int64_t)params->timepoint * v->nodes;
   a.range = v->range + (int64_t)params->timepoint * C * v->nodes * 2;
@@ -201,11 +202,11 @@ sg_status raycast_plan(Volume* v, RenderArgs& a, bool stats, RaycastPlan* out) {
   const bool gather = a.gather != 0;
   const bool loop = a.persistent || a.wave_tiles > 1;
   const int C = v->d.channels;
-  const void* f = a.model == kModelEmission ? raycast_kernel_emission(v->bpv, C, stats, gather,
-                                                                      loop)
-                  : a.model == kModelMip ? raycast_kernel_mip(v->bpv, C, stats, gather, loop)
-                                         : raycast_kernel_absorption(v->bpv, C, stats, gather,
-                                                                     loop);
+  const bool mb = v->M != 0;
+  const void* f =
+      a.model == kModelEmission ? raycast_kernel_emission(v->bpv, C, stats, gather, loop, mb)
+      : a.model == kModelMip    ? raycast_kernel_mip(v->bpv, C, stats, gather, loop, mb)
+                                : raycast_kernel_absorption(v->bpv, C, stats, gather, loop, mb);
   LaunchConfig c;
   c.gather = a.gather;
   c.tile_log = a.tile_log;

@@ -103,6 +103,63 @@ __device__ __forceinline__ float trilinear(P p0, int sy, int sz, float fx, float
   return lerpf(c0, c1, fz);
 }
 
+// Offset of stored voxel (x, y, z) in a micro-block slot with M blocks per
+// edge (slot_index for M > 0, in 32 bits: slots hold fewer than 2^31 voxels).
+__device__ __forceinline__ int mb_index(int x, int y, int z, int M) {
+  return ((((z >> 2) * M + (y >> 2)) * M + (x >> 2)) << 6) + ((z & 3) << 4) + ((y & 3) << 2) +
+         (x & 3);
+}
+// The steps from a voxel to its +x, +y and +z neighbours in a micro-block
+// slot: inside the voxel's block, or across into the next block.
+struct MbSteps {
+  int dx, dy, dz;
+};
+__device__ __forceinline__ MbSteps mb_steps(int x, int y, int z, int M) {
+  // ((i & 3) + 1) >> 2 is 1 exactly on a block's last voxel; the products
+  // take the scalar block strides as they are (a select between two
+  // non-vector operands would first copy one into a vector register)
+  const int cx = ((x & 3) + 1) >> 2, cy = ((y & 3) + 1) >> 2, cz = ((z & 3) + 1) >> 2;
+  return MbSteps{1 + cx * (64 - 4), 4 + cy * (64 * M - 16), 16 + cz * (64 * M * M - 64)};
+}
+// trilinear's value, operations and order for the stencil at stored index
+// (ix, iy, iz) of a micro-block slot. The voxels are global-memory reads at
+// 32-bit byte offsets from the slot (a slot base held in scalar registers
+// then costs one vector register per address, not two). LEAN: the four
+// voxel pairs are read one after another (no instruction moves across the
+// scheduling barriers), which keeps few registers live in a rarely taken
+// path at the cost of latency.
+template <typename T, bool LEAN = false>
+__device__ __forceinline__ float trilinear_mb(const T* slot, int ix, int iy, int iz, int M,
+                                              float fx, float fy, float fz) {
+  typedef __attribute__((address_space(1))) const uint8_t* Global;
+  const Global base = (Global)(reinterpret_cast<const uint8_t*>(slot));
+  const uint32_t e0 = (uint32_t)mb_index(ix, iy, iz, M) * (uint32_t)sizeof(T);
+  const MbSteps d = mb_steps(ix, iy, iz, M);
+  const uint32_t bx = (uint32_t)d.dx * sizeof(T), by = (uint32_t)d.dy * sizeof(T),
+                 bz = (uint32_t)d.dz * sizeof(T);
+  auto at = [&](uint32_t e) {
+    return (float)*(__attribute__((address_space(1))) const T*)(base + e);
+  };
+  const float c00 = lerpf(at(e0), at(e0 + bx), fx);
+  if (LEAN) __builtin_amdgcn_sched_barrier(0);
+  const float c10 = lerpf(at(e0 + by), at(e0 + by + bx), fx);
+  if (LEAN) __builtin_amdgcn_sched_barrier(0);
+  const float c01 = lerpf(at(e0 + bz), at(e0 + bz + bx), fx);
+  if (LEAN) __builtin_amdgcn_sched_barrier(0);
+  const float c11 = lerpf(at(e0 + bz + by), at(e0 + bz + by + bx), fx);
+  const float c0 = lerpf(c00, c10, fy);
+  const float c1 = lerpf(c01, c11, fy);
+  return lerpf(c0, c1, fz);
+}
+// The pool stencil of either slot layout (MB: micro-block slots, see
+// slot_index).
+template <bool MB, typename T>
+__device__ __forceinline__ float pool_trilinear(const RenderArgs& a, const T* slot, int ix, int iy,
+                                                int iz, float fx, float fy, float fz) {
+  if (MB) return trilinear_mb(slot, ix, iy, iz, a.M, fx, fy, fz);
+  return trilinear(slot + (iz * a.S + iy) * a.Sx + ix, a.Sx, a.S * a.Sx, fx, fy, fz);
+}
+
 // A voxel of a staged region in LDS. The reads are volatile so that the
 // compiler issues one aligned read per voxel: it would otherwise merge the
 // two voxels of a stencil row into one 2- or 4-byte read, which is
@@ -791,12 +848,12 @@ __device__ __forceinline__ void load_tf(const RenderArgs& a, float4* s_tf) {
 // ------------------------------------------------------------ gather kernel
 // The pool stencil of one sample: its eight voxels and fractions, loaded
 // ahead of their use (the same index, clamp and fraction arithmetic as
-// shade_ea's read of the pool).
+// shade_ea's read of the pool; MB: micro-block slots).
 struct Stencil {
   uint32_t v[8];
   float fx, fy, fz;
 };
-template <typename T>
+template <typename T, bool MB>
 __device__ __forceinline__ Stencil stencil_at(const Ray& r, const RenderArgs& a, const T* slot,
                                               float tau) {
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
@@ -809,6 +866,19 @@ __device__ __forceinline__ Stencil stencil_at(const Ray& r, const RenderArgs& a,
   st.fx = __builtin_amdgcn_fractf(qx);
   st.fy = __builtin_amdgcn_fractf(qy);
   st.fz = __builtin_amdgcn_fractf(qz);
+  if (MB) {
+    const T* p0 = slot + mb_index(ix, iy, iz, a.M);
+    const MbSteps d = mb_steps(ix, iy, iz, a.M);
+    st.v[0] = p0[0];
+    st.v[1] = p0[d.dx];
+    st.v[2] = p0[d.dy];
+    st.v[3] = p0[d.dy + d.dx];
+    st.v[4] = p0[d.dz];
+    st.v[5] = p0[d.dz + d.dx];
+    st.v[6] = p0[d.dz + d.dy];
+    st.v[7] = p0[d.dz + d.dy + d.dx];
+    return st;
+  }
   const T* p0 = slot + (iz * a.S + iy) * a.Sx + ix;
   const int sy = a.Sx, sz = a.S * a.Sx;
   st.v[0] = p0[0];
@@ -860,20 +930,21 @@ __device__ __forceinline__ bool shade_step(Ray& r, const RenderArgs& a, const fl
 // body and pinned there (no instruction moves across the scheduling
 // barrier); the last full step loads its own stencil again instead of the
 // partial step's.
-template <typename T, bool DEPTH, typename F>
+template <typename T, bool DEPTH, bool MB, typename F>
 __device__ __forceinline__ void gather_run(Ray& r, const RenderArgs& a, const float4* s_tf,
                                            const T* slot, F&& fetch, int (*mb_key)[3]) {
   const TfWin<1> w = tf_win<1>(a);
   const int kb = r.n - 1, kf = r.n - 2;
   if (r.k <= kf) {
-    Stencil c0 = stencil_at(r, a, slot, r.tau);
-    Stencil c1 = stencil_at(r, a, slot, r.k < kf ? r.tau + r.Df : r.tau);
+    Stencil c0 = stencil_at<T, MB>(r, a, slot, r.tau);
+    Stencil c1 = stencil_at<T, MB>(r, a, slot, r.k < kf ? r.tau + r.Df : r.tau);
     bool go = true;
     while (go) {
       const float t1 = r.k < kf ? r.tau + r.Df : r.tau;
       const float t2 = r.k + 1 < kf ? t1 + r.Df : t1;
       const float t3 = r.k + 2 < kf ? t2 + r.Df : t2;
-      const Stencil n0 = stencil_at(r, a, slot, t2), n1 = stencil_at(r, a, slot, t3);
+      const Stencil n0 = stencil_at<T, MB>(r, a, slot, t2);
+      const Stencil n1 = stencil_at<T, MB>(r, a, slot, t3);
       __builtin_amdgcn_sched_barrier(0);
       const float4 e0 = tf_lookup(a, s_tf, 0, stencil_value(c0), w.scale[0], w.bias[0]);
       const float4 e1 = tf_lookup(a, s_tf, 0, stencil_value(c1), w.scale[0], w.bias[0]);
@@ -889,7 +960,7 @@ __device__ __forceinline__ void gather_run(Ray& r, const RenderArgs& a, const fl
   if (terminated(r, a)) r.alive = false;
 }
 
-template <typename T, int CH, bool STATS, int MODEL>
+template <typename T, int CH, bool STATS, int MODEL, bool MB>
 __device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* s_tf,
                                              const TileLane& tl) {
   // the view is the same for every lane of the wave (one 8x8 tile)
@@ -901,19 +972,18 @@ __device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* 
   Ray r;
   ray_setup(r, a, V, tl.px, tl.py);
   if (r.alive) next_segment<MODEL, CH>(r, a, V, true);
-  const int sy = a.Sx, sz = a.S * a.Sx;
   while (r.alive) {
     const T* slot[CH];
     slot_ptrs<T, CH>(a, r.node, slot, true);
     if (STATS) atomicAdd((unsigned long long*)a.counters + 1, 1ull);
     auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-      return trilinear(slot[ch] + (iz * a.S + iy) * a.Sx + ix, sy, sz, fx, fy, fz);
+      return pool_trilinear<MB>(a, slot[ch], ix, iy, iz, fx, fy, fz);
     };
     if (CH == 1 && !STATS && MODEL == kModelAbsorption) {
       if (depth_on)
-        gather_run<T, true>(r, a, s_tf, slot[0], fetch, mb_key);
+        gather_run<T, true, MB>(r, a, s_tf, slot[0], fetch, mb_key);
       else
-        gather_run<T, false>(r, a, s_tf, slot[0], fetch, mb_key);
+        gather_run<T, false, MB>(r, a, s_tf, slot[0], fetch, mb_key);
     } else if (depth_on) {
       sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, r.n - 1, mb_key);
     } else {
@@ -933,7 +1003,7 @@ __device__ __forceinline__ bool gather_pixel(const RenderArgs& a, const float4* 
 // LOOP: the wave renders several tiles (persistent grid, or a direct grid
 // with more wave tiles than waves per workgroup); without it exactly one.
 // The two are separate instances because the loop costs registers.
-template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
+template <typename T, int CH, bool STATS, int MODEL, bool LOOP, bool MB>
 __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
   if (a.enable && *a.enable == 0) return;  // whole grid: before any barrier
   extern __shared__ float4 s_tf[];
@@ -941,20 +1011,20 @@ __global__ __launch_bounds__(256) void raycast_gather(RenderArgs a) {
   if (!LOOP) {
     const TileLane tl = tile_lane(a, 0);
     bool nz = false;
-    if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+    if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL, MB>(a, s_tf, tl);
     mark_tile(a, tl, nz);
   } else if (a.persistent) {
     TileLane tl;
     while (next_tile(a, tl)) {
       bool nz = false;
-      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL, MB>(a, s_tf, tl);
       mark_tile(a, tl, nz);
     }
   } else {
     for (int it = 0; it < a.wave_tiles; ++it) {
       const TileLane tl = tile_lane(a, it);
       bool nz = false;
-      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL>(a, s_tf, tl);
+      if (tl.in_image) nz = gather_pixel<T, CH, STATS, MODEL, MB>(a, s_tf, tl);
       mark_tile(a, tl, nz);
     }
   }
@@ -1092,7 +1162,7 @@ __device__ __forceinline__ void stat_loop(const RenderArgs& a, int taken, bool p
 }
 
 // One wave tile of the staged kernel (the whole wave active).
-template <typename T, int CH, bool STATS, int MODEL>
+template <typename T, int CH, bool STATS, int MODEL, bool MB>
 __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s_tf, T* stage,
                                             const TileLane& tl) {
   const int lane = threadIdx.x & 63;
@@ -1161,6 +1231,28 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     const float my_sum = fabsf(r.dq[0]) + fabsf(r.dq[1]) + fabsf(r.dq[2]);
     const bool bad = mine && !((float)sgn * my_dqm >= 0.25f * my_sum);
     const bool axis_ok = __ballot(bad) == 0;
+    // samples r.k .. kb of this lane read from the pool (a sample loop per
+    // slot layout: one loop choosing per sample would hold the registers of
+    // both address forms)
+    auto pool_run = [&](int kb) {
+      if (MB) {
+        auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+          return trilinear_mb<T, true>(slot[ch], ix, iy, iz, a.M, fx, fy, fz);
+        };
+        if (depth_on)
+          sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, kb, mb_key);
+        else
+          sample_run<MODEL, CH, STATS, true, false>(r, a, s_tf, fetch, kb, mb_key);
+      } else {
+        auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
+          return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
+        };
+        if (depth_on)
+          sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, kb, mb_key);
+        else
+          sample_run<MODEL, CH, STATS, true, false>(r, a, s_tf, fetch, kb, mb_key);
+      }
+    };
 
     // --- slabs along the main axis, in the rays' direction of travel. The
     // first slab starts at the first stencil layer any ray needs; each owns
@@ -1182,15 +1274,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         // no shared dominant direction (or, defensively, nothing left in
         // range): read the pool for all remaining samples
         const int k_before = r.k;
-        if (more) {
-          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
-          };
-          if (depth_on)
-            sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, r.n - 1, mb_key);
-          else
-            sample_run<MODEL, CH, STATS, true, false>(r, a, s_tf, fetch, r.n - 1, mb_key);
-        }
+        if (more) pool_run(r.n - 1);
         if (STATS) stat_loop(a, r.k - k_before, true);
         continue;
       }
@@ -1312,18 +1396,44 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           // multiplier into the loop)
           asm volatile("" : "+v"(step), "+v"(step_c));
           const int lim = rr < R ? rows - rr : 0;  // the lane's rows: r0 + rr < rows
-          for (int r0 = 0; r0 < rows; r0 += R) {
-            if (r0 < lim) {
+          if (MB) {
+            // micro-block slots: the lane's chunk (two u16 or four u8 voxels
+            // from an even x) lies in one block row; its offset is formed
+            // from the row's y and z at each pass
+            const int x = o[0] + col * align;
+            const int xo = ((x >> 2) << 6) + (x & 3);
+            const int M = a.M, yend = o[1] + wy;
+            int y = o[1] + yy, z = o[2] + pz;
+            for (int r0 = 0; r0 < rows; r0 += R) {
+              if (r0 < lim) {
+                const int e = ((((z >> 2) * M + (y >> 2)) * M) << 6) + ((z & 3) << 4) +
+                              ((y & 3) << 2) + xo;
 #pragma unroll
-              for (int ch = 0; ch < CH; ++ch)
-                __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)gb,
-                    reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
+                for (int ch = 0; ch < CH; ++ch)
+                  __builtin_amdgcn_global_load_lds(
+                      reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)(e * (int)sizeof(T)),
+                      reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
+              }
+              y += dy;
+              z += dz;
+              const bool c = y >= yend;
+              y -= c ? wy : 0;
+              z += c ? 1 : 0;
             }
-            yy += dy;
-            const bool c = yy >= wy;
-            yy -= c ? wy : 0;
-            gb += c ? step_c : step;
+          } else {
+            for (int r0 = 0; r0 < rows; r0 += R) {
+              if (r0 < lim) {
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch)
+                  __builtin_amdgcn_global_load_lds(
+                      reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)gb,
+                      reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
+              }
+              yy += dy;
+              const bool c = yy >= wy;
+              yy -= c ? wy : 0;
+              gb += c ? step_c : step;
+            }
           }
         } else {
           // rows wider than a pass (bricks of 128 or more): pass p moves
@@ -1337,11 +1447,16 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
             if (i < total) {
               const int row = (int)(((float)i + 0.5f) * inv_cpr);
               const int rz = (int)(((float)row + 0.5f) * inv_wy);
-              const int g = base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane);
+              // byte offset in the slot: chunk g of a linear slot, or the
+              // chunk's first voxel in a micro-block slot
+              const size_t off =
+                  MB ? (size_t)mb_index(o[0] + (i - row * cpr) * align, o[1] + row - rz * wy,
+                                         o[2] + rz, a.M) * sizeof(T)
+                      : (size_t)(base + i + __mul24(row, skip_row) + __mul24(rz, skip_plane)) * cb;
 #pragma unroll
               for (int ch = 0; ch < CH; ++ch)
                 __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const uint8_t*>(slot[ch]) + (size_t)g * cb,
+                    reinterpret_cast<const uint8_t*>(slot[ch]) + off,
                     reinterpret_cast<uint8_t*>(stage + ch * cap) + p0 * cb, cb, 0, 0);
             }
           }
@@ -1377,13 +1492,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
       } else {
         if (kb >= r.k) {
           // the slab does not fit even one layer deep: read the pool for it
-          auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
-            return trilinear(slot[ch] + (iz * S + iy) * Sx + ix, Sx, S * Sx, fx, fy, fz);
-          };
-          if (depth_on)
-            sample_run<MODEL, CH, STATS, true, true>(r, a, s_tf, fetch, kb, mb_key);
-          else
-            sample_run<MODEL, CH, STATS, true, false>(r, a, s_tf, fetch, kb, mb_key);
+          pool_run(kb);
         }
         if (STATS) stat_loop(a, r.k - k_slab, true);
       }
@@ -1403,7 +1512,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
   mark_tile(a, tl, nz);
 }
 
-template <typename T, int CH, bool STATS, int MODEL, bool LOOP>
+template <typename T, int CH, bool STATS, int MODEL, bool LOOP, bool MB>
 __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   if (a.enable && *a.enable == 0) return;  // whole grid: before any barrier
   extern __shared__ float4 smem[];
@@ -1416,50 +1525,56 @@ __global__ __launch_bounds__(256) void raycast_staged(RenderArgs a) {
   // no workgroup barrier follows: the waves work independently from here
   if (!LOOP) {
     const TileLane tl = tile_lane(a, 0);
-    if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+    if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL, MB>(a, s_tf, stage, tl);
   } else if (a.persistent) {
     TileLane tl;
     while (next_tile(a, tl))
-      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL, MB>(a, s_tf, stage, tl);
   } else {
     for (int it = 0; it < a.wave_tiles; ++it) {
       const TileLane tl = tile_lane(a, it);
-      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL>(a, s_tf, stage, tl);
+      if (tl.tile_valid) staged_tile<T, CH, STATS, MODEL, MB>(a, s_tf, stage, tl);
     }
   }
 }
 
-template <typename T, int CH, int MODEL, bool LOOP>
+template <typename T, int CH, int MODEL, bool LOOP, bool MB>
 const void* kernel_for(bool stats, bool gather) {
   if (gather)
-    return stats ? reinterpret_cast<const void*>(raycast_gather<T, CH, true, MODEL, LOOP>)
-                 : reinterpret_cast<const void*>(raycast_gather<T, CH, false, MODEL, LOOP>);
-  return stats ? reinterpret_cast<const void*>(raycast_staged<T, CH, true, MODEL, LOOP>)
-               : reinterpret_cast<const void*>(raycast_staged<T, CH, false, MODEL, LOOP>);
+    return stats ? reinterpret_cast<const void*>(raycast_gather<T, CH, true, MODEL, LOOP, MB>)
+                 : reinterpret_cast<const void*>(raycast_gather<T, CH, false, MODEL, LOOP, MB>);
+  return stats ? reinterpret_cast<const void*>(raycast_staged<T, CH, true, MODEL, LOOP, MB>)
+               : reinterpret_cast<const void*>(raycast_staged<T, CH, false, MODEL, LOOP, MB>);
+}
+template <typename T, int CH, int MODEL, bool LOOP>
+const void* kernel_for(bool stats, bool gather, bool mb) {
+  return mb ? kernel_for<T, CH, MODEL, LOOP, true>(stats, gather)
+            : kernel_for<T, CH, MODEL, LOOP, false>(stats, gather);
 }
 
 template <typename T, int MODEL>
-const void* kernel_ch(int C, bool stats, bool gather, bool loop) {
+const void* kernel_ch(int C, bool stats, bool gather, bool loop, bool mb) {
   switch (C) {
-    case 1: return loop ? kernel_for<T, 1, MODEL, true>(stats, gather)
-                        : kernel_for<T, 1, MODEL, false>(stats, gather);
-    case 2: return loop ? kernel_for<T, 2, MODEL, true>(stats, gather)
-                        : kernel_for<T, 2, MODEL, false>(stats, gather);
-    case 3: return loop ? kernel_for<T, 3, MODEL, true>(stats, gather)
-                        : kernel_for<T, 3, MODEL, false>(stats, gather);
-    default: return loop ? kernel_for<T, 4, MODEL, true>(stats, gather)
-                         : kernel_for<T, 4, MODEL, false>(stats, gather);
+    case 1: return loop ? kernel_for<T, 1, MODEL, true>(stats, gather, mb)
+                        : kernel_for<T, 1, MODEL, false>(stats, gather, mb);
+    case 2: return loop ? kernel_for<T, 2, MODEL, true>(stats, gather, mb)
+                        : kernel_for<T, 2, MODEL, false>(stats, gather, mb);
+    case 3: return loop ? kernel_for<T, 3, MODEL, true>(stats, gather, mb)
+                        : kernel_for<T, 3, MODEL, false>(stats, gather, mb);
+    default: return loop ? kernel_for<T, 4, MODEL, true>(stats, gather, mb)
+                         : kernel_for<T, 4, MODEL, false>(stats, gather, mb);
   }
 }
 
 }  // namespace
 
 // The ray-casting kernel of one optical model for a voxel type and channel
-// count (instrumented or not, staged or gather, one tile per wave or a loop).
+// count (instrumented or not, staged or gather, one tile per wave or a loop,
+// linear or micro-block slots).
 template <int MODEL>
-const void* model_kernel(int bpv, int channels, bool stats, bool gather, bool loop) {
-  if (bpv == 1) return kernel_ch<uint8_t, MODEL>(channels, stats, gather, loop);
-  return kernel_ch<uint16_t, MODEL>(channels, stats, gather, loop);
+const void* model_kernel(int bpv, int channels, bool stats, bool gather, bool loop, bool mb) {
+  if (bpv == 1) return kernel_ch<uint8_t, MODEL>(channels, stats, gather, loop, mb);
+  return kernel_ch<uint16_t, MODEL>(channels, stats, gather, loop, mb);
 }
 
 }  // namespace sg

@@ -5,8 +5,8 @@
 namespace sg {
 
 const void* raycast_kernel_mip(int bpv, int channels, bool stats, bool gather,
-                               bool loop) {
-  return model_kernel<kModelMip>(bpv, channels, stats, gather, loop);
+                               bool loop, bool mb) {
+  return model_kernel<kModelMip>(bpv, channels, stats, gather, loop, mb);
 }
 
 }  // namespace sg

@@ -127,6 +127,17 @@ struct InlineViews {
   int32_t n;  // 0: the device table is already in place
 };
 
+// Element offset of stored voxel (x, y, z) in a pool slot, 0 <= x < Sx and
+// 0 <= y, z < S. Linear slots (M = 0): rows of Sx voxels, x fastest.
+// Micro-block slots (M = ceil(S / 4) >= Sx / 4): M^3 blocks of 4^3 voxels,
+// each contiguous with x fastest inside it, the blocks in x-fastest order.
+__host__ __device__ __forceinline__ int64_t slot_index(int x, int y, int z, int S, int Sx,
+                                                       int M) {
+  if (M == 0) return ((int64_t)z * S + y) * Sx + x;
+  return ((((int64_t)(z >> 2) * M + (y >> 2)) * M + (x >> 2)) << 6) + ((z & 3) << 4) +
+         ((y & 3) << 2) + (x & 3);
+}
+
 struct Volume {
   sg_volume_desc d{};
   int bpv = 0;       // bytes per voxel
@@ -134,6 +145,7 @@ struct Volume {
   int logB = 0;
   int S = 0;         // stored edge B + 2
   int Sx = 0;        // row stride in voxels (S rounded up to kRowAlignBytes)
+  int M = 0;         // SG_LAYOUT_MICROBLOCK: 4^3 blocks per slot edge; 0: linear
   int L = 0;         // levels
   int32_t ldims[kMaxLevels][3]{};
   int32_t grid[kMaxLevels][3]{};
@@ -307,6 +319,7 @@ struct RenderArgs {
   uint32_t* stamp;      // cache volumes: [slots] frame of last use, else NULL
   uint32_t frame;
   int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
+  int32_t M;            // micro-blocks per slot edge, 0 for linear slots
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
   int32_t stage_bytes;  // LDS staging bytes per wave
@@ -331,11 +344,14 @@ struct RaycastPlan {
 };
 sg_status raycast_plan(Volume* v, RenderArgs& a, bool stats, RaycastPlan* out);
 sg_status raycast_launch(Volume* v, RenderArgs& a, bool stats, Launch* out);
-// Kernel instances per optical model (one translation unit each).
+// Kernel instances per optical model (one translation unit each); mb:
+// micro-block pool slots.
 const void* raycast_kernel_absorption(int bpv, int channels, bool stats, bool gather,
-                                      bool loop);
-const void* raycast_kernel_emission(int bpv, int channels, bool stats, bool gather, bool loop);
-const void* raycast_kernel_mip(int bpv, int channels, bool stats, bool gather, bool loop);
+                                      bool loop, bool mb);
+const void* raycast_kernel_emission(int bpv, int channels, bool stats, bool gather, bool loop,
+                                    bool mb);
+const void* raycast_kernel_mip(int bpv, int channels, bool stats, bool gather, bool loop,
+                               bool mb);
 
 }  // namespace sg
 

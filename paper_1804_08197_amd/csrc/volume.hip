@@ -3,9 +3,10 @@
 // per-transfer-function refresh).
 //
 // Pool layout: one slot per (timepoint, channel, node); a slot stores the
-// node's brick as (B+2)^3 voxels, x fastest, rows padded to a multiple of 4
-// bytes (row stride Sx), the core at offset (1, 1, 1) and a one-voxel apron
-// around it holding the clamped neighbour values
+// node's brick as (B+2)^3 voxels, the core at offset (1, 1, 1) and a
+// one-voxel apron around it holding the clamped neighbour values, in the
+// volume's slot layout (slot_index): linear rows, x fastest, padded to a
+// multiple of 4 bytes (row stride Sx), or 4^3-voxel micro-blocks
 // (Sec 5.2: blocks of a multi-resolution pyramid; Sec 4.2: chunks resident
 // in a GPU cache). With the apron, any trilinear sample inside a node reads
 // only that node's slot.
@@ -39,7 +40,7 @@ template <typename T>
 __global__ void upload_kernel(uint8_t* pool, int64_t slot_bytes,
                               const int32_t* page, LevelGeom lg,
                               const int32_t* coords, const T* src, int n,
-                              int logB, int S, int Sx) {
+                              int logB, int S, int Sx, int M) {
   const int64_t per = (int64_t)1 << (3 * logB);
   const int64_t total = (int64_t)n * per;
   const int32_t B = 1 << logB, mask = B - 1;
@@ -51,7 +52,7 @@ __global__ void upload_kernel(uint8_t* pool, int64_t slot_bytes,
     const int32_t* c = coords + 3 * j;
     int64_t node = lg.node_off + ((int64_t)c[2] * lg.g[1] + c[1]) * lg.g[0] + c[0];
     T* dst = slot_ptr<T>(pool, slot_bytes, page[node]);
-    dst[((int64_t)(lz + 1) * S + (ly + 1)) * Sx + (lx + 1)] = src[i];
+    dst[slot_index(lx + 1, ly + 1, lz + 1, S, Sx, M)] = src[i];
   }
 }
 
@@ -60,7 +61,7 @@ __global__ void upload_kernel(uint8_t* pool, int64_t slot_bytes,
 template <typename T>
 __global__ void downsample_kernel(uint8_t* pool, int64_t slot_bytes,
                                   const int32_t* page, LevelGeom src,
-                                  LevelGeom dst, int logB, int S, int Sx) {
+                                  LevelGeom dst, int logB, int S, int Sx, int M) {
   const int32_t B = 1 << logB, mask = B - 1;
   const int64_t per = (int64_t)1 << (3 * logB);
   const int64_t nb = (int64_t)dst.g[0] * dst.g[1] * dst.g[2];
@@ -89,11 +90,11 @@ __global__ void downsample_kernel(uint8_t* pool, int64_t slot_bytes,
                              src.g[0] +
                          (h[0] >> logB);
           const T* p = slot_ptr<T>(pool, slot_bytes, page[node]);
-          sum += p[((int64_t)((h[2] & mask) + 1) * S + ((h[1] & mask) + 1)) * Sx +
-                   ((h[0] & mask) + 1)];
+          sum += p[slot_index((h[0] & mask) + 1, (h[1] & mask) + 1, (h[2] & mask) + 1, S, Sx,
+                              M)];
         }
     T* q = slot_ptr<T>(pool, slot_bytes, page[dst.node_off + j]);
-    q[((int64_t)(l[2] + 1) * S + (l[1] + 1)) * Sx + (l[0] + 1)] = (T)((sum + 4u) >> 3);
+    q[slot_index(l[0] + 1, l[1] + 1, l[2] + 1, S, Sx, M)] = (T)((sum + 4u) >> 3);
   }
 }
 
@@ -103,7 +104,7 @@ __global__ void downsample_kernel(uint8_t* pool, int64_t slot_bytes,
 template <typename T>
 __global__ void apron_kernel(uint8_t* pool, int64_t slot_bytes,
                              const int32_t* page, LevelGeom lg, int logB,
-                             int S, int Sx) {
+                             int S, int Sx, int M) {
   const int32_t B = 1 << logB, mask = B - 1;
   const int64_t rows = (int64_t)S * S;
   const int64_t nb = (int64_t)lg.g[0] * lg.g[1] * lg.g[2];
@@ -119,8 +120,7 @@ __global__ void apron_kernel(uint8_t* pool, int64_t slot_bytes,
     bool row_core = y >= 1 && y <= B && z >= 1 && z <= B && gy < lg.n[1] &&
                     gz < lg.n[2];
     int32_t cy = clampi(gy, 0, lg.n[1] - 1), cz = clampi(gz, 0, lg.n[2] - 1);
-    T* dst = slot_ptr<T>(pool, slot_bytes, page[lg.node_off + j]) +
-             ((int64_t)z * S + y) * Sx;
+    T* dst = slot_ptr<T>(pool, slot_bytes, page[lg.node_off + j]);
     for (int32_t x = 0; x < S; ++x) {
       int32_t gx = b[0] * B - 1 + x;
       bool core = row_core && x >= 1 && x <= B && gx < lg.n[0];
@@ -130,8 +130,8 @@ __global__ void apron_kernel(uint8_t* pool, int64_t slot_bytes,
                      ((int64_t)(cz >> logB) * lg.g[1] + (cy >> logB)) * lg.g[0] +
                      (cx >> logB);
       const T* p = slot_ptr<T>(pool, slot_bytes, page[node]);
-      dst[x] = p[((int64_t)((cz & mask) + 1) * S + ((cy & mask) + 1)) * Sx +
-                 ((cx & mask) + 1)];
+      dst[slot_index(x, y, z, S, Sx, M)] =
+          p[slot_index((cx & mask) + 1, (cy & mask) + 1, (cz & mask) + 1, S, Sx, M)];
     }
   }
 }
@@ -142,14 +142,15 @@ __global__ __launch_bounds__(256) void range_kernel(const uint8_t* pool,
                                                     int64_t slot_bytes,
                                                     const int32_t* page,
                                                     uint32_t* range,
-                                                    int64_t nodes, int S, int Sx) {
+                                                    int64_t nodes, int S, int Sx, int M) {
   const int64_t node = blockIdx.x;
   const T* p = reinterpret_cast<const T*>(pool + (int64_t)page[node] * slot_bytes);
   const int32_t n = S * S * S;
   uint32_t lo = 0xFFFFFFFFu, hi = 0;
   for (int32_t i = threadIdx.x; i < n; i += 256) {
-    const int32_t row = i / S, x = i - row * S;  // skip the row padding
-    uint32_t v = p[row * Sx + x];
+    const int32_t row = i / S, x = i - row * S;  // (not the row padding)
+    const int32_t y = row % S, z = row / S;
+    uint32_t v = p[slot_index(x, y, z, S, Sx, M)];
     lo = min(lo, v);
     hi = max(hi, v);
   }
@@ -232,11 +233,11 @@ sg_status launch_upload(Volume* v, int c, int t, int level, int n,
   if (v->bpv == 1)
     hipLaunchKernelGGL(upload_kernel<uint8_t>, dim3(blocks_for(work)), dim3(256), 0, s,
                        v->pool, v->slot_bytes, page_at(v, c, t), lg, dcoords,
-                       (const uint8_t*)dsrc, n, v->logB, v->S, v->Sx);
+                       (const uint8_t*)dsrc, n, v->logB, v->S, v->Sx, v->M);
   else
     hipLaunchKernelGGL(upload_kernel<uint16_t>, dim3(blocks_for(work)), dim3(256), 0, s,
                        v->pool, v->slot_bytes, page_at(v, c, t), lg, dcoords,
-                       (const uint16_t*)dsrc, n, v->logB, v->S, v->Sx);
+                       (const uint16_t*)dsrc, n, v->logB, v->S, v->Sx, v->M);
   SG_HIP(hipGetLastError());
   return SG_OK;
 }
@@ -247,11 +248,12 @@ sg_status launch_downsample(Volume* v, int c, int t, int level_dst,
   int64_t work = ((int64_t)dst.g[0] * dst.g[1] * dst.g[2]) << (3 * v->logB);
   if (v->bpv == 1)
     hipLaunchKernelGGL(downsample_kernel<uint8_t>, dim3(blocks_for(work)), dim3(256), 0, s,
-                       v->pool, v->slot_bytes, page_at(v, c, t), src, dst, v->logB, v->S, v->Sx);
+                       v->pool, v->slot_bytes, page_at(v, c, t), src, dst, v->logB, v->S, v->Sx,
+                       v->M);
   else
     hipLaunchKernelGGL(downsample_kernel<uint16_t>, dim3(blocks_for(work)), dim3(256), 0,
                        s, v->pool, v->slot_bytes, page_at(v, c, t), src, dst, v->logB,
-                       v->S, v->Sx);
+                       v->S, v->Sx, v->M);
   SG_HIP(hipGetLastError());
   return SG_OK;
 }
@@ -262,10 +264,12 @@ sg_status launch_apron(Volume* v, int c, int t, hipStream_t s) {
     int64_t work = (int64_t)lg.g[0] * lg.g[1] * lg.g[2] * v->S * v->S;
     if (v->bpv == 1)
       hipLaunchKernelGGL(apron_kernel<uint8_t>, dim3(blocks_for(work)), dim3(256), 0, s,
-                         v->pool, v->slot_bytes, page_at(v, c, t), lg, v->logB, v->S, v->Sx);
+                         v->pool, v->slot_bytes, page_at(v, c, t), lg, v->logB, v->S, v->Sx,
+                         v->M);
     else
       hipLaunchKernelGGL(apron_kernel<uint16_t>, dim3(blocks_for(work)), dim3(256), 0, s,
-                         v->pool, v->slot_bytes, page_at(v, c, t), lg, v->logB, v->S, v->Sx);
+                         v->pool, v->slot_bytes, page_at(v, c, t), lg, v->logB, v->S, v->Sx,
+                         v->M);
     SG_HIP(hipGetLastError());
   }
   return SG_OK;
@@ -275,10 +279,12 @@ sg_status launch_range(Volume* v, int c, int t, hipStream_t s) {
   uint32_t* r = v->range + 2 * ((int64_t)t * v->d.channels + c) * v->nodes;
   if (v->bpv == 1)
     hipLaunchKernelGGL(range_kernel<uint8_t>, dim3((unsigned)v->nodes), dim3(256), 0, s,
-                       v->pool, v->slot_bytes, page_at(v, c, t), r, v->nodes, v->S, v->Sx);
+                       v->pool, v->slot_bytes, page_at(v, c, t), r, v->nodes, v->S, v->Sx,
+                       v->M);
   else
     hipLaunchKernelGGL(range_kernel<uint16_t>, dim3((unsigned)v->nodes), dim3(256), 0, s,
-                       v->pool, v->slot_bytes, page_at(v, c, t), r, v->nodes, v->S, v->Sx);
+                       v->pool, v->slot_bytes, page_at(v, c, t), r, v->nodes, v->S, v->Sx,
+                       v->M);
   SG_HIP(hipGetLastError());
   return SG_OK;
 }

@@ -22,11 +22,12 @@ SG_ERR_DEVICE = -3
 SG_ERR_STATE = -4
 SG_ERR_UNSUPPORTED = -5
 SG_U8, SG_U16 = 1, 2
+SG_LAYOUT_LINEAR, SG_LAYOUT_MICROBLOCK = 0, 1
 SG_LOD, SG_SKIP_EMPTY, SG_GATHER = 1, 2, 4
 SG_MODEL_EMISSION_ABSORPTION, SG_MODEL_EMISSION_ONLY, SG_MODEL_MAX_INTENSITY = 0, 1, 2
 MODELS = {"ea": SG_MODEL_EMISSION_ABSORPTION, "eo": SG_MODEL_EMISSION_ONLY,
           "mip": SG_MODEL_MAX_INTENSITY}
-SG_ABI_VERSION = 4
+SG_ABI_VERSION = 5
 
 
 class SgError(RuntimeError):
@@ -38,7 +39,7 @@ class SgError(RuntimeError):
 class sg_volume_desc(C.Structure):
     _fields_ = [("dims", C.c_int32 * 3), ("channels", C.c_int32), ("timepoints", C.c_int32),
                 ("dtype", C.c_int32), ("brick", C.c_int32), ("levels", C.c_int32),
-                ("device", C.c_int32), ("cache_slots", C.c_int32)]
+                ("device", C.c_int32), ("cache_slots", C.c_int32), ("layout", C.c_int32)]
 
 
 class sg_view(C.Structure):
@@ -256,13 +257,13 @@ def sg_last_error() -> str:
 
 
 def sg_volume_create(dims, channels=1, timepoints=1, dtype=SG_U16, brick=64, levels=1,
-                     device=0, cache_slots=0):
+                     device=0, cache_slots=0, layout=SG_LAYOUT_LINEAR):
     d = sg_volume_desc()
     for i in range(3):
         d.dims[i] = int(dims[i])
     d.channels, d.timepoints, d.dtype = int(channels), int(timepoints), int(dtype)
     d.brick, d.levels, d.device = int(brick), int(levels), int(device)
-    d.cache_slots = int(cache_slots)
+    d.cache_slots, d.layout = int(cache_slots), int(layout)
     h = C.c_void_p()
     _check(_lib.sg_volume_create(C.byref(d), C.byref(h)), "sg_volume_create")
     return h

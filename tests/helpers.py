@@ -7,6 +7,9 @@ import numpy as np
 ERT = 0.99
 BRACKET = 1e-5  # early-termination threshold bracket (several correct results)
 TOL = 1e-4      # max abs RGBA error against the oracle
+# pool slot layouts (sg_layout), as test parameters
+LAYOUTS = [0, 1]
+LAYOUT_IDS = ["linear", "microblock"]
 
 
 def as_f64_tf(tf):
@@ -14,7 +17,7 @@ def as_f64_tf(tf):
     return np.asarray(tf, dtype=np.float32).astype(np.float64)
 
 
-def gpu_volume(channels, brick, levels, tfs, domains, device_upload=True):
+def gpu_volume(channels, brick, levels, tfs, domains, device_upload=True, layout=0):
     import torch
 
     from paper_1804_08197_amd import sg, upload_volume
@@ -22,7 +25,7 @@ def gpu_volume(channels, brick, levels, tfs, domains, device_upload=True):
     nz, ny, nx = vol0.shape
     dtype = sg.SG_U8 if vol0.dtype == np.uint8 else sg.SG_U16
     h = sg.sg_volume_create((nx, ny, nz), channels=len(channels), dtype=dtype, brick=brick,
-                            levels=levels)
+                            levels=levels, layout=layout)
     for c, v in enumerate(channels):
         data = torch.from_numpy(v).cuda() if device_upload else v
         upload_volume(h, data, brick, channel=c)

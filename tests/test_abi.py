@@ -92,7 +92,7 @@ int main(void) {
 
 
 def test_version_and_status_strings(sg):
-    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 4
+    assert sg.sg_abi_version() == sg.SG_ABI_VERSION == 5
     for code, name in [(0, "SG_OK"), (-1, "SG_ERR_INVALID_ARG"), (-2, "SG_ERR_OUT_OF_MEMORY"),
                        (-3, "SG_ERR_DEVICE"), (-4, "SG_ERR_STATE"), (-5, "SG_ERR_UNSUPPORTED")]:
         assert sg.sg_status_string(code) == name
@@ -104,7 +104,8 @@ def test_version_and_status_strings(sg):
     dict(dims=(8, 8, 8), timepoints=0), dict(dims=(8, 8, 8), dtype=3),
     dict(dims=(8, 8, 8), brick=48), dict(dims=(8, 8, 8), brick=1), dict(dims=(8, 8, 8), brick=512),
     dict(dims=(8, 8, 8), levels=0), dict(dims=(8, 8, 8), levels=17),
-    dict(dims=(8, 8, 8), device=-1)])
+    dict(dims=(8, 8, 8), device=-1), dict(dims=(8, 8, 8), layout=2),
+    dict(dims=(8, 8, 8), layout=-1)])
 def test_create_rejects_bad_descriptions_without_a_device(sg, kw):
     with pytest.raises(sg.SgError) as ex:
         sg.sg_volume_create(**kw)

@@ -44,12 +44,13 @@ def views():
             gen.view(gen.look_at(c + np.array([10.0, -9.0, 6.0]), c), 40, 64, 0.8)]
 
 
-def make_cache(vols, slots, tf, timepoints=1):
+def make_cache(vols, slots, tf, timepoints=1, layout=0):
     from paper_1804_08197_amd import sg
     from paper_1804_08197_amd.container import BrickSource
     nz, ny, nx = vols[0][0].shape
     h = sg.sg_volume_create((nx, ny, nz), channels=len(vols[0]), timepoints=timepoints,
-                            dtype=sg.SG_U16, brick=B, levels=LEVELS, cache_slots=slots)
+                            dtype=sg.SG_U16, brick=B, levels=LEVELS, cache_slots=slots,
+                            layout=layout)
     src = BrickSource(h, B, LEVELS)
     for t in range(timepoints):
         for c, v in enumerate(vols[t]):
@@ -120,11 +121,15 @@ def test_residency_cut_requests_and_render_match_the_oracle(data):
         sg.sg_volume_destroy(h)
 
 
-def test_serving_requests_converges_to_the_all_resident_image(data):
+@pytest.mark.parametrize("layout", [0, 1], ids=["linear", "microblock"])
+def test_serving_requests_converges_to_the_all_resident_image(data, layout):
+    """Served into a cache of either slot layout (sg_cache_put writes the
+    stored regions into the slots in that layout), the image converges to
+    the all-resident linear volume's, bit for bit."""
     from paper_1804_08197_amd import sg
     vol, tf = data
     full = make_full([vol], tf)
-    h, src = make_cache([[vol]], 4000, tf)
+    h, src = make_cache([[vol]], 4000, tf, layout=layout)
     try:
         src.put_top(0)
         vs = views()

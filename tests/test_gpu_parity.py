@@ -1,7 +1,9 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle.
 
 RGBA within 1e-4 per pixel (with the early-termination bracket), LOD cuts
-and empty flags bit-exact, skip / stereo / repeat invariants bit-identical.
+and empty flags bit-exact, skip / stereo / repeat invariants bit-identical,
+and the two pool slot layouts (linear rows, 4^3 micro-blocks) render the
+same images bit for bit.
 """
 import math
 import sys
@@ -10,8 +12,8 @@ import numpy as np
 import pytest
 
 import gen
-from tests.helpers import (ERT, TOL, bracket_error, gpu_volume, oracle_bracket, oracle_scene,
-                           render_gpu)
+from tests.helpers import (ERT, LAYOUT_IDS, LAYOUTS, TOL, bracket_error, gpu_volume,
+                           oracle_bracket, oracle_scene, render_gpu)
 
 pytestmark = pytest.mark.gpu
 
@@ -81,19 +83,21 @@ def test_blobs128_full_image_parity(brick, levels):
 
 
 # ------------------------------------------------------ bricked LOD parity
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
 @pytest.mark.parametrize("dtype,shape,brick,levels,seed", [
     (np.uint16, (29, 38, 45), 8, 4, 1),
     (np.uint8, (40, 40, 40), 16, 3, 2),
     (np.uint16, (17, 50, 33), 4, 5, 3),
 ])
-def test_bricked_lod_parity(dtype, shape, brick, levels, seed):
-    log("bricked parity %s %s brick=%d levels=%d" % (np.dtype(dtype).name, shape, brick, levels))
+def test_bricked_lod_parity(dtype, shape, brick, levels, seed, layout):
+    log("bricked parity %s %s brick=%d levels=%d layout=%d" % (
+        np.dtype(dtype).name, shape, brick, levels, layout))
     from paper_1804_08197_amd import sg
     vol = gen.random_volume(shape, seed, dtype=dtype)
     vmax = 255 if dtype == np.uint8 else 65535
     tf = gen.tf_hot(a_start=60)
     tf[:, 3] *= 4.0
-    h = gpu_volume([vol], brick, levels, [tf], [(0, vmax)])
+    h = gpu_volume([vol], brick, levels, [tf], [(0, vmax)], layout=layout)
     try:
         sc = oracle_scene([vol], brick, levels, [tf], [(0, vmax)])
         c = np.array(shape[::-1]) / 2.0
@@ -202,13 +206,14 @@ def test_constant_medium_closed_form_on_gpu():
         sg.sg_volume_destroy(h)
 
 
-def test_multichannel_parity():
-    log("multichannel parity")
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+def test_multichannel_parity(layout):
+    log("multichannel parity layout=%d" % layout)
     from paper_1804_08197_amd import sg
     chans = [gen.random_volume((36, 40, 44), 20 + c, dtype=np.uint16) for c in range(3)]
     tfs = [gen.tf_tint(t, a_start=50, a_max=0.4) for t in gen.CELL_TINTS]
     doms = [(0, 65535)] * 3
-    h = gpu_volume(chans, 8, 3, tfs, doms)
+    h = gpu_volume(chans, 8, 3, tfs, doms, layout=layout)
     try:
         sc = oracle_scene(chans, 8, 3, tfs, doms)
         views = gen.stereo((-40.0, 90.0, 60.0), (22, 20, 18), 5.0, 45, 39, 0.5, 0.55)
@@ -286,20 +291,22 @@ def test_error_paths_on_gpu():
         sg.sg_volume_destroy(h)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
 @pytest.mark.parametrize("dtype,shape,brick,levels,chans", [
     (np.uint16, (29, 38, 45), 8, 4, 1), (np.uint8, (40, 40, 40), 16, 3, 1),
     (np.uint8, (17, 50, 33), 2, 5, 1), (np.uint16, (36, 40, 44), 8, 3, 3),
     (np.uint8, (70, 66, 90), 32, 3, 2)])
-def test_staged_and_gather_kernels_bit_identical(dtype, shape, brick, levels, chans):
+def test_staged_and_gather_kernels_bit_identical(dtype, shape, brick, levels, chans, layout):
     """The LDS-staged kernel and the direct-gather kernel share every sample
     computation, so their images (and sample counts) must agree exactly."""
-    log("staged vs gather %s %s brick=%d ch=%d" % (np.dtype(dtype).name, shape, brick, chans))
+    log("staged vs gather %s %s brick=%d ch=%d layout=%d" % (
+        np.dtype(dtype).name, shape, brick, chans, layout))
     from paper_1804_08197_amd import sg
     vols = [gen.random_volume(shape, 50 + c, dtype=dtype) for c in range(chans)]
     vmax = 255 if dtype == np.uint8 else 65535
     tfs = [gen.tf_hot(a_start=40)] if chans == 1 else \
         [gen.tf_tint(t, a_start=40, a_max=0.5) for t in gen.CELL_TINTS[:chans]]
-    h = gpu_volume(vols, brick, levels, tfs, [(0, vmax)] * chans)
+    h = gpu_volume(vols, brick, levels, tfs, [(0, vmax)] * chans, layout=layout)
     try:
         c = np.array(shape[::-1]) / 2.0
         views = gen.orbit_views(c, (15, 150), 4, 7, 77, 45, tan_top=0.7)
@@ -318,3 +325,48 @@ def test_staged_and_gather_kernels_bit_identical(dtype, shape, brick, levels, ch
                     assert a["stats"][key] == b["stats"][key]
     finally:
         sg.sg_volume_destroy(h)
+
+
+@pytest.mark.parametrize("dtype,shape,brick,levels,chans", [
+    (np.uint16, (29, 38, 45), 8, 4, 1), (np.uint8, (40, 40, 40), 16, 3, 1),
+    (np.uint8, (17, 50, 33), 2, 5, 1), (np.uint16, (36, 40, 44), 4, 3, 3),
+    (np.uint16, (70, 66, 90), 32, 3, 2), (np.uint8, (60, 70, 130), 128, 1, 1)])
+def test_microblock_slots_render_the_linear_images(dtype, shape, brick, levels, chans):
+    """The same data in linear and in micro-block slots (every brick edge,
+    so stored edges of 4 to 130 voxels: multiples of 4 and not), rendered
+    by both kernels under every optical model, with LOD, depth and sample
+    counts: the images are equal bit for bit. Pins the slot addressing of
+    the uploads, the pyramid, the aprons, the staging copies and the pool
+    reads of the micro-block layout to the linear one."""
+    log("layouts %s %s brick=%d ch=%d" % (np.dtype(dtype).name, shape, brick, chans))
+    from paper_1804_08197_amd import sg
+    vols = [gen.random_volume(shape, 90 + c, dtype=dtype) for c in range(chans)]
+    vmax = 255 if dtype == np.uint8 else 65535
+    tfs = [gen.tf_hot(a_start=40)] if chans == 1 else \
+        [gen.tf_tint(t, a_start=40, a_max=0.5) for t in gen.CELL_TINTS[:chans]]
+    hl = gpu_volume(vols, brick, levels, tfs, [(0, vmax)] * chans, layout=sg.SG_LAYOUT_LINEAR)
+    hm = gpu_volume(vols, brick, levels, tfs, [(0, vmax)] * chans,
+                    layout=sg.SG_LAYOUT_MICROBLOCK)
+    try:
+        c = np.array(shape[::-1]) / 2.0
+        views = gen.orbit_views(c, (15, 150), 3, 11, 69, 41, tan_top=0.7)
+        views.append(gen.view(gen.look_at(c, c + (3, 7, -2)), 64, 64, 1.2))  # inside
+        for model in ("ea", "eo", "mip"):
+            for gather in (0, 1):
+                p = {"ert": ERT, "tau": 1.5, "model": model, "gather": gather}
+                a = render_gpu(hl, views, p, depth=True, samples=True)
+                b = render_gpu(hm, views, p, depth=True, samples=True)
+                for i in range(len(views)):
+                    assert np.array_equal(a["rgba"][i], b["rgba"][i]), (model, gather, i)
+                    assert np.array_equal(a["depth"][i], b["depth"][i], equal_nan=True)
+                    assert np.array_equal(a["nsamp"][i], b["nsamp"][i])
+                for key in ("total_samples", "microblocks", "node_visits"):
+                    assert a["stats"][key] == b["stats"][key], key
+        for v in views[:2]:
+            for L in range(levels):
+                p = {"lod": 0, "bias": L}
+                assert all(np.array_equal(x, y) for x, y in zip(sg.sg_get_lod_cut(hl, v, p),
+                                                                 sg.sg_get_lod_cut(hm, v, p)))
+    finally:
+        sg.sg_volume_destroy(hl)
+        sg.sg_volume_destroy(hm)

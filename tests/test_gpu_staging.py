@@ -7,12 +7,15 @@ from inside the volume), and a slab whose single layer does not fit the
 staging space (rays many voxels apart, 1 KiB of staging). The render
 statistics show each path was taken; the images match the oracle within
 1e-4 (with the early-termination bracket) and equal the gather kernel's
-bit for bit. Retries of the slab size show up on an ordinary view."""
+bit for bit. Retries of the slab size show up on an ordinary view. Every
+case runs on both pool slot layouts (linear rows and 4^3 micro-blocks),
+whose staging copies and pool reads address the slots differently."""
 import numpy as np
 import pytest
 
 import gen
-from tests.helpers import ERT, TOL, bracket_error, gpu_volume, oracle_bracket, oracle_scene
+from tests.helpers import (ERT, LAYOUT_IDS, LAYOUTS, TOL, bracket_error, gpu_volume,
+                           oracle_bracket, oracle_scene)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,11 +43,12 @@ def _check(h, sc, views, params):
     return st
 
 
-def test_rays_without_a_shared_direction_read_the_pool():
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+def test_rays_without_a_shared_direction_read_the_pool(layout):
     from paper_1804_08197_amd import sg
     vol = gen.random_volume((36, 40, 44), 21, dtype=np.uint16)
     tf = gen.tf_hot(a_start=30)
-    h = gpu_volume([vol], 16, 2, [tf], [(0, 65535)])
+    h = gpu_volume([vol], 16, 2, [tf], [(0, 65535)], layout=layout)
     try:
         sc = oracle_scene([vol], 16, 2, [tf], [(0, 65535)])
         c = np.array([22.0, 20.0, 18.0])
@@ -59,11 +63,12 @@ def test_rays_without_a_shared_direction_read_the_pool():
         sg.sg_volume_destroy(h)
 
 
-def test_slab_wider_than_the_staging_space_reads_the_pool():
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+def test_slab_wider_than_the_staging_space_reads_the_pool(layout):
     from paper_1804_08197_amd import sg
     vol = gen.random_volume((100, 120, 140), 22, dtype=np.uint16)
     tf = gen.tf_hot(a_start=30)
-    h = gpu_volume([vol], 64, 1, [tf], [(0, 65535)])
+    h = gpu_volume([vol], 64, 1, [tf], [(0, 65535)], layout=layout)
     try:
         sg.sg_set_launch_config(h, {"kernel": 0, "tile": 16, "block": 64, "stage_bytes": 1024,
                                     "persistent": 0})
@@ -79,11 +84,12 @@ def test_slab_wider_than_the_staging_space_reads_the_pool():
         sg.sg_volume_destroy(h)
 
 
-def test_ordinary_view_stages_everything_and_retries_slab_sizes():
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+def test_ordinary_view_stages_everything_and_retries_slab_sizes(layout):
     from paper_1804_08197_amd import sg
     vol = gen.random_volume((48, 56, 64), 23, dtype=np.uint16)
     tf = gen.tf_hot(a_start=30)
-    h = gpu_volume([vol], 32, 2, [tf], [(0, 65535)])
+    h = gpu_volume([vol], 32, 2, [tf], [(0, 65535)], layout=layout)
     try:
         sg.sg_set_launch_config(h, {"kernel": 0, "tile": 16, "block": 64, "stage_bytes": 8192,
                                     "persistent": 0})
@@ -97,7 +103,8 @@ def test_ordinary_view_stages_everything_and_retries_slab_sizes():
         sg.sg_volume_destroy(h)
 
 
-def test_rows_wider_than_a_copy_pass_are_staged_chunk_by_chunk():
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+def test_rows_wider_than_a_copy_pass_are_staged_chunk_by_chunk(layout):
     """uint16 bricks of 128 voxels: a region row can hold more than 64
     4-byte chunks (one copy pass), which the staging copies chunk by chunk.
     One-wave 8x8 views down z, 80-120 voxels above the volume, wide across
@@ -109,7 +116,7 @@ def test_rows_wider_than_a_copy_pass_are_staged_chunk_by_chunk():
     from paper_1804_08197_amd import sg
     vol = gen.random_volume((40, 140, 130), 29, dtype=np.uint16)  # z, y, x
     tf = gen.tf_hot(a_start=30)
-    h = gpu_volume([vol], 128, 1, [tf], [(0, 65535)])
+    h = gpu_volume([vol], 128, 1, [tf], [(0, 65535)], layout=layout)
     try:
         sg.sg_set_launch_config(h, {"kernel": 0, "tile": 16, "block": 32, "stage_bytes": 8192,
                                     "persistent": 0})
