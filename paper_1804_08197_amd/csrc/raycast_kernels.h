@@ -1398,27 +1398,28 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           const int lim = rr < R ? rows - rr : 0;  // the lane's rows: r0 + rr < rows
           if (MB) {
             // micro-block slots: the lane's chunk (two u16 or four u8 voxels
-            // from an even x) lies in one block row; its offset is formed
-            // from the row's y and z at each pass
+            // from an even x) lies in one block row; its byte offset is
+            // formed from the row's y and z at each pass, with 24-bit
+            // multiply-adds (block strides below 2^24 bytes: M <= 65)
+            constexpr int vb = (int)sizeof(T);
             const int x = o[0] + col * align;
-            const int xo = ((x >> 2) << 6) + (x & 3);
-            const int M = a.M, yend = o[1] + wy;
+            const int xo = (((x >> 2) << 6) + (x & 3)) * vb;
+            const int zs = 64 * a.M * a.M * vb, ys = 64 * a.M * vb, yend = o[1] + wy;
             int y = o[1] + yy, z = o[2] + pz;
             for (int r0 = 0; r0 < rows; r0 += R) {
               if (r0 < lim) {
-                const int e = ((((z >> 2) * M + (y >> 2)) * M) << 6) + ((z & 3) << 4) +
-                              ((y & 3) << 2) + xo;
+                const int in = (((z & 3) << 2) + (y & 3)) * (4 * vb);  // inside the block
+                const uint32_t e = __umul24(z >> 2, zs) + __umul24(y >> 2, ys) + xo + in;
 #pragma unroll
                 for (int ch = 0; ch < CH; ++ch)
                   __builtin_amdgcn_global_load_lds(
-                      reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)(e * (int)sizeof(T)),
+                      reinterpret_cast<const uint8_t*>(slot[ch]) + e,
                       reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
               }
               y += dy;
-              z += dz;
               const bool c = y >= yend;
-              y -= c ? wy : 0;
-              z += c ? 1 : 0;
+              y = c ? y - wy : y;
+              z += dz + (c ? 1 : 0);
             }
           } else {
             for (int r0 = 0; r0 < rows; r0 += R) {
