@@ -183,7 +183,7 @@ def main():
     elif not args.no_autotune:
         # set-up, untimed: pick the launch configuration on this frame (every
         # configuration renders the same image)
-        launch, tuned_ms = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+        launch, tuned_ms = sg.sg_autotune(h, views, PARAMS, outs, repeats=5)
         log("autotuned launch %s (%.3f ms)" % (launch, tuned_ms))
 
     if args.render_only:
@@ -509,7 +509,7 @@ def run_cells(args, want_cpu):
         launch = dict(zip(sg.LAUNCH_FIELDS, (int(x) for x in args.launch.split(","))))
         sg.sg_set_launch_config(h, launch)
     else:
-        launch, _ = sg.sg_autotune(h, views, params, outs, repeats=2)
+        launch, _ = sg.sg_autotune(h, views, params, outs, repeats=5)
     if args.render_only:
         for _ in range(args.warmup):
             sg.sg_render_views(h, views, params, outs)
@@ -723,7 +723,7 @@ def run_upsampler(args):
     # frame serves both paths (every configuration renders the same image)
     launch, _ = sg.sg_autotune(h, gen.orbit_views(center, radius, 1, 4005, W, H, tan_t,
                                                   stereo_ipd=sc["ipd"])[0], p_full, list(plain),
-                               repeats=2)
+                               repeats=5)
     log("launch configuration: %s" % launch)
     # the upsampler path's own launches (set-up, untimed; images are the
     # same under every launch): the half-resolution render tuned on its own
@@ -733,7 +733,7 @@ def run_upsampler(args):
     # queues, one more launch)
     hv = gen.orbit_views(center, radius, 1, 4005, W, H, tan_t, stereo_ipd=sc["ipd"])[0]
     launch_half, _ = sg.sg_autotune(h, path._half_views(hv), path.p_half, list(path.rgba_lo),
-                                    repeats=2)
+                                    repeats=5)
     launch_full = dict(launch, tile=32, block=max(32, launch["block"]), persistent=0)
     log("launch configuration: half %s, gated full %s" % (launch_half, launch_full))
     path.launch_half, path.launch_full = launch_half, launch_full
@@ -929,7 +929,7 @@ def run_hmd(h, views, launch, args):
     outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
     depth = [torch.empty(v["height"], v["width"], device="cuda") for v in views]
     if launch is None:
-        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=5)
     else:
         sg.sg_set_launch_config(h, launch)
     # the synthetic depth buffer: distance along each pixel's ray to a plane
@@ -1014,7 +1014,7 @@ def run_octants(h, views, launch, args):
     dims = gen.TUBES_DIMS
     if launch is None:
         outs = [torch.empty(v["height"], v["width"], 4, device="cuda") for v in views]
-        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=2)
+        launch, _ = sg.sg_autotune(h, views, PARAMS, outs, repeats=5)
         del outs
     else:
         sg.sg_set_launch_config(h, launch)
