@@ -120,6 +120,7 @@ void fill_args(const Volume* v, const sg_render_params* params, int n_views,
   a.pool = v->pool;
   a.slot_bytes = v->slot_bytes;
   a.M = v->M;
+  a.Bf = (float)v->B;
   a.page = v->page + (int64_t)params->timepoint * C * v->nodes;
   a.empty = v->empty + (int64_t)params->timepoint * v->nodes;
   a.range = v->range + (int64_t)params->timepoint * C * v->nodes * 2;

@@ -103,11 +103,20 @@ __device__ __forceinline__ float trilinear(P p0, int sy, int sz, float fx, float
   return lerpf(c0, c1, fz);
 }
 
+// Stencil corner index of a brick-local position along one axis, clamped to
+// [0, B] (bf = B) for reads of the pool. Clamping the position first (one
+// median) gives the same index as clamping the truncated one: a position
+// in (-1, 0) truncates to 0 either way, and every finite position gives
+// min(max(trunc(q), 0), B).
+__device__ __forceinline__ int clamp_index(float q, float bf) {
+  return (int)__builtin_amdgcn_fmed3f(q, 0.0f, bf);
+}
+
 // Offset of stored voxel (x, y, z) in a micro-block slot with M blocks per
 // edge (slot_index for M > 0, in 32 bits: slots hold fewer than 2^31 voxels).
 __device__ __forceinline__ int mb_index(int x, int y, int z, int M) {
-  return ((((z >> 2) * M + (y >> 2)) * M + (x >> 2)) << 6) + ((z & 3) << 4) + ((y & 3) << 2) +
-         (x & 3);
+  return ((__umul24(__umul24(z >> 2, M) + (y >> 2), M) + (x >> 2)) << 6) + ((z & 3) << 4) +
+         ((y & 3) << 2) + (x & 3);
 }
 // The steps from a voxel to its +x, +y and +z neighbours in a micro-block
 // slot: inside the voxel's block, or across into the next block.
@@ -533,9 +542,9 @@ __device__ __forceinline__ Shade shade_ea(const Ray& r, const RenderArgs& a, con
   // [0, B]; reads from the pool clamp it anyway to guard memory safety
   // (LDS reads need no guard: out-of-range LDS addresses cannot fault and
   // the staged region is proven to contain every staged stencil).
-  const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
-  const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
-  const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
+  const int ix = CLAMP ? clamp_index(qx, a.Bf) : (int)qx;
+  const int iy = CLAMP ? clamp_index(qy, a.Bf) : (int)qy;
+  const int iz = CLAMP ? clamp_index(qz, a.Bf) : (int)qz;
   // q >= 0, so fract(q) = q - floor(q) = q - ix (exact)
   const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
               fz = __builtin_amdgcn_fractf(qz);
@@ -620,9 +629,9 @@ __device__ __forceinline__ bool sample_step(Ray& r, const RenderArgs& a, const f
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
-  const int ix = CLAMP ? min(max((int)qx, 0), a.B) : (int)qx;
-  const int iy = CLAMP ? min(max((int)qy, 0), a.B) : (int)qy;
-  const int iz = CLAMP ? min(max((int)qz, 0), a.B) : (int)qz;
+  const int ix = CLAMP ? clamp_index(qx, a.Bf) : (int)qx;
+  const int iy = CLAMP ? clamp_index(qy, a.Bf) : (int)qy;
+  const int iz = CLAMP ? clamp_index(qz, a.Bf) : (int)qz;
   const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy),
               fz = __builtin_amdgcn_fractf(qz);
   float er = 0.f, eg = 0.f, eb = 0.f;
@@ -859,9 +868,9 @@ __device__ __forceinline__ Stencil stencil_at(const Ray& r, const RenderArgs& a,
   const float qx = fmaf(tau, r.dq[0], r.q0[0]);
   const float qy = fmaf(tau, r.dq[1], r.q0[1]);
   const float qz = fmaf(tau, r.dq[2], r.q0[2]);
-  const int ix = min(max((int)qx, 0), a.B);
-  const int iy = min(max((int)qy, 0), a.B);
-  const int iz = min(max((int)qz, 0), a.B);
+  const int ix = clamp_index(qx, a.Bf);
+  const int iy = clamp_index(qy, a.Bf);
+  const int iz = clamp_index(qz, a.Bf);
   Stencil st;
   st.fx = __builtin_amdgcn_fractf(qx);
   st.fy = __builtin_amdgcn_fractf(qy);
@@ -879,7 +888,9 @@ __device__ __forceinline__ Stencil stencil_at(const Ray& r, const RenderArgs& a,
     st.v[7] = p0[d.dz + d.dy + d.dx];
     return st;
   }
-  const T* p0 = slot + (iz * a.S + iy) * a.Sx + ix;
+  // (an unsigned 32-bit element offset from 24-bit products: stored
+  // indices and edges are below 2^9)
+  const T* p0 = slot + (uint32_t)(__umul24(__umul24(iz, a.S) + iy, a.Sx) + ix);
   const int sy = a.Sx, sz = a.S * a.Sx;
   st.v[0] = p0[0];
   st.v[1] = p0[1];

@@ -320,6 +320,7 @@ struct RenderArgs {
   uint32_t frame;
   int32_t B, S, Sx;     // brick core edge, stored edge, row stride (voxels)
   int32_t M;            // micro-blocks per slot edge, 0 for linear slots
+  float Bf;             // B as a float (stencil index clamps)
   int32_t skip_empty;
   int32_t gather;       // 1: stencils read the pool directly (no LDS staging)
   int32_t stage_bytes;  // LDS staging bytes per wave
