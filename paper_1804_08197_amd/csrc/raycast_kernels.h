@@ -912,18 +912,8 @@ __device__ __forceinline__ float stencil_value(const Stencil& st) {
   const float c1 = lerpf(c01, c11, st.fy);
   return lerpf(c0, c1, st.fz);
 }
-// A full step of one channel (emission-absorption) from a loaded stencil:
-// sample_step's full step.
-template <bool DEPTH>
-__device__ __forceinline__ bool stencil_step(Ray& r, const RenderArgs& a, const float4* s_tf,
-                                             const TfWin<1>& w, const Stencil& st) {
-  const float4 c = tf_lookup(a, s_tf, 0, stencil_value(st), w.scale[0], w.bias[0]);
-  const float tau = r.tau;
-  r.k += 1;
-  r.tau += r.Df;
-  return composite_ea<DEPTH>(r, a, Shade{c.w, c.x, c.y, c.z}, r.Df * kNegLog2e, tau);
-}
-
+// A full step of one channel (emission-absorption) from its table entry c:
+// sample_step's full step after the lookup.
 template <bool DEPTH>
 __device__ __forceinline__ bool shade_step(Ray& r, const RenderArgs& a, const float4& c) {
   const float tau = r.tau;
@@ -933,14 +923,15 @@ __device__ __forceinline__ bool shade_step(Ray& r, const RenderArgs& a, const fl
 }
 
 // The gather kernel's samples of the current segment for one channel under
-// emission-absorption: sample_run's samples, with the stencil of each full
-// step's next sample loaded while the current one is shaded, so that a ray
-// waits for memory about once per sample rather than twice (the rays of a
-// sparse frame are few, and a frame then lasts as long as its longest
-// chain of dependent reads). The loads are issued at the top of the loop
-// body and pinned there (no instruction moves across the scheduling
-// barrier); the last full step loads its own stencil again instead of the
-// partial step's.
+// emission-absorption: sample_run's samples, two full steps per iteration,
+// with the stencils of the next two loaded while the current two are
+// shaded, so that a ray waits for memory about once per two samples (the
+// rays of a sparse frame are few, and a frame then lasts as long as its
+// longest chain of dependent samples). The loads are issued at the top of
+// the loop body and pinned there, and the loop-carried stencils copied at
+// its end (no instruction moves across the scheduling barriers); a stencil
+// past the last full step repeats the last full step's instead of reading
+// the partial step's.
 template <typename T, bool DEPTH, bool MB, typename F>
 __device__ __forceinline__ void gather_run(Ray& r, const RenderArgs& a, const float4* s_tf,
                                            const T* slot, F&& fetch, int (*mb_key)[3]) {
