@@ -1127,20 +1127,21 @@ __device__ __forceinline__ int quot(int x, int d) {
   return (int)(((float)x + 0.5f) * __builtin_amdgcn_rcpf((float)d));
 }
 
-// Main-axis stencil layer of sample k (same arithmetic as the sample).
-__device__ __forceinline__ int sample_layer(const Ray& r, int k, float dqm, float qm0, int B) {
-  return min(max((int)fmaf(sample_tau(r, k), dqm, qm0), 0), B);
+// Main-axis stencil layer of sample k (same arithmetic as the sample),
+// clamped to [0, B] (bf = B).
+__device__ __forceinline__ int sample_layer(const Ray& r, int k, float dqm, float qm0, float bf) {
+  return clamp_index(fmaf(sample_tau(r, k), dqm, qm0), bf);
 }
 
 // Stencil corner bounds (per axis; the stencil also reads corner + 1) of
 // samples ka and kb of the lane's segment, hence of every sample between.
-__device__ __forceinline__ void stencil_bounds(const Ray& r, int ka, int kb, int B, int lo[3],
+__device__ __forceinline__ void stencil_bounds(const Ray& r, int ka, int kb, float bf, int lo[3],
                                                int hi[3]) {
   const float ta = sample_tau(r, ka), tb = sample_tau(r, kb);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const int ia = min(max((int)fmaf(ta, r.dq[i], r.q0[i]), 0), B);
-    const int ib = min(max((int)fmaf(tb, r.dq[i], r.q0[i]), 0), B);
+    const int ia = clamp_index(fmaf(ta, r.dq[i], r.q0[i]), bf);
+    const int ib = clamp_index(fmaf(tb, r.dq[i], r.q0[i]), bf);
     lo[i] = min(ia, ib);
     hi[i] = max(ia, ib);
   }
@@ -1265,7 +1266,7 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
     const bool more0 = mine && r.alive && r.k < r.n;
     int j;
     {
-      const int my_im = more0 ? sample_layer(r, r.k, my_dqm, my_qm0, B) : (sgn > 0 ? big : -1);
+      const int my_im = more0 ? sample_layer(r, r.k, my_dqm, my_qm0, a.Bf) : (sgn > 0 ? big : -1);
       j = uniform(sgn > 0 ? wave_min_i(my_im) : wave_max_i(my_im));
     }
     int D = 8;
@@ -1299,18 +1300,18 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           kb = (int)ceilf(tlim * __builtin_amdgcn_rcpf(r.Df) - 0.5f) - 1;
           kb = min(max(kb, r.k - 1), r.n - 1);
           while (kb + 1 < r.n) {
-            const int im = sample_layer(r, kb + 1, my_dqm, my_qm0, B);
+            const int im = sample_layer(r, kb + 1, my_dqm, my_qm0, a.Bf);
             if (im < jl || im > jh) break;
             ++kb;
           }
           while (kb >= r.k) {
-            const int im = sample_layer(r, kb, my_dqm, my_qm0, B);
+            const int im = sample_layer(r, kb, my_dqm, my_qm0, a.Bf);
             if (im >= jl && im <= jh) break;
             --kb;
           }
           if (kb >= r.k) {
             int lo3[3], hi3[3];
-            stencil_bounds(r, r.k, kb, B, lo3, hi3);
+            stencil_bounds(r, r.k, kb, a.Bf, lo3, hi3);
             const int ua = m == 0 ? 1 : 0, ub = m == 2 ? 1 : 2;  // cross axes
             plo = (uint32_t)pick(lo3, ua) | ((uint32_t)pick(lo3, ub) << 16);
             phi = (uint32_t)(0xFFFF - pick(hi3, ua)) | ((uint32_t)(0xFFFF - pick(hi3, ub)) << 16);

@@ -119,6 +119,44 @@ def test_persistent_grid_parity_on_sampled_pixels(blobs):
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
+def test_graph_replays_on_microblock_slots(persistent):
+    """A render graph over a volume with micro-block slots replays the eager
+    render of the same volume, and that of the same data in linear slots."""
+    import torch
+
+    from paper_1804_08197_amd import sg
+    vol = gen.random_volume((44, 52, 60), 123, dtype=np.uint16)
+    tf = gen.tf_hot(a_start=30)
+    hl = gpu_volume([vol], 16, 3, [tf], [(0, 65535)], layout=sg.SG_LAYOUT_LINEAR)
+    hm = gpu_volume([vol], 16, 3, [tf], [(0, 65535)], layout=sg.SG_LAYOUT_MICROBLOCK)
+    try:
+        c = np.array([30.0, 26.0, 22.0])
+        views = gen.stereo(c + np.array([-80.0, 50.0, 40.0]), c, 6.0, 72, 64, 0.55, 0.5)
+        params = {"ert": ERT, "tau": 1.0}
+        for h in (hl, hm):
+            sg.sg_set_launch_config(h, dict(kernel=0, tile=16, block=32, stage_bytes=8192,
+                                            persistent=persistent))
+        ref = render(hl, views, params)
+        outs = [torch.zeros(v["height"], v["width"], 4, device="cuda") for v in views]
+        g = sg.RenderGraph(hm, views, params, outs)
+        try:
+            for rep in range(3):
+                for o in outs:
+                    o.fill_(float("nan"))
+                g.launch()
+                torch.cuda.synchronize()
+                eager = render(hm, views, params)
+                for a, b, e in zip(ref, outs, eager):
+                    assert torch.equal(a, b), rep
+                    assert torch.equal(a, e), rep
+        finally:
+            g.destroy()
+    finally:
+        sg.sg_volume_destroy(hl)
+        sg.sg_volume_destroy(hm)
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
 def test_graph_replays_equal_eager_renders(blobs, persistent):
     import torch
 

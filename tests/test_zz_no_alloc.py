@@ -22,13 +22,14 @@ def _render(fn, h, views, params):
     return [o.cpu().numpy() for o in out], [d.cpu().numpy() for d in dep]
 
 
-def _case(shape, dtype, brick, levels, views, seed, launch=None):
+def _case(shape, dtype, brick, levels, views, seed, launch=None, layout=0):
     from paper_1804_08197_amd import sg
-    print("noalloc case", shape, dtype.__name__, brick, levels, len(views), launch, flush=True)
+    print("noalloc case", shape, dtype.__name__, brick, levels, len(views), launch, layout,
+          flush=True)
     vol = gen.random_volume(shape, seed, dtype=dtype)
     dom = (0, 255) if dtype == np.uint8 else (0, 65535)
     tf = gen.tf_hot(a_start=30)
-    h = gpu_volume([vol], brick, levels, [tf], [dom])
+    h = gpu_volume([vol], brick, levels, [tf], [dom], layout=layout)
     try:
         if launch is not None:
             sg.sg_set_launch_config(h, launch)
@@ -45,17 +46,18 @@ def _case(shape, dtype, brick, levels, views, seed, launch=None):
         sg.sg_volume_destroy(h)
 
 
+@pytest.mark.parametrize("layout", [0, 1], ids=["linear", "microblock"])
 @pytest.mark.parametrize("launch", [None, {"kernel": 0, "tile": 8, "block": 32,
                                            "stage_bytes": 8192, "persistent": 1}])
-def test_noalloc_render_equals_sg_render_views_twice(launch):
+def test_noalloc_render_equals_sg_render_views_twice(launch, layout):
     big = (40, 48, 56)  # z, y, x
     c = np.array([28.0, 24.0, 20.0])
     stereo = gen.stereo(c + np.array([-70.0, 45.0, 35.0]), c, 6.0, 96, 80, 0.55, 0.5)
-    _case(big, np.uint16, 8, 3, stereo, 11, launch)
+    _case(big, np.uint16, 8, 3, stereo, 11, launch, layout)
     small = (22, 26, 30)
     c2 = np.array([15.0, 13.0, 11.0])
     mono = [gen.view(gen.look_at(c2 + np.array([30.0, -25.0, 20.0]), c2), 40, 30, 0.6)]
-    _case(small, np.uint8, 4, 2, mono, 12, launch)
+    _case(small, np.uint8, 4, 2, mono, 12, launch, layout)
 
 
 def test_noalloc_render_rejects_what_it_cannot_hold():
