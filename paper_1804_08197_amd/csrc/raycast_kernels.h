@@ -1382,61 +1382,38 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
                     inv_wy = __builtin_amdgcn_rcpf((float)wy);
         constexpr int cb = kRowAlignBytes;
         if (cpr <= 64) {
-          // a pass moves R = 64 / cpr whole rows: lane rr * cpr + c takes
-          // chunk c of row rr of the pass (lanes past R * cpr rest). Each
-          // lane keeps the byte offset in the slot of its chunk and its
-          // row's position within its plane, and steps both by R rows per
-          // pass (dz planes and dy rows, with one carry)
-          const int R = uniform((int)(64.5f * inv_cpr));
-          const int dz = uniform((int)(((float)R + 0.5f) * inv_wy)), dy = R - dz * wy;
-          const int rr = (int)(((float)lane + 0.5f) * inv_cpr), col = lane - rr * cpr;
-          const int pz = (int)(((float)rr + 0.5f) * inv_wy);
-          int yy = rr - pz * wy;
-          int gb = ((((o[2] + pz) * S + o[1] + yy) * Sx + o[0]) / align + col) * cb;
-          // slot bytes per pass, without and with the carry into the next plane
-          int step = (dz * S + dy) * P * cb, step_c = step + (S - wy) * P * cb;
-          // as they are (one select per pass, no factoring of the common
-          // multiplier into the loop)
-          asm volatile("" : "+v"(step), "+v"(step_c));
-          const int lim = rr < R ? rows - rr : 0;  // the lane's rows: r0 + rr < rows
-          if (MB) {
-            // micro-block slots: the lane's chunk (two u16 or four u8 voxels
-            // from an even x) lies in one block row; its byte offset is
-            // formed from the row's y and z at each pass, with 24-bit
-            // multiply-adds (block strides below 2^24 bytes: M <= 65)
-            constexpr int vb = (int)sizeof(T);
-            const int x = o[0] + col * align;
-            const int xo = (((x >> 2) << 6) + (x & 3)) * vb;
-            const int zs = 64 * a.M * a.M * vb, ys = 64 * a.M * vb, yend = o[1] + wy;
-            int y = o[1] + yy, z = o[2] + pz;
-            for (int r0 = 0; r0 < rows; r0 += R) {
-              if (r0 < lim) {
-                const int in = (((z & 3) << 2) + (y & 3)) * (4 * vb);  // inside the block
-                const uint32_t e = __umul24(z >> 2, zs) + __umul24(y >> 2, ys) + xo + in;
+          // a lane keeps chunk i = s0 + lane of a region plane (row i / cpr,
+          // column i % cpr) and a sub-pass walks the planes. A chunk's
+          // offset in the slot is the sum of a part from its (x, y) and a
+          // part from its plane z, the same for every lane and kept in
+          // scalar registers: no per-lane work per load. In a micro-block
+          // slot the chunk (two u16 or four u8 voxels from an even x) lies
+          // in one block row, and the plane part steps by a block plane
+          // every fourth plane.
+          constexpr int vb = (int)sizeof(T), zin = 16 * vb;
+          const int Q = cpr * wy;  // chunks per plane
+          const int zs = MB ? 64 * a.M * a.M * vb : S * Sx * vb, zjump = zs - 3 * zin;
+          const int nz = wd[2];
+          const int h0 = MB ? (o[2] >> 2) * zs + (o[2] & 3) * zin : o[2] * zs;
+          for (int s0 = 0; s0 < Q; s0 += 64) {
+            const int i = s0 + lane;
+            if (i < Q) {
+              const int ry = (int)(((float)i + 0.5f) * inv_cpr);
+              const int x = o[0] + (i - ry * cpr) * align, y = o[1] + ry;
+              const uint32_t c =
+                  MB ? (uint32_t)((((x >> 2) + (y >> 2) * a.M) << 6) + ((y & 3) << 2) + (x & 3)) * vb
+                     : (uint32_t)((y * Sx + x) * vb);
+              uint32_t hz = (uint32_t)h0;
+              int zp = o[2] & 3;
+              for (int t = 0; t < nz; ++t) {
 #pragma unroll
                 for (int ch = 0; ch < CH; ++ch)
                   __builtin_amdgcn_global_load_lds(
-                      reinterpret_cast<const uint8_t*>(slot[ch]) + e,
-                      reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
+                      reinterpret_cast<const uint8_t*>(slot[ch]) + hz + c,
+                      reinterpret_cast<uint8_t*>(stage + ch * cap) + (t * Q + s0) * cb, cb, 0, 0);
+                hz += (uint32_t)(MB ? (zp == 3 ? zjump : zin) : zs);
+                zp = (zp + 1) & 3;
               }
-              y += dy;
-              const bool c = y >= yend;
-              y = c ? y - wy : y;
-              z += dz + (c ? 1 : 0);
-            }
-          } else {
-            for (int r0 = 0; r0 < rows; r0 += R) {
-              if (r0 < lim) {
-#pragma unroll
-                for (int ch = 0; ch < CH; ++ch)
-                  __builtin_amdgcn_global_load_lds(
-                      reinterpret_cast<const uint8_t*>(slot[ch]) + (uint32_t)gb,
-                      reinterpret_cast<uint8_t*>(stage + ch * cap) + r0 * cpr * cb, cb, 0, 0);
-              }
-              yy += dy;
-              const bool c = yy >= wy;
-              yy -= c ? wy : 0;
-              gb += c ? step_c : step;
             }
           }
         } else {
