@@ -1403,16 +1403,36 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
               const uint32_t c =
                   MB ? (uint32_t)((((x >> 2) + (y >> 2) * a.M) << 6) + ((y & 3) << 2) + (x & 3)) * vb
                      : (uint32_t)((y * Sx + x) * vb);
+              // the plane part's steps after planes o[2] + 4u + j: a block
+              // plane after every fourth plane of a micro-block slot
+              uint32_t st[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                st[j] = (uint32_t)(MB ? (((o[2] + j) & 3) == 3 ? zjump : zin) : zs);
               uint32_t hz = (uint32_t)h0;
-              int zp = o[2] & 3;
-              for (int t = 0; t < nz; ++t) {
+              auto load_plane = [&](int t) {
 #pragma unroll
                 for (int ch = 0; ch < CH; ++ch)
                   __builtin_amdgcn_global_load_lds(
                       reinterpret_cast<const uint8_t*>(slot[ch]) + hz + c,
                       reinterpret_cast<uint8_t*>(stage + ch * cap) + (t * Q + s0) * cb, cb, 0, 0);
-                hz += (uint32_t)(MB ? (zp == 3 ? zjump : zin) : zs);
-                zp = (zp + 1) & 3;
+              };
+              int t = 0;
+              for (; t + 4 <= nz; t += 4) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  load_plane(t + j);
+                  hz += st[j];
+                }
+              }
+              if (t < nz) {  // the last nz % 4 planes
+                load_plane(t);
+                hz += st[0];
+                if (t + 1 < nz) {
+                  load_plane(t + 1);
+                  hz += st[1];
+                  if (t + 2 < nz) load_plane(t + 2);
+                }
               }
             }
           }
