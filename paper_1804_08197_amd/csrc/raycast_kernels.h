@@ -1381,7 +1381,38 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
         const float inv_cpr = __builtin_amdgcn_rcpf((float)cpr),
                     inv_wy = __builtin_amdgcn_rcpf((float)wy);
         constexpr int cb = kRowAlignBytes;
-        if (cpr <= 64) {
+        if (cpr * wy <= 32) {
+          // planes of at most 32 chunks: a pass moves k = 64 / Q whole
+          // planes, lane pz * Q + i taking chunk i of plane pz of the pass
+          // (row i / cpr, column i % cpr; lanes past k * Q rest). A lane's
+          // offset in the slot is the part from its (x, y), kept, plus the
+          // part from its plane, formed at each pass
+          constexpr int vb = (int)sizeof(T), zin = 16 * vb;
+          const int Q = cpr * wy;
+          const float inv_q = __builtin_amdgcn_rcpf((float)Q);
+          const int k = uniform((int)(64.5f * inv_q));
+          const int zs = MB ? 64 * a.M * a.M * vb : S * Sx * vb, nz = wd[2];
+          const int pz = (int)(((float)lane + 0.5f) * inv_q), i = lane - pz * Q;
+          if (pz < k) {
+            const int ry = (int)(((float)i + 0.5f) * inv_cpr);
+            const int x = o[0] + (i - ry * cpr) * align, y = o[1] + ry;
+            const uint32_t c =
+                MB ? (uint32_t)((((x >> 2) + (y >> 2) * a.M) << 6) + ((y & 3) << 2) + (x & 3)) * vb
+                   : (uint32_t)((y * Sx + x) * vb);
+            for (int t = 0; t < nz; t += k) {
+              if (t + pz < nz) {
+                const int z = o[2] + t + pz;
+                const uint32_t hz =
+                    MB ? (uint32_t)(__umul24(z >> 2, zs) + (z & 3) * zin) : (uint32_t)__umul24(z, zs);
+#pragma unroll
+                for (int ch = 0; ch < CH; ++ch)
+                  __builtin_amdgcn_global_load_lds(
+                      reinterpret_cast<const uint8_t*>(slot[ch]) + hz + c,
+                      reinterpret_cast<uint8_t*>(stage + ch * cap) + t * Q * cb, cb, 0, 0);
+              }
+            }
+          }
+        } else if (cpr <= 64) {
           // a lane keeps chunk i = s0 + lane of a region plane (row i / cpr,
           // column i % cpr) and a sub-pass walks the planes. A chunk's
           // offset in the slot is the sum of a part from its (x, y) and a
