@@ -1508,11 +1508,14 @@ __device__ __forceinline__ void staged_tile(const RenderArgs& a, const float4* s
           const int syb = sy_l * (int)sizeof(T), szb = sy_l * wy * (int)sizeof(T);
           auto fetch = [&](int ch, int ix, int iy, int iz, float fx, float fy, float fz) {
             // stencil corner: x step, then the row and plane steps as 24-bit
-            // multiply-adds (every term below 2^23)
-            const char* p = sb + ch * cap * (int)sizeof(T) + ix * (int)sizeof(T);
-            p += __mul24(iy, syb);
-            p += __mul24(iz, szb);
-            return trilinear_bytes<T>(p, syb, szb, fx, fy, fz);
+            // multiply-adds (every term below 2^23; written out, since the
+            // compiler would form two products and a three-way add)
+            typedef __attribute__((address_space(3))) const char* LdsP;
+            uint32_t q = (uint32_t)(uintptr_t)(LdsP)(sb + ch * cap * (int)sizeof(T)) +
+                         (uint32_t)(ix * (int)sizeof(T));
+            asm("v_mad_u32_u24 %0, %1, %2, %0" : "+v"(q) : "v"(iy), "s"(syb));
+            asm("v_mad_u32_u24 %0, %1, %2, %0" : "+v"(q) : "v"(iz), "s"(szb));
+            return trilinear_bytes<T>((const char*)(LdsP)(uintptr_t)q, syb, szb, fx, fy, fz);
           };
           if (depth_on)
             sample_run<MODEL, CH, STATS, false, true>(r, a, s_tf, fetch, kb, mb_key);
