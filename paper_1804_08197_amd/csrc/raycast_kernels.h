@@ -622,6 +622,9 @@ __device__ __forceinline__ bool sample_step(Ray& r, const RenderArgs& a, const f
   if (MODEL != kModelEmission && MODEL != kModelMip) {
     const Shade z = shade_ea<CH, STATS, CLAMP>(r, a, s_tf, w, fetch, tau, mb_key);
     r.k = k + 1;
+    // (the loop tests the new index: comparing the old one instead keeps
+    // both alive and costs a register copy per sample)
+    asm("" : "+v"(r.k));
     r.tau += r.Df;
     if (STATS) ++r.nsamp;
     return composite_ea<DEPTH>(r, a, z, s * kNegLog2e, tau);
