@@ -75,6 +75,8 @@ def lib():
         L.sgo_node_id.argtypes = [C.c_int32] * 4
         L.sgo_node_id.restype = C.c_uint64
         L.sgo_node_box.argtypes = [i3, C.c_int32, C.c_int32, i3, d3, d3]
+        L.sgo_box_outside_view.argtypes = [C.POINTER(View), d3, d3]
+        L.sgo_box_outside_view.restype = C.c_int32
         L.sgo_downsample.argtypes = [vp, C.c_int32, i3, vp]
         L.sgo_brick_region.argtypes = [vp, C.c_int32, i3, C.c_int32, i3, vp]
         L.sgo_brick_minmax.argtypes = [vp, C.c_int32, i3, C.c_int32, i3, d3, d3]
@@ -210,6 +212,12 @@ def node_box(dims0, B, L, b):
     lo, hi = (C.c_double * 3)(), (C.c_double * 3)()
     lib().sgo_node_box(_i3(dims0), int(B), int(L), _i3(b), lo, hi)
     return np.array(lo[:]), np.array(hi[:])
+
+
+def box_outside_view(view: dict, lo, hi) -> bool:
+    """Does box [lo, hi] lie outside every ray of the view (Sec 5.2)?"""
+    v = make_view(view)
+    return bool(lib().sgo_box_outside_view(C.byref(v), _d3(lo), _d3(hi)))
 
 
 def downsample(vol: np.ndarray) -> np.ndarray:

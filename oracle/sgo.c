@@ -151,6 +151,34 @@ void sgo_node_box(const int32_t dims0[3], int32_t B, int32_t L,
   }
 }
 
+/* O18 (Sec 5.2: blocks no ray can see are left out): does box [lo, hi]
+ * lie outside every ray of the view? The rays leave the eye inside the
+ * pyramid spanned by the image's edge tangents (every pixel centre lies
+ * half a pixel inside it), so a box whose eight corners all lie beyond one
+ * of the four side planes meets none of them. In the camera frame (x
+ * right, y up, looking down -z) a corner q lies beyond the right plane when
+ * x > tan_right z, with z = -q.z the distance along the view axis. A view
+ * with a lens map is never culled: its rays leave the pyramid. */
+int32_t sgo_box_outside_view(const sgo_view *v, const double lo[3],
+                             const double hi[3]) {
+  if (v->lens[0] != 0.0 || v->lens[1] != 0.0) return 0;
+  const double *m = v->cam_to_world;
+  int nr = 0, nl = 0, nt = 0, nb = 0;
+  for (int k = 0; k < 8; ++k) {
+    double q0 = ((k & 1) ? hi[0] : lo[0]) - m[3];
+    double q1 = ((k & 2) ? hi[1] : lo[1]) - m[7];
+    double q2 = ((k & 4) ? hi[2] : lo[2]) - m[11];
+    double x = (q0 * m[0] + q1 * m[4]) + q2 * m[8];
+    double y = (q0 * m[1] + q1 * m[5]) + q2 * m[9];
+    double z = -((q0 * m[2] + q1 * m[6]) + q2 * m[10]);
+    nr += x > v->tan_right * z;
+    nl += x < v->tan_left * z;
+    nt += y > v->tan_top * z;
+    nb += y < v->tan_bottom * z;
+  }
+  return nr == 8 || nl == 8 || nt == 8 || nb == 8;
+}
+
 /* ------------------------------------------------------------- O2 pyramid */
 
 /* Next pyramid level (Sec 5.2, multi-resolution pyramid): each coarse voxel
@@ -501,13 +529,15 @@ int64_t sgo_lod_cut(const int32_t dims0[3], int32_t B, int32_t levels,
  * traversal above with one change: a node that is too coarse for the view
  * descends only if all of its existing children are resident; otherwise the
  * node itself is drawn, one level coarser than wanted, and the children that
- * are absent are recorded as requests for the loader.
+ * are absent are recorded as requests for the loader, except those no ray
+ * of the view can see (sgo_box_outside_view).
  * `resident` is the ascending list of resident node identifiers; every
  * top-level node must be in it (returns -2 otherwise). The requested
  * identifiers (ascending, without repeats) go to req (first req_cap),
  * their number to *n_req. Returns the cut size as sgo_lod_cut does. */
 typedef struct {
   cut_ctx c;
+  const sgo_view *v;
   const uint64_t *res;
   int64_t n_res;
   uint64_t *req;
@@ -543,6 +573,9 @@ static void res_visit(res_ctx *r, int32_t L, const int32_t b[3]) {
     for (int k = 0; k < nk; ++k) {
       uint64_t id = sgo_node_id(L - 1, kids[k][0], kids[k][1], kids[k][2]);
       if (is_resident(r, id)) continue;
+      double lo[3], hi[3];
+      sgo_node_box(c->dims0, c->B, L - 1, kids[k], lo, hi);
+      if (sgo_box_outside_view(r->v, lo, hi)) continue;
       if (r->n_req < r->req_cap) r->req[r->n_req] = id;
       r->n_req++;
     }
@@ -571,6 +604,7 @@ int64_t sgo_lod_cut_resident(const int32_t dims0[3], int32_t B, int32_t levels,
   c->out = out;
   c->n = 0;
   c->cap = cap;
+  r.v = v;
   r.res = resident;
   r.n_res = n_resident;
   r.req = req;

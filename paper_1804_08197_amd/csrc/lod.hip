@@ -60,9 +60,45 @@ __device__ __forceinline__ int64_t node_index(const CutGeom& g, int L, int bx, i
   return g.node_off[L] + ((int64_t)bz * g.grid[L][1] + by) * g.grid[L][0] + bx;
 }
 
+// Does node (L, b)'s box lie outside every ray of view V (Sec 5.2: blocks
+// no ray can see are left out)? The rays leave the eye inside the pyramid
+// of the image's edge tangents, so a box whose eight corners all lie beyond
+// one of its four side planes meets none of them; in the camera frame a
+// corner lies beyond the right plane when x > tan_right z, z the distance
+// along the view axis. Views with a lens map are never culled (their rays
+// leave the pyramid). FP64, the box [B 2^L b, B 2^L (b+1)] clipped to the
+// volume.
+__device__ bool node_outside_view(const CutGeom& g, const ViewDev& V, int L, int bx, int by,
+                                  int bz) {
+  if (V.lens_on) return false;
+  const int b[3] = {bx, by, bz};
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    const int64_t w = (int64_t)g.B << L;
+    const int64_t h = w * (b[a] + 1);
+    lo[a] = (double)(w * b[a]);
+    hi[a] = (double)(h > g.dims[a] ? (int64_t)g.dims[a] : h);
+  }
+  int nr = 0, nl = 0, nt = 0, nb = 0;
+  for (int k = 0; k < 8; ++k) {
+    const double q0 = ((k & 1) ? hi[0] : lo[0]) - V.e[0];
+    const double q1 = ((k & 2) ? hi[1] : lo[1]) - V.e[1];
+    const double q2 = ((k & 4) ? hi[2] : lo[2]) - V.e[2];
+    const double x = (q0 * V.R[0] + q1 * V.R[3]) + q2 * V.R[6];
+    const double y = (q0 * V.R[1] + q1 * V.R[4]) + q2 * V.R[7];
+    const double z = -((q0 * V.R[2] + q1 * V.R[5]) + q2 * V.R[8]);
+    nr += x > V.tr * z;
+    nl += x < V.tl * z;
+    nt += y > V.tt * z;
+    nb += y < V.tb * z;
+  }
+  return nr == 8 || nl == 8 || nt == 8 || nb == 8;
+}
+
 // Cache volumes: are all existing children of (L, b) resident? Requests the
-// missing ones.
-__device__ bool children_resident(const CutGeom& g, int L, int bx, int by, int bz) {
+// missing ones that a ray of view V can see.
+__device__ bool children_resident(const CutGeom& g, const ViewDev& V, int L, int bx, int by,
+                                  int bz) {
   bool all = true;
   for (int k = 0; k < 8; ++k) {
     const int cx = 2 * bx + (k & 1), cy = 2 * by + ((k >> 1) & 1), cz = 2 * bz + (k >> 2);
@@ -70,6 +106,7 @@ __device__ bool children_resident(const CutGeom& g, int L, int bx, int by, int b
     const int64_t child = node_index(g, L - 1, cx, cy, cz);
     if (node_resident(g, child)) continue;
     all = false;
+    if (node_outside_view(g, V, L - 1, cx, cy, cz)) continue;
     const int64_t e = g.req_base + child;
     const uint32_t bit = 1u << (e & 31);
     if ((atomicOr(g.req_flags + (e >> 5), bit) & bit) == 0u) {
@@ -125,7 +162,7 @@ __global__ void cutmap_kernel(CutGeom g, ViewDev* views, int32_t* cutmap, Inline
     int L = (g.lod || g.cache) ? g.top : g.bias;
     for (; L > g.bias; --L) {
       if (g.lod && node_suits(g, e, K, L, cx >> L, cy >> L, cz >> L)) break;
-      if (g.cache && !children_resident(g, L, cx >> L, cy >> L, cz >> L)) break;
+      if (g.cache && !children_resident(g, V, L, cx >> L, cy >> L, cz >> L)) break;
     }
     const int64_t node = node_index(g, L, cx >> L, cy >> L, cz >> L);
     out[cell] = (int32_t)node;

@@ -42,7 +42,7 @@ def brute(dims0, B, levels, view, resident, tau, bias, lod):
     """The definition, node by node: n is in the cut iff every ancestor a
     does not suit and has all its children resident, and n itself suits or
     has a missing child. Requests: the missing children of cut nodes that do
-    not suit."""
+    not suit, save those outside every ray of the view."""
     e = np.asarray(view["cam_to_world"], dtype=np.float64).reshape(4, 4)[:3, 3]
     K = O.lod_k(view, tau)
     res = set(int(r) for r in resident)
@@ -71,7 +71,9 @@ def brute(dims0, B, levels, view, resident, tau, bias, lod):
             continue
         cut.append(ident(n))
         if not suits(n):
-            req += [ident(c) for c in children(dims0, B, n) if ident(c) not in res]
+            req += [ident(c) for c in children(dims0, B, n)
+                    if ident(c) not in res
+                    and not O.box_outside_view(view, *O.node_box(dims0, B, c[0], c[1:]))]
     return np.array(sorted(cut), np.uint64), np.array(sorted(req), np.uint64)
 
 
@@ -141,6 +143,39 @@ def test_nothing_below_the_top_gives_the_top_level_and_requests_its_children():
     for L, x, y, z in O.node_decode(full):
         if L < 2:
             a = (1, x >> (1 - L), y >> (1 - L), z >> (1 - L))
-            wanted_children.add(ident(a))
+            if not O.box_outside_view(v, *O.node_box(dims0, B, 1, a[1:])):
+                wanted_children.add(ident(a))
+    assert len(wanted_children) > 0
     assert set(req.tolist()) >= wanted_children
     assert all(int(r) >> 60 == 1 for r in req)
+
+
+def test_culling_keeps_every_box_a_pixel_ray_enters():
+    """Sec 5.2 leaves out blocks no ray sees. Pinned against the rays
+    themselves: every node box that the ray of some pixel enters (at a
+    positive parameter) is kept, and boxes behind the eye or beside the
+    image are culled."""
+    rng = np.random.default_rng(83)
+    dims0, B, levels = (48, 40, 32), 4, 3
+    boxes = [(n, O.node_box(dims0, B, n[0], n[1:])) for n in all_nodes(dims0, B, levels)]
+    culled_any = 0
+    for v in tiny_views(rng, dims0, 12):
+        hit = set()
+        for py in range(v["height"]):
+            for px in range(v["width"]):
+                e, d = O.ray(v, px, py)
+                for n, (lo, hi) in boxes:
+                    ok, t0, t1 = O.box_interval(e, d, lo, hi)
+                    if ok and t1 > 0.0:
+                        hit.add(n)
+        for n, (lo, hi) in boxes:
+            out = O.box_outside_view(v, lo, hi)
+            assert not (out and n in hit), (n, v["cam_to_world"])
+            culled_any += out
+    assert culled_any > 0
+    # a box behind the eye is culled; a lens view culls nothing
+    v = gen.view(gen.look_at((0, 0, 0), (0, 0, -10)), 9, 7, 0.5)
+    assert O.box_outside_view(v, (-1, -1, 5), (1, 1, 6))
+    assert not O.box_outside_view(v, (-1, -1, -6), (1, 1, -5))
+    lens = dict(v, lens=[0.2, 0.1, 0.0, 0.0])
+    assert not O.box_outside_view(lens, (-1, -1, 5), (1, 1, 6))
